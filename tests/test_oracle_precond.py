@@ -1,0 +1,169 @@
+"""Pins of the oracle's factorized preconditioners (FSAI and the learned factor)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import precond as PC
+from oracle import trplk as O
+from workloads import make, start_block, lap3d, fem3d, powerlaw
+
+
+def _fsai_defining(A, G, cap=None):
+    A = sp.csr_matrix(A)
+    GA = (G @ A).tocsr()
+    pats = PC.fsai_pattern(A, cap)
+    worst_off, worst_diag = 0.0, 0.0
+    GAGt = (G @ A @ G.T).diagonal()
+    for i, P in enumerate(pats):
+        row = GA[i].toarray().ravel()
+        worst_off = max(worst_off, np.max(np.abs(row[P[:-1]])) if P.shape[0] > 1 else 0.0)
+    worst_diag = np.max(np.abs(GAGt - 1.0))
+    return worst_off, worst_diag
+
+
+@pytest.mark.parametrize("which", ["lap3d", "fem3d", "powerlaw"])
+def test_fsai_defining_equations(which):
+    """(G A)_{ij} = 0 on the pattern off the diagonal and (G A G^T)_{ii} = 1."""
+    if which == "lap3d":
+        A = lap3d(8, 0.05).to_scipy()
+        cap = None
+    elif which == "fem3d":
+        A = fem3d(7, 0.5)[0].to_scipy()
+        cap = None
+    else:
+        A = powerlaw(800).to_scipy()
+        cap = 8
+    G = PC.fsai(A, cap)
+    off, dg = _fsai_defining(A, G, cap)
+    scale = np.max(np.abs(A.data))
+    assert off < 1e-12 * scale * np.max(np.abs(G.data))
+    assert dg < 1e-12
+    # lower triangular with a positive diagonal
+    assert sp.triu(G, 1).nnz == 0 and np.all(G.diagonal() > 0)
+
+
+def test_fsai_full_pattern_is_inverse_cholesky():
+    """With the full lower pattern FSAI is the exact inverse Cholesky factor:
+    G^T G = A^{-1} (textbook special case)."""
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((30, 30))
+    A = R @ R.T + 30 * np.eye(30)
+    G = PC.fsai(sp.csr_matrix(A))
+    assert np.max(np.abs((G.T @ G).toarray() - np.linalg.inv(A))) < 1e-13
+    # and for a diagonal matrix it is D^{-1/2}
+    D = sp.diags(rng.uniform(1, 3, 10)).tocsr()
+    assert np.allclose(PC.fsai(D).diagonal(), 1 / np.sqrt(D.diagonal()), rtol=1e-15)
+
+
+def test_fsai_solve_small_dense():
+    """A full solve with the FSAI preconditioner reaches the dense eigenvalues
+    and needs fewer products than Jacobi on the FEM stiffness."""
+    P = make("fem3d", "small", Ne=9, sigma=0.5, p=6, m=20, k=10)
+    A, B = P.A.to_scipy(), P.B.to_scipy()
+    X0 = start_block(A.shape[0], 10, 12)
+    rj = O.solve(A, B, 6, 20, 10, 1, 1e-8, X0, apply_M=O.jacobi(A))
+    rf = O.solve(A, B, 6, 20, 10, 1, 1e-8, X0, apply_M=O.factorized(PC.fsai(A)))
+    import scipy.linalg as sl
+    ev = sl.eigh(A.toarray(), B.toarray(), eigvals_only=True)[:6]
+    assert np.all(np.abs(rf.theta - ev) <= 1e-10 * ev)
+    assert rf.matvecs < rj.matvecs
+
+
+def test_row_features_by_hand():
+    A = sp.csr_matrix(np.array([[4.0, -1.0, 0.0, -2.0],
+                                [-1.0, 3.0, 0.0, 0.0],
+                                [0.0, 0.0, 5.0, 0.0],
+                                [-2.0, 0.0, 0.0, 6.0]]))
+    raw = np.array([
+        [2, 4, 3, 1.5, 1, 2, 0.5, 4 / 3],
+        [1, 3, 1, 1, 1, 1, 0, 3],
+        [0, 5, 0, 0, 0, 0, 0, 0],
+        [1, 6, 2, 2, 2, 2, 0, 3],
+    ], dtype=float)
+    z = (raw - raw.mean(0)) / raw.std(0)
+    assert np.allclose(PC.row_features(A), z, atol=1e-14)
+
+
+def test_learned_zero_output_is_jacobi():
+    """A zero output layer gives G = D^{-1/2}, hence M = D^{-1}: the solve is
+    the Jacobi solve."""
+    P = make("powerlaw", "small", n=1200, p=4, m=16, k=8)
+    A = P.A.to_scipy()
+    params = PC.init_params(seed=1, zero_last=True)
+    o, _ = PC.mlp_forward(params, PC.mlp_inputs(A))
+    G = PC.assemble_G(A, o)
+    D = A.diagonal()
+    assert np.allclose((G.T @ G).toarray(), np.diag(1 / D), rtol=1e-15, atol=0)
+    X0 = start_block(A.shape[0], 8, 12)
+    rj = O.solve(A, None, 4, 16, 8, 1, 1e-8, X0, apply_M=O.jacobi(A))
+    rl = O.solve(A, None, 4, 16, 8, 1, 1e-8, X0, apply_M=O.factorized(G))
+    assert rl.cycles == rj.cycles
+    assert np.allclose(rl.theta, rj.theta, rtol=1e-12)
+
+
+def _pairs(A, S, seed=3):
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal((A.shape[0], S))
+    return A @ E, E
+
+
+def test_loss_gradient_G_finite_differences():
+    A = powerlaw(200).to_scipy()
+    params = PC.init_params(seed=2, zero_last=False)
+    o, _ = PC.mlp_forward(params, PC.mlp_inputs(A))
+    G = PC.assemble_G(A, o)
+    R, E = _pairs(A, 3)
+    L0, grad = PC.loss_and_grad_G(G, R, E)
+    rng = np.random.default_rng(0)
+    for idx in rng.choice(G.nnz, 12, replace=False):
+        h = 1e-6 * max(1.0, abs(G.data[idx]))
+        Gp, Gm = G.copy(), G.copy()
+        Gp.data[idx] += h
+        Gm.data[idx] -= h
+        fd = (PC.loss_and_grad_G(Gp, R, E)[0] - PC.loss_and_grad_G(Gm, R, E)[0]) / (2 * h)
+        assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_loss_gradient_params_finite_differences():
+    A = powerlaw(150).to_scipy()
+    params = PC.init_params(seed=4, zero_last=False)
+    params["w2"] *= 0.1
+    R, E = _pairs(A, 2)
+    x = PC.mlp_inputs(A)
+    L0, g, _ = PC.loss_and_grad_params(params, A, R, E, x)
+    rng = np.random.default_rng(1)
+    checks = [("b2", ())] + [("w2", (int(i),)) for i in rng.choice(PC.NHID, 4, replace=False)]
+    checks += [("b1", (int(i),)) for i in rng.choice(PC.NHID, 3, replace=False)]
+    checks += [("W1", (int(i), int(j))) for i, j in zip(rng.choice(PC.NHID, 4), rng.choice(PC.NIN, 4))]
+    for key, ix in checks:
+        h = 1e-6
+        pp = {kk: np.array(v, copy=True) for kk, v in params.items()}
+        pm = {kk: np.array(v, copy=True) for kk, v in params.items()}
+        pp[key][ix] += h
+        pm[key][ix] -= h
+        fd = (PC.loss_and_grad_params(pp, A, R, E, x)[0]
+              - PC.loss_and_grad_params(pm, A, R, E, x)[0]) / (2 * h)
+        an = float(np.asarray(g[key])[ix])
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (key, ix, fd, an)
+
+
+def test_adam_training_lowers_loss():
+    """A few Adam steps on solver-generated pairs lower the loss below the
+    Jacobi starting point."""
+    P = make("powerlaw", "small", n=1000, p=4, m=16, k=8)
+    A = P.A.to_scipy()
+    r = O.solve(A, None, 4, 16, 8, 1, 1e-6, start_block(A.shape[0], 8, 12),
+                apply_M=O.jacobi(A), max_cycles=3)
+    E = r.X
+    R = A @ E
+    params = PC.init_params(seed=0, zero_last=True)
+    x = PC.mlp_inputs(A)
+    L0, g, _ = PC.loss_and_grad_params(params, A, R, E, x)
+    st = {}
+    for _ in range(30):
+        L, g, _ = PC.loss_and_grad_params(params, A, R, E, x)
+        PC.adam_step(params, g, st, lr=1e-3)
+    L1 = PC.loss_and_grad_params(params, A, R, E, x)[0]
+    assert L1 < 0.97 * L0
