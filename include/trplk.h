@@ -1,0 +1,210 @@
+/*
+ * trplk.h -- C ABI of an MI355X (gfx950) implementation of TRPL+K, the
+ * thick-restart preconditioned Lanczos method with locally optimal (+K)
+ * restarting of Wu, Xue and Stathopoulos (arXiv 1711.10128).
+ *
+ * The library computes the p algebraically smallest eigenpairs of the pencil
+ * A v = lambda B v with A symmetric and B symmetric positive definite
+ * (paper, Sec. 1, eq. (1.1)); B = NULL means the standard problem B = I.
+ * Eigenvectors are B-orthonormal.  Every step of the iteration runs in HIP
+ * kernels on one GPU; the host only sequences launches and reads O(m)
+ * scalars once per restart cycle.
+ *
+ * Conventions for every entry point:
+ *  - return value: 0 = TRPLK_OK, > 0 = completed with a warning, < 0 = error;
+ *    no C++ exception crosses the ABI.  After an error on a context,
+ *    trplk_last_error() describes it.
+ *  - matrices are square CSR, 0-based, int32 row pointers and column
+ *    indices, columns sorted ascending within a row, no duplicates,
+ *    float64 values, nnz < 2^31.  A must be symmetric (not checked).
+ *  - dense blocks are column-major (Fortran order) with leading dimension n.
+ *  - `mem` tells whether a pointer argument is host memory (TRPLK_MEM_HOST)
+ *    or device memory of the current HIP device (TRPLK_MEM_DEVICE).
+ *  - the caller owns every buffer it passes; the library owns the context
+ *    and everything the context allocates.
+ *  - one context is used by one host thread at a time; calls on one context
+ *    are ordered on the context's stream.
+ */
+#ifndef TRPLK_H
+#define TRPLK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TRPLK_OK 0
+#define TRPLK_ENOCONV 1    /* max_cycles reached: partial results, per-pair flags */
+#define TRPLK_EINVAL (-1)  /* bad sizes, options or CSR structure */
+#define TRPLK_ENOMEM (-2)  /* device allocation failed */
+#define TRPLK_ENOTSPD (-3) /* a B-norm squared <= 0, or a non-positive pivot in setup */
+#define TRPLK_ENUMERIC (-4) /* NaN or Inf in the projected matrix or the Ritz values */
+#define TRPLK_EDEVICE (-5) /* a HIP runtime call failed */
+
+enum { TRPLK_MEM_HOST = 0, TRPLK_MEM_DEVICE = 1 };
+
+/* preconditioner M, applied as z = M r (paper Sec. 2.2: M approximates
+ * (A - rho I)^{-1}; the paper's incomplete factorisations are replaced by
+ * these) */
+enum {
+  TRPLK_PREC_NONE = 0,   /* M = I */
+  TRPLK_PREC_JACOBI = 1, /* M = diag(A)^{-1} */
+  TRPLK_PREC_FSAI = 2,   /* M = G^T G, G the FSAI factor on tril(A), built on the GPU */
+  TRPLK_PREC_FACTOR = 3  /* M = G^T G with G given by trplk_set_factor (learned) */
+};
+/* arithmetic of the operator products */
+enum {
+  TRPLK_FP64 = 0, /* everything in float64 */
+  TRPLK_MIXED = 1 /* float32 preconditioner apply always; float32 SpMV while every
+                     target residual is above the switch threshold, then float64
+                     SpMV; orthogonalisation, projection, Rayleigh-Ritz and the
+                     restart rotation always float64 */
+};
+enum { TRPLK_LOCK_AUTO = 0, TRPLK_LOCK_SOFT = 1, TRPLK_LOCK_HARD = 2 };
+enum { TRPLK_NORM_INF = 0, TRPLK_NORM_FRO = 1 };
+
+typedef struct trplk_csr {
+  int32_t n;              /* rows = columns */
+  int64_t nnz;            /* rowptr[n] */
+  const int32_t* rowptr;  /* n + 1 */
+  const int32_t* col;     /* nnz */
+  const double* val;      /* nnz */
+} trplk_csr;
+
+/* Solver options.  The paper's symbols (Alg. 1): p wanted pairs, maximum
+ * basis size q (here m), previous vectors l; the thick-restart size k >= p
+ * is the paper's minimum restart size p-hat (Sec. 3).  Requirements:
+ * 1 <= p, k + l + 1 <= m <= n, m <= 64; soft locking needs p <= k,
+ * hard locking p + m <= n. */
+typedef struct trplk_opts {
+  int32_t p;          /* wanted eigenpairs */
+  int32_t m;          /* maximum basis size */
+  int32_t k;          /* thick-restart size (Ritz vectors kept) */
+  int32_t l;          /* previous Ritz vectors appended (+K), 0 gives TRLan-like restarts */
+  double tol;         /* stop when ||A x - theta B x||_2 / ||x||_2 <= tol * ||A||  (eq. (5.1)) */
+  int32_t norm;       /* TRPLK_NORM_INF (default) or TRPLK_NORM_FRO (the paper's choice) */
+  int32_t max_cycles; /* default 5000 (Sec. 5) */
+  int32_t precond;    /* TRPLK_PREC_* */
+  int32_t precision;  /* TRPLK_FP64 or TRPLK_MIXED */
+  int32_t locking;    /* TRPLK_LOCK_AUTO: soft when p <= k, else hard */
+  int32_t fsai_cap;   /* FSAI: keep at most this many entries per row (diagonal included), 0 = no cap, max 64 */
+  int32_t profile;    /* 1 = time the SpMV and orthogonalisation kernels with HIP events */
+  double mixed_switch; /* MIXED: switch SpMV to float64 once all target residuals are below
+                          mixed_switch * ||A||; 0 selects the default 1e-5 */
+} trplk_opts;
+
+typedef struct trplk_stats {
+  int32_t cycles;      /* restart cycles run */
+  int32_t nconv;       /* pairs meeting the tolerance at exit */
+  int64_t matvecs;     /* products with A (the paper's MV count) */
+  int64_t bmatvecs;    /* products with B */
+  int64_t precs;       /* preconditioner applications */
+  int32_t fp32_cycles; /* cycles that used the float32 SpMV (MIXED) */
+  int32_t status;      /* TRPLK_OK or TRPLK_ENOCONV */
+  double normA;        /* the ||A|| used in the stopping test */
+  double solve_ms;     /* device time of trplk_solve (HIP events on the context stream) */
+  double setup_ms;     /* device time of trplk_create's preconditioner setup */
+  /* kernel profile (opts.profile = 1): summed device time and launch count */
+  double spmv_ms;      int64_t spmv_launches;     int64_t spmv_bytes;
+  double orth_ms;      int64_t orth_launches;     int64_t orth_bytes;
+  double prec_ms;      int64_t prec_launches;     int64_t prec_bytes;
+  double rot_ms;       int64_t rot_launches;      int64_t rot_bytes;
+  double rr_ms;        int64_t rr_launches;
+} trplk_stats;
+
+typedef struct trplk_ctx trplk_ctx;
+
+/* Fill *o with defaults: p=1 m=18 k=8 l=1 tol=1e-8 norm=INF max_cycles=5000
+ * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0. */
+void trplk_default_opts(trplk_opts* o);
+
+/* Create a solver context for the pencil (A, B) (paper eq. (1.1)).
+ * A, B: CSR in host or device memory per `mem`; host arrays are copied to
+ * the device, device arrays are referenced (they must outlive the context
+ * and stay unchanged).  B == NULL: standard problem.  stream: a hipStream_t,
+ * NULL = the null stream.  Builds the preconditioner (Jacobi diagonal or the
+ * FSAI factor) and ||A|| on the device.  Errors: EINVAL, ENOMEM, ENOTSPD
+ * (FSAI pivot <= 0), EDEVICE; *out is NULL on error. */
+int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B,
+                 const trplk_opts* o, int32_t mem, void* stream);
+
+/* Install M = G^T G with G sparse lower triangular with a positive diagonal
+ * (e.g. the learned factor); switches the context to TRPLK_PREC_FACTOR.
+ * G in host or device memory per `mem`; it is copied.  Errors: EINVAL when G
+ * is not square n x n, not lower triangular, or a diagonal entry is missing. */
+int trplk_set_factor(trplk_ctx* ctx, const trplk_csr* G, int32_t mem);
+
+/* Run TRPL+K (paper Alg. 1 with eq. (3.1) and the +K placement of Sec. 3;
+ * generalized form with B-inner products, Sec. 3 and Alg. 2).
+ * x0: n x k start block, column-major, any full-rank block (it is
+ * B-orthonormalised first); host or device per `mem`; NULL is EINVAL.
+ * st: optional, filled on return.  Returns OK when all p pairs converged,
+ * ENOCONV after max_cycles (results are still available), or an error. */
+int trplk_solve(trplk_ctx* ctx, const double* x0, int32_t mem, trplk_stats* st);
+
+/* Copy the result of the last solve: evals (p, ascending), evecs (n x p,
+ * column-major, B-orthonormal; may be NULL), resid (p; the residual norms
+ * ||A x - theta B x||_2 / ||x||_2 recomputed with fresh float64 products;
+ * may be NULL), conv (p flags; may be NULL).  `mem` applies to every output.
+ * Errors: EINVAL before a successful solve. */
+int trplk_get_eigpairs(trplk_ctx* ctx, double* evals, double* evecs, double* resid,
+                       int32_t* conv, int32_t mem);
+
+/* Bytes of device memory the context holds (matrices, preconditioner and the
+ * solver workspace sized for its options). */
+int64_t trplk_device_bytes(const trplk_ctx* ctx);
+
+/* Human-readable description of the last error on ctx (or of the last
+ * failed trplk_create when ctx is NULL). */
+const char* trplk_last_error(const trplk_ctx* ctx);
+
+void trplk_destroy(trplk_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Kernel-level entry points.  Each runs one building block of the iteration
+ * on device buffers (device pointers, hipStream_t `stream`, NULL = null
+ * stream), so it can be checked and timed in isolation.  They allocate a
+ * small reduction scratch on first use (kept until process exit); calls from
+ * several host threads at once are not supported.
+ * ------------------------------------------------------------------------ */
+
+/* y = A x, CSR SpMV (the paper's matrix-vector product "MV", eq. (3.1)),
+ * float64.  lanes: lanes of a wavefront per row (1,2,4,8,16,32,64), 0 = pick
+ * from the mean row length.  Rows longer than 256 entries go to a
+ * workgroup-per-row kernel. */
+int trplk_spmv(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+               const double* x, double* y, int32_t lanes, void* stream);
+
+/* Same in float32 (values, vector and accumulation): the SpMV of the
+ * mixed-precision form. */
+int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const float* val,
+                   const float* x, float* y, int32_t lanes, void* stream);
+
+/* h = U^T v for U n x c (column-major, leading dimension ldu), c <= 128:
+ * the projection coefficients of the Gram-Schmidt step (Sec. 3). */
+int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v,
+                 double* h, void* stream);
+
+/* w <- w - U h followed by h2 = U^T w (one read of U): the fused second
+ * pass of classical Gram-Schmidt applied twice. */
+int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* h,
+                         double* w, double* h2, void* stream);
+
+/* Symmetric eigendecomposition of a b x b matrix T (column-major, b <= 64),
+ * ascending eigenvalues theta (b) and orthonormal eigenvectors Y (b x b):
+ * the Rayleigh-Ritz step on the projected matrix (Alg. 1).  Device pointers. */
+int trplk_syev(int32_t b, const double* T, double* theta, double* Y, void* stream);
+
+/* In-place basis rotation U(:, 0:k) <- U(:, 0:b) * Y(:, 0:k) for U n x b
+ * (leading dimension ldu), Y b x b column-major (leading dimension ldy),
+ * k <= b <= 64: the thick restart X = U Y (Alg. 1).  Uses FP64 MFMA. */
+int trplk_rotate(int32_t n, int32_t b, int32_t k, double* U, int64_t ldu, const double* Y,
+                 int32_t ldy, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRPLK_H */

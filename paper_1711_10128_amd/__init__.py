@@ -1,0 +1,276 @@
+"""Python binding of libtrplk.so, the MI355X (gfx950) TRPL+K eigensolver.
+
+Argument marshalling only: every step of the iteration runs in the HIP
+library.  PyTorch supplies device memory and the stream.  Importing this
+package does not touch the GPU; the first call that needs the library loads
+it and raises if it has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from ._build import LIB
+
+MEM_HOST, MEM_DEVICE = 0, 1
+PREC = {"none": 0, "jacobi": 1, "fsai": 2, "factor": 3}
+PRECISION = {"fp64": 0, "mixed": 1}
+LOCKING = {"auto": 0, "soft": 1, "hard": 2}
+NORM = {"inf": 0, "fro": 1}
+STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ENUMERIC",
+          -5: "EDEVICE"}
+
+
+class TrplkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("l", ctypes.c_int32), ("tol", ctypes.c_double), ("norm", ctypes.c_int32),
+                ("max_cycles", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("locking", ctypes.c_int32),
+                ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("mixed_switch", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("nconv", ctypes.c_int32),
+                ("matvecs", ctypes.c_int64), ("bmatvecs", ctypes.c_int64),
+                ("precs", ctypes.c_int64), ("fp32_cycles", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("normA", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
+                ("spmv_bytes", ctypes.c_int64),
+                ("orth_ms", ctypes.c_double), ("orth_launches", ctypes.c_int64),
+                ("orth_bytes", ctypes.c_int64),
+                ("prec_ms", ctypes.c_double), ("prec_launches", ctypes.c_int64),
+                ("prec_bytes", ctypes.c_int64),
+                ("rot_ms", ctypes.c_double), ("rot_launches", ctypes.c_int64),
+                ("rot_bytes", ctypes.c_int64),
+                ("rr_ms", ctypes.c_double), ("rr_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_set_factor", "trplk_solve",
+           "trplk_get_eigpairs", "trplk_device_bytes", "trplk_last_error", "trplk_destroy",
+           "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
+           "trplk_rotate"]
+
+
+def lib():
+    """Load libtrplk.so (built by __graft_entry__.build()); raise if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise ImportError(f"{LIB} is not built; run __graft_entry__.build() first "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.trplk_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    L.trplk_default_opts.restype = None
+    L.trplk_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
+                               ctypes.POINTER(_Opts), i32, vp]
+    L.trplk_create.restype = ctypes.c_int
+    L.trplk_set_factor.argtypes = [vp, ctypes.POINTER(_Csr), i32]
+    L.trplk_set_factor.restype = ctypes.c_int
+    L.trplk_solve.argtypes = [vp, vp, i32, ctypes.POINTER(_Stats)]
+    L.trplk_solve.restype = ctypes.c_int
+    L.trplk_get_eigpairs.argtypes = [vp, vp, vp, vp, vp, i32]
+    L.trplk_get_eigpairs.restype = ctypes.c_int
+    L.trplk_device_bytes.argtypes = [vp]
+    L.trplk_device_bytes.restype = i64
+    L.trplk_last_error.argtypes = [vp]
+    L.trplk_last_error.restype = ctypes.c_char_p
+    L.trplk_destroy.argtypes = [vp]
+    L.trplk_destroy.restype = None
+    L.trplk_spmv.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
+    L.trplk_spmv_f32.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
+    L.trplk_gemv_t.argtypes = [i32, i32, vp, i64, vp, vp, vp]
+    L.trplk_cgs_update_dot.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp]
+    L.trplk_syev.argtypes = [i32, vp, vp, vp, vp]
+    L.trplk_rotate.argtypes = [i32, i32, i32, vp, i64, vp, i32, vp]
+    for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot",
+              "trplk_syev", "trplk_rotate"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(code, ctx=None):
+    if code < 0:
+        msg = lib().trplk_last_error(ctx).decode(errors="replace")
+        raise TrplkError(code, msg)
+    return code
+
+
+class DeviceCSR:
+    """A CSR matrix held in torch device tensors (int32 / int32 / float64)."""
+
+    def __init__(self, csr, device="cuda"):
+        import torch
+        self.n = int(csr.n)
+        self.nnz = int(csr.col.shape[0])
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(csr.rowptr, dtype=np.int32)).to(device)
+        self.col = torch.from_numpy(np.ascontiguousarray(csr.col, dtype=np.int32)).to(device)
+        self.val = torch.from_numpy(np.ascontiguousarray(csr.val, dtype=np.float64)).to(device)
+
+    def c(self):
+        return _Csr(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
+
+
+def _host_csr(csr, keep):
+    rp = np.ascontiguousarray(csr.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(csr.col, dtype=np.int32)
+    vl = np.ascontiguousarray(csr.val, dtype=np.float64)
+    keep.extend([rp, cl, vl])
+    return _Csr(int(csr.n), int(cl.shape[0]), rp.ctypes.data, cl.ctypes.data, vl.ctypes.data)
+
+
+class Solver:
+    """One TRPL+K context on the current HIP device.
+
+    A, B   CSR matrices: objects with n/rowptr/col/val numpy arrays (copied
+           to the device by the library) or DeviceCSR (referenced)
+    """
+
+    def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
+                 precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
+                 profile=False, mixed_switch=0.0):
+        L = lib()
+        o = _Opts()
+        L.trplk_default_opts(ctypes.byref(o))
+        o.p, o.m, o.k, o.l, o.tol = p, m, k, l, tol
+        o.norm, o.max_cycles = NORM[norm], max_cycles
+        o.precond, o.precision, o.locking = PREC[precond], PRECISION[precision], LOCKING[locking]
+        o.fsai_cap, o.profile, o.mixed_switch = fsai_cap, int(bool(profile)), mixed_switch
+        self.opts = o
+        self.n = int(A.n)
+        self.p = p
+        self.k = k
+        keep = []
+        dev = isinstance(A, DeviceCSR)
+        if dev:
+            ca, cb = A.c(), (B.c() if B is not None else None)
+        else:
+            ca = _host_csr(A, keep)
+            cb = _host_csr(B, keep) if B is not None else None
+        self._refs = (A, B)
+        ctx = ctypes.c_void_p()
+        code = L.trplk_create(ctypes.byref(ctx), ctypes.byref(ca),
+                              ctypes.byref(cb) if cb is not None else None, ctypes.byref(o),
+                              MEM_DEVICE if dev else MEM_HOST, _stream())
+        _check(code, None)
+        self.ctx = ctx
+        self.stats = None
+
+    def set_factor(self, G):
+        """Install M = G^T G for a lower-triangular CSR G (numpy arrays)."""
+        keep = []
+        cg = _host_csr(G, keep)
+        _check(lib().trplk_set_factor(self.ctx, ctypes.byref(cg), MEM_HOST), self.ctx)
+
+    def solve(self, X0):
+        """Run the solver from the start block X0 (n x k): numpy (column-major
+        is produced here) or a torch device tensor laid out column-major
+        (i.e. X0.T contiguous)."""
+        import torch
+        st = _Stats()
+        if isinstance(X0, torch.Tensor):
+            assert X0.is_cuda and X0.dtype == torch.float64
+            code = lib().trplk_solve(self.ctx, _ptr(X0), MEM_DEVICE, ctypes.byref(st))
+        else:
+            X = np.asfortranarray(X0, dtype=np.float64)
+            assert X.shape == (self.n, self.k)
+            code = lib().trplk_solve(self.ctx, X.ctypes.data_as(ctypes.c_void_p), MEM_HOST,
+                                     ctypes.byref(st))
+        _check(code, self.ctx)
+        self.stats = st.as_dict()
+        return self.stats
+
+    def eigpairs(self, vectors=True, residuals=True):
+        p, n = self.p, self.n
+        ev = np.empty(p)
+        X = np.empty((p, n)) if vectors else None
+        rs = np.empty(p) if residuals else None
+        cv = np.empty(p, dtype=np.int32)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None  # noqa: E731
+        _check(lib().trplk_get_eigpairs(self.ctx, vp(ev), vp(X), vp(rs), vp(cv), MEM_HOST), self.ctx)
+        return ev, (X.T if X is not None else None), rs, cv.astype(bool)
+
+    def device_bytes(self):
+        return int(lib().trplk_device_bytes(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().trplk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# kernel-level wrappers (torch device tensors in, results in place)
+# ---------------------------------------------------------------------------
+
+def spmv(rowptr, col, val, x, y, lanes=0):
+    import torch
+    f = lib().trplk_spmv if val.dtype == torch.float64 else lib().trplk_spmv_f32
+    _check(f(int(rowptr.shape[0] - 1), _ptr(rowptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
+             lanes, _stream()))
+    return y
+
+
+def gemv_t(U, v, h):
+    """h = U^T v for U given as a (c, n) contiguous tensor (column-major n x c)."""
+    c, n = U.shape
+    _check(lib().trplk_gemv_t(n, c, _ptr(U), n, _ptr(v), _ptr(h), _stream()))
+    return h
+
+
+def cgs_update_dot(U, h, w, h2):
+    c, n = U.shape
+    _check(lib().trplk_cgs_update_dot(n, c, _ptr(U), n, _ptr(h), _ptr(w), _ptr(h2), _stream()))
+    return w, h2
+
+
+def syev(T, theta, Y):
+    """T, Y: (b, b) contiguous tensors holding column-major matrices."""
+    b = T.shape[0]
+    _check(lib().trplk_syev(b, _ptr(T), _ptr(theta), _ptr(Y), _stream()))
+    return theta, Y
+
+
+def rotate(U, Y, k):
+    """U: (b, n) contiguous tensor (column-major n x b), Y: (b, b) column-major."""
+    b, n = U.shape
+    _check(lib().trplk_rotate(n, b, k, _ptr(U), n, _ptr(Y), b, _stream()))
+    return U

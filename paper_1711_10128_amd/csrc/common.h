@@ -1,0 +1,255 @@
+// Shared device helpers and the internal launch interface of the TRPL+K
+// library.  Everything here is gfx950-only HIP C++ (64-wide wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace trplk {
+
+constexpr int WAVE = 64;
+
+// Device-resident scalars of one solver context.  Kernels read the basis
+// size from here so that a breakdown detected on the device stops the
+// remaining launches of a stage without a host round trip.
+struct DevState {
+  int nb;          // columns of the active basis U (after the locked set)
+  int skip;        // nonzero: step kernels of the current stage return at once
+  int bad;         // nonzero: a B-norm squared <= 0 or a non-finite value was seen
+  int nappend;     // vectors appended in the current stage
+  double beta2;    // B-norm squared of the vector being appended
+  double inv_beta; // 1 / sqrt(beta2)
+  double h1norm2;  // squared norm of the first Gram-Schmidt coefficients
+  double rho;      // shift of the inner operator
+  double tol2;     // breakdown tolerance squared of the current stage
+  long long cnt_append;  // vectors appended to the basis (one A product each)
+  long long cnt_norm;    // B-norm evaluations (one B product each when B != I)
+  double pad[1];
+};
+
+// Launch-error helper: records the first failing call.
+struct Status {
+  hipError_t err = hipSuccess;
+  std::string where;
+  bool ok() const { return err == hipSuccess; }
+  void check(hipError_t e, const char* w) {
+    if (e != hipSuccess && err == hipSuccess) {
+      err = e;
+      where = w;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- device --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, L);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float group_sumf(float v) {
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, L);
+  return v;
+}
+
+// ------------------------------------------------------------ launchers --
+// SpMV epilogues
+enum SpmvMode : int {
+  SPMV_STORE = 0,   // y = scale * A x (scale = 1 or state->inv_beta when use_beta)
+  SPMV_APPEND = 1,  // append a basis vector: see SpmvArgs
+  SPMV_DOT = 2,     // y = A x and a per-block partial of sum_i y_i x_i
+  SPMV_RESID = 3    // y = A x - theta[j] * bx, and partial of ||y||^2 (true residual)
+};
+
+enum NextDir : int { NEXT_NONE = 0, NEXT_IDENT = 1, NEXT_JACOBI = 2, NEXT_STORE_V = 3 };
+
+struct SpmvArgs {
+  int n = 0;
+  const int* rowptr = nullptr;
+  const int* col = nullptr;
+  const void* val = nullptr;    // double or float
+  const void* x = nullptr;      // double or float gather vector
+  int mode = SPMV_STORE;
+  bool use_beta = false;        // scale by state->inv_beta
+  bool out_f64 = false;         // float32 kernels: write y as float64
+  DevState* state = nullptr;    // skip flag, inv_beta, rho, nb
+  void* y = nullptr;            // SPMV_STORE/DOT/RESID output (double or float)
+  // SPMV_APPEND: column nb (from state) of U, AU, BU is written with
+  // inv_beta * (x_i, (A x)_i, bx_i); the next inner direction is formed
+  // from v = inv_beta * ((A x)_i - rho * bx_i).
+  const double* xd = nullptr;   // float64 copy of x (own-row reads)
+  const double* bx = nullptr;   // B x (own-row), nullptr when B = I
+  double* U = nullptr;
+  double* AU = nullptr;
+  double* BU = nullptr;
+  int64_t ld = 0;
+  int col0 = 0;                 // column of U where the active basis starts
+  int next = NEXT_NONE;
+  const double* dinv = nullptr; // Jacobi
+  double* wout = nullptr;       // next direction (float64)
+  float* vout32 = nullptr;      // NEXT_STORE_V in float32 (factor preconditioner input)
+  double* vout = nullptr;       // NEXT_STORE_V in float64
+  // SPMV_DOT / SPMV_RESID partials (one double per block)
+  double* partial = nullptr;
+  const double* theta = nullptr;
+  int theta_idx = 0;
+};
+
+struct SpmvPlan {
+  int n = 0;
+  int lanes = 8;
+  int nlong = 0;            // rows with more than LONG_ROW entries
+  int* long_rows = nullptr; // device list of those rows
+  int nblk_short = 0;       // grid of the short-row kernel
+};
+constexpr int LONG_ROW = 256;
+
+int pick_lanes(double mean_len);
+// Builds the plan (row-length binning) for a device CSR; allocates the long
+// row list on the device.
+hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hipStream_t s);
+void spmv_plan_free(SpmvPlan& plan);
+// Number of blocks a SPMV_DOT / SPMV_RESID launch writes partials for.
+int spmv_partial_blocks(const SpmvPlan& plan);
+hipError_t spmv_f64(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s);
+hipError_t spmv_f32(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------- orth passes --
+enum OrthMode : int {
+  ORTH_DOT = 0,      // h_v = M_v^T vec_v for NV vectors (v0 with Md0, v1 with Md1)
+  ORTH_UPD_DOT = 1,  // w <- w - Mu h ; h2 = Md1^T w
+  ORTH_UPD = 2       // wout <- w - Mu h ; optional ||wout||^2 partial; optional f32 copy
+};
+
+struct OrthArgs {
+  int n = 0;
+  const double* Mu = nullptr;   // update matrix (column-major, ld)
+  const double* Md0 = nullptr;  // dot matrix for vec0
+  const double* Md1 = nullptr;  // dot matrix for vec1
+  int64_t ld = 0;
+  int ncol_fixed = 0;           // columns = ncol_fixed + (state ? state->nb : 0) + ncol_extra
+  int ncol_extra = 0;
+  int ncol_max = 0;             // upper bound of the column count (sizes the register tiles)
+  const DevState* state = nullptr;
+  const double* vec0 = nullptr;
+  const double* vec1 = nullptr;
+  // when non-null, vec0 = vec0_base + (vec0_col0 + state->nb) * ld (the
+  // column just appended, located on the device)
+  const double* vec0_base = nullptr;
+  int vec0_col0 = 0;
+  const double* h = nullptr;    // update coefficients (device)
+  double* w = nullptr;          // vector updated in place (ORTH_UPD_DOT) / input (ORTH_UPD)
+  double* wout = nullptr;       // ORTH_UPD output
+  float* wout32 = nullptr;      // ORTH_UPD optional float32 copy
+  bool norm = false;            // ORTH_UPD: partial of ||wout||^2
+  double* partial = nullptr;    // [nblk][stride]
+  int nvec = 1;                 // ORTH_DOT: 1 or 2
+};
+
+constexpr int ORTH_MAXCOL = 128;
+int orth_blocks(int n);
+int orth_stride();  // partial stride per block (doubles)
+hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s);
+
+// ------------------------------------------------------- finish kernels --
+enum FinishMode : int {
+  FIN_TH = 0,    // T column from vec0 dots + h1 from vec1 dots, nb += 1
+  FIN_H = 1,     // h1 from vec0 dots (single vector)
+  FIN_T = 2,     // T column from vec0 dots, nb += 1
+  FIN_H2 = 3,    // h2 (update coefficients of the second pass)
+  FIN_NORM = 4,  // beta^2: breakdown test, inv_beta, skip flag
+  FIN_SUM = 5,   // plain sums into out[0..cnt)
+  FIN_TCOL = 6,  // T column j = cnt from vec0 dots over columns 0..j, no state
+  FIN_RES = 7    // residual report: out[i] = sqrt(r2_i / x2_i), i < cnt (rotation partials)
+};
+
+struct FinishArgs {
+  int mode = FIN_SUM;
+  const double* partial = nullptr;
+  int nblk = 0;
+  int stride = 0;
+  DevState* state = nullptr;
+  int ncol_fixed = 0;   // locked columns in front of U
+  int extra = 0;        // 1 when the dot pass included the just-appended column
+  double* T = nullptr;  // projected matrix, column-major, ldT
+  int ldT = 0;
+  double* h = nullptr;  // coefficient output (device, ORTH_MAXCOL)
+  double* out = nullptr;
+  int cnt = 0;
+  int nvec = 1;
+};
+hipError_t finish(const FinishArgs& f, hipStream_t s);
+
+// ---------------------------------------------------- small kernels -----
+hipError_t set_state(DevState* st, int which, double dv, int iv, hipStream_t s);
+enum SetWhich : int {
+  SET_RHO = 0, SET_TOL2 = 1, SET_NB = 2, SET_SKIP = 3, SET_RESET_STAGE = 4, SET_RHO_FROM = 5
+};
+hipError_t set_rho_from(DevState* st, const double* theta, int idx, hipStream_t s);
+// T <- 0 except T(i,i) = theta[off + i] for i < kact
+hipError_t reset_T(double* T, int ldT, int m, int kact, const double* theta, int off, hipStream_t s);
+
+// r = AX(:,t) - theta_t BX(:,t) followed by the Jacobi / identity scale, or
+// stored for the factor preconditioner (v, float32 or float64).
+hipError_t restart_residual(int n, const double* AXt, const double* BXt, const double* theta,
+                            int t, int next, const double* dinv, double* wout, double* vout,
+                            float* vout32, hipStream_t s);
+
+hipError_t copy_cols(int n, const double* src, int64_t lds, double* dst, int64_t ldd, int ncols,
+                     hipStream_t s);
+hipError_t cast_f32(int64_t n, const double* x, float* y, hipStream_t s);
+hipError_t cast_f64(int64_t n, const float* x, double* y, hipStream_t s);
+
+// Setup kernels
+hipError_t extract_diag_inv(int n, const int* rowptr, const int* col, const double* val,
+                            double* dinv, int* bad, hipStream_t s);
+hipError_t row_norms(int n, const int* rowptr, const double* val, double* partial_inf,
+                     double* partial_fro, int nblk, hipStream_t s);
+int rownorm_blocks(int n);
+
+// ------------------------------------------------------------- FSAI --
+// FSAI factor of A on its (capped) lower pattern; allocates the output CSR.
+// bad_host = 1 when a diagonal entry is missing or a local matrix is not SPD.
+hipError_t fsai_build(int n, const int* rowptr, const int* col, const double* val, int cap,
+                      int** g_rowptr, int** g_col, double** g_val, int64_t* g_nnz, int* bad_host,
+                      hipStream_t s);
+// CSR transpose with sorted columns (deterministic radix sort); allocates.
+hipError_t csr_transpose(int n, int64_t nnz, const int* rowptr, const int* col, const double* val,
+                         int** t_rowptr, int** t_col, double** t_val, hipStream_t s);
+
+// ----------------------------------------------------------- eig / rot --
+constexpr int SYEV_MAXB = 64;
+// Jacobi eigensolver of T (b x b, b from *nb_dev or b_fixed when nb_dev is
+// null), column-major with leading dimension ldT.
+hipError_t syev(const double* T, int ldT, int b_fixed, const int* nb_dev, int nb_offset,
+                double* theta, double* Y, int ldY, hipStream_t s);
+
+struct RotArgs {
+  int n = 0;
+  int kout = 0;                // requested output columns (min with b)
+  int b_fixed = 0;             // basis columns when state is null
+  const DevState* state = nullptr;
+  const double* Y = nullptr;   // ldY
+  int ldY = 0;
+  double* U = nullptr;         // rotated in place
+  double* AU = nullptr;        // optional
+  double* BU = nullptr;        // optional
+  int64_t ld = 0;
+  const double* theta = nullptr;  // residual partials when non-null
+  double* partial = nullptr;      // [nblk][2 * 64]: ||AX_i - th_i BX_i||^2, ||X_i||^2
+};
+int rot_blocks(int n);
+hipError_t rotate(const RotArgs& a, int nblk, hipStream_t s);
+
+}  // namespace trplk

@@ -1,0 +1,478 @@
+// Tall-skinny Gram-Schmidt passes over the basis, the finishing reductions
+// and the small vector kernels of the inner step.
+//
+// The basis U is n x c (c <= 128) column-major.  One workgroup of 8
+// wavefronts walks slabs of 256 rows; wavefront w owns the columns
+// w, w+8, w+16, ... and lane j the rows j, j+64, j+128, j+192 of the slab, so
+// each column load is a contiguous 512-byte run.  Dot products accumulate in
+// registers across all slabs of the workgroup and are reduced once at the
+// end; the update w - U h needs the sum over all columns of a row, which the
+// 8 wavefronts combine through a double-buffered LDS array (one barrier per
+// slab).  The fused pass w <- w - U h, h2 = U^T w reads U once.
+// Reductions are deterministic: fixed per-lane order, fixed shuffle tree,
+// and a fixed-order sum over blocks in the finishing kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace trplk {
+
+namespace {
+
+constexpr int OT_THREADS = 512;
+constexpr int NWV = OT_THREADS / WAVE;  // 8
+constexpr int RPL = 4;                  // rows per lane per slab
+constexpr int SLAB = WAVE * RPL;        // 256 rows
+constexpr int STRIDE = 2 * ORTH_MAXCOL; // partial doubles per block
+
+template <int CPW, int MODE, int NV, bool SAME>
+__global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
+  if (a.state && a.state->skip) return;
+  const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int64_t ld = a.ld;
+  const int n = a.n;
+
+  double hc[CPW];
+  double acc[CPW][NV];
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int c = wv + NWV * i;
+    hc[i] = (MODE != ORTH_DOT && c < ncol) ? a.h[c] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
+  }
+  double nacc = 0.0;
+  __shared__ double red[2][NWV][SLAB];
+  int buf = 0;
+  const int nslab = (n + SLAB - 1) / SLAB;
+
+  const double* vec0 = a.vec0;
+  if (a.vec0_base) vec0 = a.vec0_base + static_cast<int64_t>(a.vec0_col0 + a.state->nb) * ld;
+
+  for (int sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
+    const int base = sl * SLAB + lane;
+    if constexpr (MODE == ORTH_DOT) {
+      double vv[NV][RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = base + WAVE * r;
+        const bool ok = row < n;
+        vv[0][r] = ok ? vec0[row] : 0.0;
+        if constexpr (NV == 2) vv[1][r] = ok ? a.vec1[row] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) {
+        const int c = wv + NWV * i;
+        if (c < ncol) {
+          const double* p0 = a.Md0 + c * ld;
+          const double* p1 = SAME ? p0 : a.Md1 + c * ld;
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int row = base + WAVE * r;
+            const bool ok = row < n;
+            const double u0 = ok ? p0[row] : 0.0;
+            acc[i][0] += u0 * vv[0][r];
+            if constexpr (NV == 2) {
+              const double u1 = SAME ? u0 : (ok ? p1[row] : 0.0);
+              acc[i][NV - 1] += u1 * vv[NV - 1][r];
+            }
+          }
+        }
+      }
+    } else {
+      double u[CPW][RPL];
+      double part[RPL];
+      double win[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = base + WAVE * r;
+        part[r] = 0.0;
+        win[r] = row < n ? a.w[row] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) {
+        const int c = wv + NWV * i;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int row = base + WAVE * r;
+          u[i][r] = (c < ncol && row < n) ? a.Mu[c * ld + row] : 0.0;
+          part[r] += u[i][r] * hc[i];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) red[buf][wv][lane + WAVE * r] = part[r];
+      __syncthreads();
+      double wn[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NWV; ++q) t += red[buf][q][lane + WAVE * r];
+        wn[r] = win[r] - t;
+      }
+      buf ^= 1;
+      if constexpr (MODE == ORTH_UPD_DOT) {
+        if (wv == 0) {
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int row = base + WAVE * r;
+            if (row < n) a.w[row] = wn[r];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+          const int c = wv + NWV * i;
+          if (c < ncol) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              const int row = base + WAVE * r;
+              const double ud = SAME ? u[i][r] : (row < n ? a.Md1[c * ld + row] : 0.0);
+              acc[i][0] += ud * wn[r];
+            }
+          }
+        }
+      } else {
+        if (wv == 0) {
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int row = base + WAVE * r;
+            if (row < n) {
+              a.wout[row] = wn[r];
+              if (a.wout32) a.wout32[row] = static_cast<float>(wn[r]);
+              nacc += wn[r] * wn[r];
+            }
+          }
+        }
+      }
+    }
+  }
+
+  double* out = a.partial + static_cast<int64_t>(blockIdx.x) * STRIDE;
+  if constexpr (MODE == ORTH_UPD) {
+    if (a.norm && wv == 0) {
+      nacc = wave_sum(nacc);
+      if (lane == 0) out[0] = nacc;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+      const int c = wv + NWV * i;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double s = wave_sum(acc[i][v]);
+        if (lane == 0 && c < ncol) out[v * ORTH_MAXCOL + c] = s;
+      }
+    }
+  }
+}
+
+template <int CPW>
+hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  const dim3 g(nblk), b(OT_THREADS);
+  const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
+  if (mode == ORTH_DOT) {
+    if (a.nvec == 1) {
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true>), g, b, 0, s, a);
+    } else if (same) {
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true>), g, b, 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false>), g, b, 0, s, a);
+    }
+  } else if (mode == ORTH_UPD_DOT) {
+    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD, 1, true>), g, b, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- finish --
+__global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
+  DevState* st = f.state;
+  if (st && st->skip) return;
+  const int nb = st ? st->nb : 0;
+  __shared__ double sh[ORTH_MAXCOL];
+  auto sum_idx = [&](int idx) {
+    double t = 0.0;
+    for (int b = 0; b < f.nblk; ++b) t += f.partial[static_cast<int64_t>(b) * f.stride + idx];
+    return t;
+  };
+  const int tid = threadIdx.x;
+  switch (f.mode) {
+    case FIN_TH:
+    case FIN_T: {
+      // new column j = nb of T; the dots cover U columns 0..nb (after the
+      // ncol_fixed locked columns)
+      const int j = nb;
+      for (int r = tid; r <= j; r += blockDim.x) {
+        const double v = sum_idx(f.ncol_fixed + r);
+        f.T[r + static_cast<int64_t>(j) * f.ldT] = v;
+        f.T[j + static_cast<int64_t>(r) * f.ldT] = v;
+      }
+      if (f.mode == FIN_TH) {
+        const int nc = f.ncol_fixed + nb + 1;
+        for (int c = tid; c < nc; c += blockDim.x) {
+          const double v = sum_idx(ORTH_MAXCOL + c);
+          f.h[c] = v;
+          sh[c] = v * v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          double t = 0.0;
+          for (int c = 0; c < nc; ++c) t += sh[c];
+          st->h1norm2 = t;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        st->nb = nb + 1;
+        st->cnt_append += 1;
+      }
+      break;
+    }
+    case FIN_TCOL: {
+      const int j = f.cnt;
+      for (int r = tid; r <= j; r += blockDim.x) {
+        const double v = sum_idx(r);
+        f.T[r + static_cast<int64_t>(j) * f.ldT] = v;
+        f.T[j + static_cast<int64_t>(r) * f.ldT] = v;
+      }
+      break;
+    }
+    case FIN_RES: {
+      for (int i = tid; i < f.cnt; i += blockDim.x) {
+        const double r2 = sum_idx(i), x2 = sum_idx(64 + i);
+        f.out[i] = sqrt(r2 / x2);
+        f.out[64 + i] = sqrt(x2);
+      }
+      break;
+    }
+    case FIN_H:
+    case FIN_H2: {
+      const int nc = f.ncol_fixed + nb + f.extra;
+      for (int c = tid; c < nc; c += blockDim.x) {
+        const double v = sum_idx(c);
+        f.h[c] = v;
+        sh[c] = v * v;
+      }
+      __syncthreads();
+      if (f.mode == FIN_H && tid == 0) {
+        double t = 0.0;
+        for (int c = 0; c < nc; ++c) t += sh[c];
+        st->h1norm2 = t;
+      }
+      break;
+    }
+    case FIN_NORM: {
+      if (tid == 0) {
+        const double b2 = sum_idx(0);
+        st->beta2 = b2;
+        st->cnt_norm += 1;
+        const bool finite = (b2 == b2) && (b2 < 1.0e308);
+        if (!finite) st->bad = 1;
+        if (!(b2 > st->tol2 * (st->h1norm2 + b2)) || !finite) {
+          st->skip = 1;  // breakdown / dropped vector: nothing is appended
+        } else {
+          st->inv_beta = 1.0 / sqrt(b2);
+        }
+      }
+      break;
+    }
+    default: {
+      for (int c = tid; c < f.cnt; c += blockDim.x) f.out[c] = sum_idx(c);
+      break;
+    }
+  }
+}
+
+__global__ void k_set_state(DevState* st, int which, double dv, int iv) {
+  switch (which) {
+    case SET_RHO: st->rho = dv; break;
+    case SET_TOL2: st->tol2 = dv; break;
+    case SET_NB: st->nb = iv; break;
+    case SET_SKIP: st->skip = iv; break;
+    case SET_RESET_STAGE:
+      st->skip = 0;
+      st->tol2 = dv;
+      break;
+  }
+}
+
+__global__ void k_set_rho_from(DevState* st, const double* theta, int idx) { st->rho = theta[idx]; }
+
+__global__ void k_reset_T(double* T, int ldT, int m, int kact, const double* theta, int off) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m * m; t += gridDim.x * blockDim.x) {
+    const int i = t % m, j = t / m;
+    T[i + static_cast<int64_t>(j) * ldT] = (i == j && i < kact) ? theta[off + i] : 0.0;
+  }
+}
+
+__global__ void k_restart_residual(int n, const double* AXt, const double* BXt, const double* theta,
+                                   int t, int next, const double* dinv, double* wout, double* vout,
+                                   float* vout32) {
+  const double th = theta[t];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double v = AXt[i] - th * BXt[i];
+    if (next == NEXT_IDENT) wout[i] = v;
+    else if (next == NEXT_JACOBI) wout[i] = dinv[i] * v;
+    else if (vout32) vout32[i] = static_cast<float>(v);
+    else vout[i] = v;
+  }
+}
+
+__global__ void k_copy_cols(int n, const double* src, int64_t lds, double* dst, int64_t ldd,
+                            int ncols) {
+  const int64_t total = static_cast<int64_t>(n) * ncols;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = t / n;
+    const int64_t i = t - c * n;
+    dst[c * ldd + i] = src[c * lds + i];
+  }
+}
+
+__global__ void k_cast_f32(int64_t n, const double* x, float* y) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = static_cast<float>(x[i]);
+}
+
+__global__ void k_cast_f64(int64_t n, const float* x, double* y) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = static_cast<double>(x[i]);
+}
+
+__global__ void k_diag_inv(int n, const int* rowptr, const int* col, const double* val,
+                           double* dinv, int* bad) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double d = 0.0;
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j)
+      if (col[j] == i) d = val[j];
+    if (!(d > 0.0)) {
+      *bad = 1;
+      dinv[i] = 1.0;
+    } else {
+      dinv[i] = 1.0 / d;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_norms(int n, const int* rowptr, const double* val,
+                                                   double* pinf, double* pfro) {
+  double mx = 0.0, fr = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j) {
+      s += fabs(val[j]);
+      fr += val[j] * val[j];
+    }
+    mx = fmax(mx, s);
+  }
+  __shared__ double smx[256], sfr[256];
+  smx[threadIdx.x] = mx;
+  sfr[threadIdx.x] = fr;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + o]);
+      sfr[threadIdx.x] += sfr[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pinf[blockIdx.x] = smx[0];
+    pfro[blockIdx.x] = sfr[0];
+  }
+}
+
+int grid1d(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
+
+}  // namespace
+
+int orth_blocks(int n) {
+  const int nslab = (std::max(n, 1) + SLAB - 1) / SLAB;
+  return std::max(1, std::min(nslab, 512));
+}
+
+int orth_stride() { return STRIDE; }
+
+hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  // columns a wavefront may own: ceil(max columns / 8)
+  int need = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
+  if (need > ORTH_MAXCOL) return hipErrorInvalidValue;
+  const int cpw = (std::max(need, 1) + NWV - 1) / NWV;
+  if (cpw <= 1) return launch_cpw<1>(mode, a, nblk, s);
+  if (cpw <= 2) return launch_cpw<2>(mode, a, nblk, s);
+  if (cpw <= 4) return launch_cpw<4>(mode, a, nblk, s);
+  if (cpw <= 8) return launch_cpw<8>(mode, a, nblk, s);
+  return launch_cpw<16>(mode, a, nblk, s);
+}
+
+hipError_t finish(const FinishArgs& f, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, f);
+  return hipGetLastError();
+}
+
+hipError_t set_state(DevState* st, int which, double dv, int iv, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st, which, dv, iv);
+  return hipGetLastError();
+}
+
+hipError_t set_rho_from(DevState* st, const double* theta, int idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_rho_from, dim3(1), dim3(1), 0, s, st, theta, idx);
+  return hipGetLastError();
+}
+
+hipError_t reset_T(double* T, int ldT, int m, int kact, const double* theta, int off, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_T, dim3(16), dim3(256), 0, s, T, ldT, m, kact, theta, off);
+  return hipGetLastError();
+}
+
+hipError_t restart_residual(int n, const double* AXt, const double* BXt, const double* theta,
+                            int t, int next, const double* dinv, double* wout, double* vout,
+                            float* vout32, hipStream_t s) {
+  hipLaunchKernelGGL(k_restart_residual, dim3(grid1d(n)), dim3(256), 0, s, n, AXt, BXt, theta, t,
+                     next, dinv, wout, vout, vout32);
+  return hipGetLastError();
+}
+
+hipError_t copy_cols(int n, const double* src, int64_t lds, double* dst, int64_t ldd, int ncols,
+                     hipStream_t s) {
+  if (ncols <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_cols, dim3(grid1d(static_cast<int64_t>(n) * ncols)), dim3(256), 0, s,
+                     n, src, lds, dst, ldd, ncols);
+  return hipGetLastError();
+}
+
+hipError_t cast_f32(int64_t n, const double* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f32, dim3(grid1d(n)), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t cast_f64(int64_t n, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f64, dim3(grid1d(n)), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t extract_diag_inv(int n, const int* rowptr, const int* col, const double* val,
+                            double* dinv, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_inv, dim3(grid1d(n)), dim3(256), 0, s, n, rowptr, col, val, dinv, bad);
+  return hipGetLastError();
+}
+
+int rownorm_blocks(int n) { return grid1d(n); }
+
+hipError_t row_norms(int n, const int* rowptr, const double* val, double* partial_inf,
+                     double* partial_fro, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_norms, dim3(nblk), dim3(256), 0, s, n, rowptr, val, partial_inf,
+                     partial_fro);
+  return hipGetLastError();
+}
+
+}  // namespace trplk

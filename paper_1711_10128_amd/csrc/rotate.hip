@@ -1,0 +1,170 @@
+// Thick restart: X = U Y(:, 1:k) for the basis and its products
+// (Alg. 1, restart with the k smallest Ritz vectors), in place, with the
+// residual norms of the new Ritz pairs computed in the same pass.
+//
+// This is a dense (n x b) * (b x k) product, so it runs on the FP64 matrix
+// cores: each wavefront computes the transposed 16-row output tile
+// X(rows,:)^T = Y^T U(rows,:)^T with V_MFMA_F64_16X16X4F64, Y^T fragments held
+// in registers for the whole kernel and U fragments loaded straight from
+// memory (16 consecutive rows of 4 columns per instruction).  The output tile
+// layout puts 16 consecutive rows of one column in consecutive lanes, so the
+// stores are as contiguous as the loads.  A wavefront reads all b columns of
+// its rows before it writes the first k of them, which makes the in-place
+// update safe: no other wavefront touches those rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace trplk {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int RT = 256;          // threads per block (4 wavefronts)
+constexpr int KSMAX = SYEV_MAXB / 4;
+
+template <int NTILE>
+__global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
+  const int b = a.state ? a.state->nb : a.b_fixed;
+  const int kk = min(a.kout, b);
+  const int nks = (b + 3) / 4;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int li = lane & 15;   // row within the tile / output column of A fragment
+  const int lg = lane >> 4;   // k index within a K-step / output row group
+  const int64_t ld = a.ld;
+  const int n = a.n;
+
+  // A operand (16 outputs x 4 inputs): lane holds Y^T[16 t + li][4 ks + lg]
+  double yf[NTILE][KSMAX];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+      const int kin = 4 * ks + lg, kout = 16 * t + li;
+      yf[t][ks] = (kin < b && kout < kk) ? a.Y[kin + static_cast<int64_t>(kout) * a.ldY] : 0.0;
+    }
+  }
+  double th[NTILE][4];
+  double rs[NTILE][4], xs[NTILE][4];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kc = 16 * t + 4 * lg + r;
+      th[t][r] = (a.theta && kc < kk) ? a.theta[kc] : 0.0;
+      rs[t][r] = 0.0;
+      xs[t][r] = 0.0;
+    }
+
+  const int nwave = gridDim.x * (RT / WAVE);
+  const int ntile_rows = (n + 15) / 16;
+  for (int rb = blockIdx.x * (RT / WAVE) + wv; rb < ntile_rows; rb += nwave) {
+    const int row = rb * 16 + li;
+    const bool ok = row < n;
+    d4 DX[NTILE], DA[NTILE], DB[NTILE];
+    double* mats[3] = {a.U, a.AU, a.BU};
+#pragma unroll
+    for (int mi = 0; mi < 3; ++mi) {
+      double* M = mats[mi];
+      if (M == nullptr) continue;
+      d4 D[NTILE];
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t) D[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KSMAX; ++ks) {
+        if (ks < nks) {
+          const int kin = 4 * ks + lg;
+          const double bv = (ok && kin < b) ? M[kin * ld + row] : 0.0;
+#pragma unroll
+          for (int t = 0; t < NTILE; ++t)
+            D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yf[t][ks], bv, D[t], 0, 0, 0);
+        }
+      }
+      // lane holds X(row = rb*16 + li, col = 16 t + 4 lg + r)
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int kc = 16 * t + 4 * lg + r;
+          if (ok && kc < kk) M[kc * ld + row] = D[t][r];
+        }
+        if (mi == 0) DX[t] = D[t];
+        else if (mi == 1) DA[t] = D[t];
+        else DB[t] = D[t];
+      }
+    }
+    if (a.theta && a.AU) {
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double x = DX[t][r];
+          const double bx = a.BU ? DB[t][r] : x;
+          const double rr = DA[t][r] - th[t][r] * bx;
+          rs[t][r] += rr * rr;
+          xs[t][r] += x * x;
+        }
+    }
+  }
+
+  if (a.theta && a.AU) {
+    // sum over the 16 lanes that hold the same output columns
+    __shared__ double sr[RT / WAVE][2][64];
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = rs[t][r], w = xs[t][r];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          v += __shfl_xor(v, off, WAVE);
+          w += __shfl_xor(w, off, WAVE);
+        }
+        const int kc = 16 * t + 4 * lg + r;
+        if (li == 0 && kc < 64) {
+          sr[wv][0][kc] = v;
+          sr[wv][1][kc] = w;
+        }
+      }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int kc = threadIdx.x;
+      double v = 0.0, w = 0.0;
+      if (kc < 16 * NTILE) {
+        for (int q = 0; q < RT / WAVE; ++q) {
+          v += sr[q][0][kc];
+          w += sr[q][1][kc];
+        }
+      }
+      a.partial[static_cast<int64_t>(blockIdx.x) * 128 + kc] = v;
+      a.partial[static_cast<int64_t>(blockIdx.x) * 128 + 64 + kc] = w;
+    }
+  }
+}
+
+}  // namespace
+
+int rot_blocks(int n) {
+  const int tiles = (std::max(n, 1) + 15) / 16;
+  const int want = (tiles + (RT / WAVE) - 1) / (RT / WAVE);
+  return std::max(1, std::min(want, 1024));
+}
+
+hipError_t rotate(const RotArgs& a, int nblk, hipStream_t s) {
+  const int nt = (a.kout + 15) / 16;
+  const dim3 g(nblk), b(RT);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_rotate<1>, g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_rotate<2>, g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_rotate<3>, g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_rotate<4>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace trplk

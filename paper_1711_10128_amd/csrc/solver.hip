@@ -1,0 +1,1224 @@
+// TRPL+K driver and C ABI.
+//
+// The host sequences kernel launches on the context stream; all n-length
+// work runs on the device.  Per restart cycle the host reads back one small
+// report (the Ritz values and residual norms of the kept Ritz pairs, O(m)
+// doubles) to take the locking and target decisions of Alg. 1; everything
+// inside a cycle is launched without a host synchronisation.  The basis size
+// lives in device memory (DevState::nb) so that an invariant-subspace
+// breakdown or a dropped +K vector detected on the device turns the rest of
+// the stage into no-ops.
+//
+// Memory layout (all float64, column-major, leading dimension ld = n rounded
+// up to 32 elements, i.e. 256-byte aligned columns):
+//   W  = [Q | U]   locked vectors (hard locking) followed by the active
+//                  basis; locking a converged Ritz vector only moves the start
+//                  u0 of U one column to the right, so [Q, U] stays one
+//                  contiguous block for the Gram-Schmidt passes.
+//   AW = A W, BW = B W (BW only for B != I).
+//   T (m x m), theta (m), Y (m x m), the previous Ritz vectors (n x l) and
+//   a handful of n-vectors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/trplk.h"
+#include "common.h"
+
+using namespace trplk;
+
+namespace {
+
+constexpr double BREAKDOWN_TOL = 1e-14;  // inner-step breakdown (relative)
+constexpr double PLUSK_DROP_TOL = 1e-12; // +K vector dropped when nearly dependent
+
+struct DevCsr {
+  int n = 0;
+  int64_t nnz = 0;
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  bool owned = false;
+  SpmvPlan plan;
+};
+
+struct Report {
+  int nb;
+  int bad;
+  int pad[2];
+  long long cnt_append;
+  long long cnt_norm;
+  double theta[SYEV_MAXB];
+  double res[SYEV_MAXB];
+  double xn[SYEV_MAXB];
+};
+
+struct Prof {
+  hipEvent_t a, b;
+  int cls;
+  int64_t bytes;
+};
+
+}  // namespace
+
+struct trplk_ctx {
+  hipStream_t s = nullptr;
+  trplk_opts o{};
+  int n = 0;
+  DevCsr A, B;
+  bool hasB = false;
+  int prec = TRPLK_PREC_NONE;
+  double* dinv = nullptr;
+  DevCsr G, Gt;  // factor preconditioner M = G^T G
+  double normA_inf = 0.0, normA_fro = 0.0;
+  // workspace
+  int64_t ld = 0;
+  int pcap = 0;  // locked-vector capacity
+  int m = 0;
+  double* W = nullptr;
+  double* AW = nullptr;
+  double* BW = nullptr;
+  double* w = nullptr;
+  double* wtmp = nullptr;
+  double* tmpB = nullptr;
+  double* vtmp = nullptr;
+  double* ytmp = nullptr;
+  float* v32 = nullptr;
+  float* y32 = nullptr;
+  float* wtmp32 = nullptr;
+  double* Xprev = nullptr;
+  double* T = nullptr;
+  double* theta = nullptr;
+  double* Y = nullptr;
+  double* hbuf = nullptr;
+  double* partial = nullptr;
+  double* resout = nullptr;
+  DevState* st = nullptr;
+  Report* rep_h = nullptr;
+  Report* rep_d = nullptr;
+  int orth_nblk = 0, rot_nblk = 0;
+  int64_t partial_bytes = 0;
+  bool ws_ready = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> evpool;
+  std::vector<Prof> prof;
+  size_t evused = 0;
+  // results
+  bool solved = false;
+  int u0 = 0;             // locked columns in front of U
+  int nout = 0;           // result columns in W starting at column 0
+  std::vector<double> theta_out, res_out;
+  std::vector<int> conv_out;
+  trplk_stats stats{};
+  std::string err;
+  int64_t dev_bytes = 0;
+  bool fp32_phase = false;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+int set_err(trplk_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(ctx, TRPLK_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(trplk_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e == hipSuccess) c->dev_bytes += static_cast<int64_t>(count * sizeof(T));
+  return e;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int validate_host_csr(const trplk_csr* M, int n, std::string& why) {
+  if (!M || !M->rowptr || !M->col || !M->val) {
+    why = "null CSR array";
+    return TRPLK_EINVAL;
+  }
+  if (M->n != n || M->n < 1) {
+    why = "CSR dimension mismatch";
+    return TRPLK_EINVAL;
+  }
+  if (M->nnz < 0 || M->nnz >= (int64_t(1) << 31)) {
+    why = "nnz out of range";
+    return TRPLK_EINVAL;
+  }
+  if (M->rowptr[0] != 0 || M->rowptr[n] != M->nnz) {
+    why = "rowptr[0] must be 0 and rowptr[n] must equal nnz";
+    return TRPLK_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (M->rowptr[i + 1] < M->rowptr[i]) {
+      why = "rowptr not monotone";
+      return TRPLK_EINVAL;
+    }
+    for (int j = M->rowptr[i]; j < M->rowptr[i + 1]; ++j) {
+      if (M->col[j] < 0 || M->col[j] >= n) {
+        why = "column index out of range";
+        return TRPLK_EINVAL;
+      }
+      if (j > M->rowptr[i] && M->col[j] <= M->col[j - 1]) {
+        why = "columns not sorted or duplicated";
+        return TRPLK_EINVAL;
+      }
+      if (!std::isfinite(M->val[j])) {
+        why = "non-finite matrix value";
+        return TRPLK_ENUMERIC;
+      }
+    }
+  }
+  return TRPLK_OK;
+}
+
+int upload_csr(trplk_ctx* c, DevCsr& D, const trplk_csr* M, int32_t mem, bool want32) {
+  D.n = M->n;
+  D.nnz = M->nnz;
+  if (mem == TRPLK_MEM_HOST) {
+    D.owned = true;
+    HIPCHK(c, dalloc(c, &D.rowptr, D.n + 1));
+    HIPCHK(c, dalloc(c, &D.col, std::max<int64_t>(D.nnz, 1)));
+    HIPCHK(c, dalloc(c, &D.val, std::max<int64_t>(D.nnz, 1)));
+    HIPCHK(c, hipMemcpyAsync(D.rowptr, M->rowptr, sizeof(int) * (D.n + 1), hipMemcpyHostToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(D.col, M->col, sizeof(int) * D.nnz, hipMemcpyHostToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(D.val, M->val, sizeof(double) * D.nnz, hipMemcpyHostToDevice, c->s));
+  } else {
+    D.owned = false;
+    D.rowptr = const_cast<int*>(M->rowptr);
+    D.col = const_cast<int*>(M->col);
+    D.val = const_cast<double*>(M->val);
+  }
+  if (want32) {
+    HIPCHK(c, dalloc(c, &D.val32, std::max<int64_t>(D.nnz, 1)));
+    HIPCHK(c, cast_f32(D.nnz, D.val, D.val32, c->s));
+  }
+  HIPCHK(c, spmv_plan(D.plan, D.n, D.rowptr, 0, c->s));
+  return TRPLK_OK;
+}
+
+void free_csr(DevCsr& D) {
+  if (D.owned) {
+    dfree(D.rowptr);
+    dfree(D.col);
+    dfree(D.val);
+  }
+  dfree(D.val32);
+  spmv_plan_free(D.plan);
+  D = DevCsr();
+}
+
+// ------------------------------------------------------------ profiling --
+enum { PC_SPMV = 0, PC_ORTH = 1, PC_PREC = 2, PC_ROT = 3, PC_RR = 4 };
+
+struct ProfScope {
+  trplk_ctx* c;
+  size_t idx = SIZE_MAX;
+  ProfScope(trplk_ctx* ctx, int cls, int64_t bytes) : c(ctx) {
+    if (!c->o.profile) return;
+    if (c->evused + 2 > c->evpool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->evpool.push_back(e);
+      }
+    }
+    Prof p{c->evpool[c->evused], c->evpool[c->evused + 1], cls, bytes};
+    c->evused += 2;
+    (void)hipEventRecord(p.a, c->s);
+    idx = c->prof.size();
+    c->prof.push_back(p);
+  }
+  ~ProfScope() {
+    if (idx != SIZE_MAX) (void)hipEventRecord(c->prof[idx].b, c->s);
+  }
+};
+
+// ------------------------------------------------------------ workspace --
+int ensure_workspace(trplk_ctx* c) {
+  if (c->ws_ready) return TRPLK_OK;
+  const int n = c->n;
+  const trplk_opts& o = c->o;
+  c->m = o.m;
+  c->ld = (static_cast<int64_t>(n) + 31) / 32 * 32;
+  const bool hard = (o.locking == TRPLK_LOCK_HARD) || (o.locking == TRPLK_LOCK_AUTO && o.p > o.k);
+  c->pcap = hard ? o.p : 0;
+  const int64_t cols = c->pcap + c->m;
+  HIPCHK(c, dalloc(c, &c->W, c->ld * cols));
+  HIPCHK(c, dalloc(c, &c->AW, c->ld * cols));
+  if (c->hasB) HIPCHK(c, dalloc(c, &c->BW, c->ld * cols));
+  HIPCHK(c, dalloc(c, &c->w, c->ld));
+  HIPCHK(c, dalloc(c, &c->wtmp, c->ld));
+  HIPCHK(c, dalloc(c, &c->vtmp, c->ld));
+  HIPCHK(c, dalloc(c, &c->ytmp, c->ld));
+  if (c->hasB) HIPCHK(c, dalloc(c, &c->tmpB, c->ld));
+  HIPCHK(c, dalloc(c, &c->v32, c->ld));
+  HIPCHK(c, dalloc(c, &c->y32, c->ld));
+  HIPCHK(c, dalloc(c, &c->wtmp32, c->ld));
+  HIPCHK(c, dalloc(c, &c->Xprev, c->ld * std::max(o.l, 1)));
+  HIPCHK(c, dalloc(c, &c->T, SYEV_MAXB * SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->theta, SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->Y, SYEV_MAXB * SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->hbuf, ORTH_MAXCOL));
+  HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
+  c->orth_nblk = orth_blocks(n);
+  c->rot_nblk = rot_blocks(n);
+  int64_t pb = static_cast<int64_t>(c->orth_nblk) * orth_stride();
+  pb = std::max<int64_t>(pb, static_cast<int64_t>(c->rot_nblk) * 128);
+  pb = std::max<int64_t>(pb, spmv_partial_blocks(c->A.plan));
+  if (c->hasB) pb = std::max<int64_t>(pb, spmv_partial_blocks(c->B.plan));
+  pb = std::max<int64_t>(pb, 2 * static_cast<int64_t>(rownorm_blocks(n)));
+  HIPCHK(c, dalloc(c, &c->partial, pb));
+  HIPCHK(c, dalloc(c, &c->st, 1));
+  HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), c->s));
+  HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->rep_h), sizeof(Report)));
+  HIPCHK(c, dalloc(c, &c->rep_d, 1));
+  HIPCHK(c, hipEventCreate(&c->ev0));
+  HIPCHK(c, hipEventCreate(&c->ev1));
+  c->ws_ready = true;
+  return TRPLK_OK;
+}
+
+// ------------------------------------------------------------- building --
+// The report kernel copies the device scalars the host needs once per cycle.
+__global__ void k_report(const DevState* st, const double* theta, const double* resout, int nth,
+                         int nres, Report* rep) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    rep->nb = st->nb;
+    rep->bad = st->bad;
+    rep->cnt_append = st->cnt_append;
+    rep->cnt_norm = st->cnt_norm;
+  }
+  if (t < nth && t < SYEV_MAXB) rep->theta[t] = theta[t];
+  if (t < nres && t < SYEV_MAXB) {
+    rep->res[t] = resout[t];
+    rep->xn[t] = resout[64 + t];
+  }
+}
+
+struct Solver {
+  trplk_ctx* c;
+  int n;
+  int64_t ld;
+  hipStream_t s;
+  int nbh = 0;  // host-side expected basis size
+  bool keepT = false;  // the next cycle keeps T(0:kact,0:kact) (recomputed X^T A X)
+
+  double* Ucol(int j) const { return c->W + (c->u0 + j) * ld; }
+  double* AUcol(int j) const { return c->AW + (c->u0 + j) * ld; }
+  double* BUcol(int j) const { return c->hasB ? c->BW + (c->u0 + j) * ld : Ucol(j); }
+  double* Wq() const { return c->W; }              // [Q | U] start
+  double* BWq() const { return c->hasB ? c->BW : c->W; }
+
+  int64_t spmv_bytes(const DevCsr& M, bool f32) const {
+    const int64_t vb = f32 ? 4 : 8;
+    return M.nnz * (vb + 4) + 4 * (static_cast<int64_t>(M.n) + 1) + 2 * vb * M.n;
+  }
+
+  hipError_t orth(int mode, const OrthArgs& a) {
+    int64_t cols = a.ncol_fixed + a.ncol_extra + (a.state ? nbh : 0);
+    int64_t bytes;
+    const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
+    if (mode == ORTH_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 8LL * n * a.nvec;
+    else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
+    else bytes = 8 * cols * n + 16LL * n;
+    ProfScope ps(c, PC_ORTH, bytes);
+    return orth_pass(mode, a, c->orth_nblk, s);
+  }
+
+  hipError_t spmv(const DevCsr& M, const SpmvArgs& a, bool f32, int cls, int64_t extra_bytes) {
+    ProfScope ps(c, cls, spmv_bytes(M, f32) + extra_bytes);
+    return f32 ? spmv_f32(M.plan, a, s) : spmv_f64(M.plan, a, s);
+  }
+
+  hipError_t fin(const FinishArgs& f) { return finish(f, s); }
+
+  int maxcols() const { return c->u0 + c->m + 1; }
+
+  // B-CGS2 of the vector in c->w against [Q | U(:, 0:nb)]; leaves the
+  // projected vector in c->wtmp (and wtmp32), its B-norm in the state.
+  // first_pass: false when h1 is already in hbuf (fused with the T column).
+  int project(bool first_pass) {
+    Status S;
+    const int ncf = c->u0;
+    if (first_pass) {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
+      a.Md0 = BWq(); a.vec0 = c->w; a.nvec = 1; a.partial = c->partial;
+      S.check(orth(ORTH_DOT, a), "orth h1");
+      FinishArgs f;
+      f.mode = FIN_H; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
+      S.check(fin(f), "fin h1");
+    }
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
+      a.Mu = Wq(); a.Md1 = BWq(); a.h = c->hbuf; a.w = c->w; a.partial = c->partial;
+      S.check(orth(ORTH_UPD_DOT, a), "orth upd-dot");
+      FinishArgs f;
+      f.mode = FIN_H2; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
+      S.check(fin(f), "fin h2");
+    }
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
+      a.Mu = Wq(); a.h = c->hbuf; a.w = c->w; a.wout = c->wtmp;
+      a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
+      a.norm = !c->hasB; a.partial = c->partial;
+      S.check(orth(ORTH_UPD, a), "orth upd");
+    }
+    FinishArgs f;
+    f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
+    if (c->hasB) {
+      SpmvArgs b;
+      b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = c->wtmp;
+      b.mode = SPMV_DOT; b.state = c->st; b.y = c->tmpB; b.xd = c->wtmp; b.partial = c->partial;
+      S.check(spmv(c->B, b, false, PC_SPMV, 8LL * n), "spmv B");
+      f.nblk = spmv_partial_blocks(c->B.plan);
+      f.stride = 1;
+    } else {
+      f.nblk = c->orth_nblk;
+      f.stride = orth_stride();
+    }
+    S.check(fin(f), "fin norm");
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
+  // Append wtmp / beta as basis column nb; z = A g into AU.  next selects the
+  // formation of the next inner direction in the epilogue.
+  int append(int next) {
+    Status S;
+    SpmvArgs a;
+    const bool f32 = c->fp32_phase;
+    a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col;
+    a.val = f32 ? static_cast<const void*>(c->A.val32) : static_cast<const void*>(c->A.val);
+    a.x = f32 ? static_cast<const void*>(c->wtmp32) : static_cast<const void*>(c->wtmp);
+    a.mode = SPMV_APPEND; a.use_beta = true; a.state = c->st; a.xd = c->wtmp;
+    a.bx = c->hasB ? c->tmpB : nullptr;
+    a.U = c->W; a.AU = c->AW; a.BU = c->BW; a.ld = ld; a.col0 = c->u0;
+    int64_t extra = 8LL * n * (c->hasB ? 4 : 2);
+    if (next == 1) {
+      if (c->prec == TRPLK_PREC_JACOBI) {
+        a.next = NEXT_JACOBI; a.dinv = c->dinv; a.wout = c->w; extra += 16LL * n;
+      } else if (c->prec == TRPLK_PREC_NONE) {
+        a.next = NEXT_IDENT; a.wout = c->w; extra += 8LL * n;
+      } else {
+        a.next = NEXT_STORE_V;
+        if (c->o.precision == TRPLK_MIXED) { a.vout32 = c->v32; extra += 4LL * n; }
+        else { a.vout = c->vtmp; extra += 8LL * n; }
+      }
+    }
+    S.check(spmv(c->A, a, f32, PC_SPMV, extra), "spmv append");
+    if (next == 1 && c->prec >= TRPLK_PREC_FSAI) S.check(apply_factor(), "factor");
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
+  // w = G^T (G v) with v in vtmp (float64) or v32 (mixed)
+  hipError_t apply_factor() {
+    const bool f32 = c->o.precision == TRPLK_MIXED;
+    SpmvArgs a;
+    a.n = n; a.rowptr = c->G.rowptr; a.col = c->G.col; a.state = c->st; a.mode = SPMV_STORE;
+    a.val = f32 ? static_cast<const void*>(c->G.val32) : static_cast<const void*>(c->G.val);
+    a.x = f32 ? static_cast<const void*>(c->v32) : static_cast<const void*>(c->vtmp);
+    a.y = f32 ? static_cast<void*>(c->y32) : static_cast<void*>(c->ytmp);
+    hipError_t e = spmv(c->G, a, f32, PC_PREC, 0);
+    if (e != hipSuccess) return e;
+    SpmvArgs b;
+    b.n = n; b.rowptr = c->Gt.rowptr; b.col = c->Gt.col; b.state = c->st; b.mode = SPMV_STORE;
+    b.val = f32 ? static_cast<const void*>(c->Gt.val32) : static_cast<const void*>(c->Gt.val);
+    b.x = f32 ? static_cast<const void*>(c->y32) : static_cast<const void*>(c->ytmp);
+    b.y = c->w; b.out_f64 = true;
+    return spmv(c->Gt, b, f32, PC_PREC, f32 ? 4LL * n : 0);
+  }
+
+  // T column of the vector just appended: T(0:nb, nb) = U^T z (after
+  // increments nb), optionally fused with h1 = BW^T w for the next direction.
+  int tcol(bool with_h1) {
+    Status S;
+    OrthArgs a;
+    a.n = n; a.ld = ld; a.ncol_fixed = c->u0; a.ncol_extra = 1; a.state = c->st;
+    a.ncol_max = maxcols();
+    a.Md0 = Wq(); a.vec0_base = c->AW; a.vec0_col0 = c->u0; a.partial = c->partial;
+    if (with_h1) {
+      a.nvec = 2; a.Md1 = BWq(); a.vec1 = c->w;
+    } else {
+      a.nvec = 1;
+    }
+    S.check(orth(ORTH_DOT, a), "orth tcol");
+    FinishArgs f;
+    f.mode = with_h1 ? FIN_TH : FIN_T; f.partial = c->partial; f.nblk = c->orth_nblk;
+    f.stride = orth_stride(); f.state = c->st; f.ncol_fixed = c->u0; f.T = c->T; f.ldT = SYEV_MAXB;
+    f.h = c->hbuf;
+    S.check(fin(f), "fin tcol");
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
+  int stage_reset(double tol) {
+    HIPCHK(c, set_state(c->st, SET_RESET_STAGE, tol * tol, 0, s));
+    return TRPLK_OK;
+  }
+
+  // orthogonalise + append one non-Krylov vector held in c->w (start block
+  // column or +K vector) and fill its T column
+  int add_vector(double tol) {
+    int r;
+    if ((r = stage_reset(tol))) return r;
+    if ((r = project(true))) return r;
+    if ((r = append(0))) return r;
+    if ((r = tcol(false))) return r;
+    ++nbh;
+    return TRPLK_OK;
+  }
+
+  int load_w(const double* src, int32_t mem) {
+    HIPCHK(c, hipMemcpyAsync(c->w, src, sizeof(double) * n,
+                             mem == TRPLK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    return TRPLK_OK;
+  }
+
+  // Rayleigh-Ritz on T(0:nb,0:nb), rotation of U, AU, BU to kout columns
+  // and residuals of the first `nres` Ritz pairs; fills the host report.
+  int rayleigh_ritz(int kout, int nres) {
+    Status S;
+    {
+      ProfScope ps(c, PC_RR, 0);
+      S.check(syev(c->T, SYEV_MAXB, 0, &c->st->nb, 0, c->theta, c->Y, SYEV_MAXB, s), "syev");
+    }
+    RotArgs r;
+    r.n = n; r.kout = kout; r.state = c->st; r.Y = c->Y; r.ldY = SYEV_MAXB;
+    r.U = Ucol(0); r.AU = AUcol(0); r.BU = c->hasB ? BUcol(0) : nullptr; r.ld = ld;
+    r.theta = c->theta; r.partial = c->partial;
+    {
+      const int64_t mats = c->hasB ? 3 : 2;
+      ProfScope ps(c, PC_ROT, 8LL * n * (nbh + kout) * mats);
+      S.check(rotate(r, c->rot_nblk, s), "rotate");
+    }
+    FinishArgs f;
+    f.mode = FIN_RES; f.partial = c->partial; f.nblk = c->rot_nblk; f.stride = 128;
+    f.out = c->resout; f.cnt = nres;
+    S.check(fin(f), "fin res");
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, c->st, c->theta, c->resout, SYEV_MAXB,
+                       nres, c->rep_d);
+    S.check(hipGetLastError(), "report");
+    S.check(hipMemcpyAsync(c->rep_h, c->rep_d, sizeof(Report), hipMemcpyDeviceToHost, s), "d2h");
+    S.check(hipStreamSynchronize(s), "sync");
+    if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+    const Report& R = *c->rep_h;
+    const int kk = std::min(kout, R.nb);
+    for (int i = 0; i < kk; ++i)
+      if (!std::isfinite(R.theta[i])) return set_err(c, TRPLK_ENUMERIC, "non-finite Ritz value");
+    if (R.bad) return set_err(c, TRPLK_ENOTSPD, "B-norm squared not positive or not finite");
+    return TRPLK_OK;
+  }
+
+  // Recompute A X for the kact active columns in float64 and the projected
+  // block T(0:kact, 0:kact) = X^T A X (used when the mixed form switches its
+  // SpMV to float64).
+  int refresh_products(int kact) {
+    Status S;
+    for (int j = 0; j < kact; ++j) {
+      SpmvArgs a;
+      a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = Ucol(j);
+      a.mode = SPMV_STORE; a.y = AUcol(j);
+      S.check(spmv(c->A, a, false, PC_SPMV, 0), "refresh spmv");
+    }
+    for (int j = 0; j < kact; ++j) {
+      OrthArgs o;
+      o.n = n; o.ld = ld; o.ncol_fixed = j + 1; o.ncol_max = j + 1; o.Md0 = Ucol(0);
+      o.vec0 = AUcol(j); o.nvec = 1; o.partial = c->partial;
+      S.check(orth(ORTH_DOT, o), "refresh T");
+      FinishArgs f;
+      f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.T = c->T; f.ldT = SYEV_MAXB; f.cnt = j;
+      S.check(fin(f), "fin refresh T");
+    }
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
+  int run(const double* x0, int32_t mem, trplk_stats* out);
+};
+
+int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
+  const trplk_opts& o = c->o;
+  const int p = o.p, m = o.m, k = o.k, l = o.l;
+  const bool hard = c->pcap > 0;
+  const double normA = (o.norm == TRPLK_NORM_FRO) ? c->normA_fro : c->normA_inf;
+  const double thr = o.tol * normA;
+  const double mixed_switch = (o.mixed_switch > 0 ? o.mixed_switch : 1e-5) * normA;
+  trplk_stats& stt = c->stats;
+  stt = trplk_stats{};
+  stt.normA = normA;
+  c->prof.clear();
+  c->evused = 0;
+  c->u0 = 0;
+  c->solved = false;
+  c->fp32_phase = (o.precision == TRPLK_MIXED);
+  int r;
+  HIPCHK(c, hipEventRecord(c->ev0, s));
+  HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
+  HIPCHK(c, hipMemsetAsync(c->T, 0, sizeof(double) * SYEV_MAXB * SYEV_MAXB, s));
+  // ---- start block: B-orthonormalise X0 column by column, A X0, T0 ----
+  nbh = 0;
+  for (int j = 0; j < k; ++j) {
+    if ((r = load_w(x0 + static_cast<int64_t>(j) * n, mem))) return r;
+    if ((r = add_vector(BREAKDOWN_TOL))) return r;
+  }
+  if ((r = rayleigh_ritz(k, std::min(k, SYEV_MAXB)))) return r;
+  if (c->rep_h->nb != k) return set_err(c, TRPLK_EINVAL, "start block is rank deficient");
+  long long prev_app = c->rep_h->cnt_append;
+  stt.matvecs = prev_app;
+  std::vector<double> th(c->rep_h->theta, c->rep_h->theta + k);
+  std::vector<double> res(c->rep_h->res, c->rep_h->res + k);
+  std::vector<double> locked_theta;
+  int t = 0;         // target among the active Ritz pairs
+  int kact = k;      // active Ritz vectors kept
+  int nprev = 0;     // previous Ritz vectors held in Xprev
+  int th_off = 0;    // index of the first active Ritz value in theta (device)
+  bool done = false;
+  int cycle = 0;
+  for (cycle = 1; cycle <= o.max_cycles; ++cycle) {
+    // ---- restart vector u1 = M (A x_t - rho B x_t) ----
+    const double rho = th[t];
+    HIPCHK(c, set_state(c->st, SET_RHO, rho, 0, s));
+    HIPCHK(c, set_state(c->st, SET_NB, 0.0, kact, s));
+    if (!keepT) HIPCHK(c, reset_T(c->T, SYEV_MAXB, SYEV_MAXB, kact, c->theta, th_off, s));
+    keepT = false;
+    nbh = kact;
+    {
+      const bool fac = c->prec >= TRPLK_PREC_FSAI;
+      const int next = c->prec == TRPLK_PREC_JACOBI ? NEXT_JACOBI
+                       : c->prec == TRPLK_PREC_NONE ? NEXT_IDENT : NEXT_STORE_V;
+      const bool f32v = fac && o.precision == TRPLK_MIXED;
+      HIPCHK(c, restart_residual(n, AUcol(t), BUcol(t), c->theta, th_off + t, next, c->dinv, c->w,
+                                 fac && !f32v ? c->vtmp : nullptr, f32v ? c->v32 : nullptr, s));
+      if (fac) HIPCHK(c, apply_factor());
+      stt.precs += 1;
+    }
+    // ---- inner preconditioned Krylov loop, eq. (3.1) ----
+    const int m_in = m - kact - nprev;
+    if ((r = stage_reset(BREAKDOWN_TOL))) return r;
+    for (int j = 0; j < m_in; ++j) {
+      if ((r = project(j == 0))) return r;
+      const bool more = j < m_in - 1;
+      if ((r = append(more ? 1 : 0))) return r;
+      if ((r = tcol(more))) return r;
+      ++nbh;
+      if (more) stt.precs += 1;
+    }
+    // ---- +K: previous Ritz vectors after the Krylov block ----
+    for (int j = 0; j < nprev; ++j) {
+      if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
+      if ((r = add_vector(PLUSK_DROP_TOL))) return r;
+    }
+    HIPCHK(c, set_state(c->st, SET_SKIP, 0.0, 0, s));
+    // previous vectors are taken from X before the Rayleigh-Ritz
+    const int want = hard ? (p - c->u0) : p;
+    const int lcnt = std::max(0, std::min(t + l, want) - t);
+    HIPCHK(c, copy_cols(n, Ucol(t), ld, c->Xprev, ld, lcnt, s));
+    // ---- Rayleigh-Ritz and thick restart ----
+    const int kout = std::min(k, SYEV_MAXB);
+    if ((r = rayleigh_ritz(kout, kout))) return r;
+    const Report& R = *c->rep_h;
+    stt.matvecs += R.cnt_append - prev_app;
+    prev_app = R.cnt_append;
+    const int kk = std::min(kout, R.nb);
+    th.assign(R.theta, R.theta + kk);
+    res.assign(R.res, R.res + kk);
+    nprev = lcnt;
+    th_off = 0;
+    if (!hard) {
+      int tn = 0;
+      while (tn < p && res[tn] <= thr) ++tn;
+      if (tn > t) nprev = std::max(0, nprev - (tn - t));
+      if (tn > t && nprev > 0) {
+        // drop the first previous vector(s): shift the kept ones left
+        const int drop = lcnt - nprev;
+        HIPCHK(c, copy_cols(n, c->Xprev + drop * ld, ld, c->Xprev, ld, nprev, s));
+      }
+      t = tn;
+      kact = kk;
+      if (t >= p) {
+        done = true;
+        break;
+      }
+    } else {
+      int nlock = 0;
+      while (c->u0 + nlock < p && nlock < kk && res[nlock] <= thr) ++nlock;
+      if (nlock) {
+        for (int i = 0; i < nlock; ++i) locked_theta.push_back(th[i]);
+        const int drop = std::min(nlock, nprev);
+        nprev -= drop;
+        if (drop && nprev > 0)
+          HIPCHK(c, copy_cols(n, c->Xprev + drop * ld, ld, c->Xprev, ld, nprev, s));
+        c->u0 += nlock;
+        th.erase(th.begin(), th.begin() + nlock);
+        res.erase(res.begin(), res.begin() + nlock);
+        th_off = nlock;
+      }
+      t = 0;
+      kact = kk - nlock;
+      if (c->u0 >= p) {
+        done = true;
+        break;
+      }
+      if (kact <= 0) return set_err(c, TRPLK_EINVAL, "restart size exhausted by locking");
+    }
+    // mixed form: float64 SpMV once every target residual is small
+    if (c->fp32_phase) {
+      double worst = 0.0;
+      for (int i = t; i < std::min<int>(static_cast<int>(res.size()), hard ? 1 : p); ++i)
+        worst = std::max(worst, res[i]);
+      if (worst <= mixed_switch) {
+        c->fp32_phase = false;
+        stt.fp32_cycles = cycle;
+        // theta on the device must hold the active values from index th_off
+        if ((r = refresh_products(kact))) return r;
+        stt.matvecs += kact;
+        // T(0:kact,0:kact) now holds X^T A X; the next cycle keeps it
+        keepT = true;
+      }
+    }
+  }
+  if (cycle > o.max_cycles) cycle = o.max_cycles;
+  stt.cycles = cycle;
+  if (c->fp32_phase) stt.fp32_cycles = cycle;
+  stt.bmatvecs = c->hasB ? c->rep_h->cnt_norm : 0;
+  // ---- results ----
+  if (hard) {
+    // final Rayleigh-Ritz on the locked set: T_Q = Q^T A Q
+    const int nq = c->u0;
+    if (nq > 0) {
+      Status S;
+      for (int j = 0; j < nq; ++j) {
+        OrthArgs a;
+        a.n = n; a.ld = ld; a.ncol_fixed = j + 1; a.ncol_max = j + 1; a.Md0 = c->W;
+        a.vec0 = c->AW + j * ld; a.nvec = 1; a.partial = c->partial;
+        S.check(orth(ORTH_DOT, a), "TQ");
+        FinishArgs f;
+        f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+        f.T = c->T; f.ldT = SYEV_MAXB; f.cnt = j;
+        S.check(fin(f), "fin TQ");
+      }
+      S.check(set_state(c->st, SET_NB, 0.0, nq, s), "nb");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where);
+      const int save = c->u0;
+      c->u0 = 0;
+      nbh = nq;
+      r = rayleigh_ritz(nq, nq);
+      c->u0 = save;
+      if (r) return r;
+    }
+    c->theta_out.assign(c->rep_h->theta, c->rep_h->theta + std::min(nq, p));
+    c->res_out.assign(c->rep_h->res, c->rep_h->res + std::min(nq, p));
+    // not-yet-locked pairs fill the remainder
+    for (int i = 0; static_cast<int>(c->theta_out.size()) < p && i < static_cast<int>(th.size()); ++i) {
+      c->theta_out.push_back(th[i]);
+      c->res_out.push_back(res[i]);
+    }
+    c->nout = std::min(p, nq + kact);
+  } else {
+    c->theta_out.assign(th.begin(), th.begin() + std::min<size_t>(p, th.size()));
+    c->res_out.assign(res.begin(), res.begin() + std::min<size_t>(p, res.size()));
+    c->nout = static_cast<int>(c->theta_out.size());
+  }
+  c->conv_out.assign(p, 0);
+  int nconv = 0;
+  for (int i = 0; i < static_cast<int>(c->res_out.size()); ++i) {
+    c->conv_out[i] = c->res_out[i] <= thr;
+    nconv += c->conv_out[i];
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, s));
+  HIPCHK(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  stt.solve_ms = ms;
+  stt.nconv = nconv;
+  stt.status = done ? TRPLK_OK : TRPLK_ENOCONV;
+  if (c->o.profile) {
+    for (const Prof& pr : c->prof) {
+      float e = 0.f;
+      if (hipEventElapsedTime(&e, pr.a, pr.b) != hipSuccess) continue;
+      switch (pr.cls) {
+        case PC_SPMV: stt.spmv_ms += e; stt.spmv_launches++; stt.spmv_bytes += pr.bytes; break;
+        case PC_ORTH: stt.orth_ms += e; stt.orth_launches++; stt.orth_bytes += pr.bytes; break;
+        case PC_PREC: stt.prec_ms += e; stt.prec_launches++; stt.prec_bytes += pr.bytes; break;
+        case PC_ROT: stt.rot_ms += e; stt.rot_launches++; stt.rot_bytes += pr.bytes; break;
+        case PC_RR: stt.rr_ms += e; stt.rr_launches++; break;
+      }
+    }
+  }
+  c->solved = true;
+  if (out) *out = stt;
+  return stt.status;
+}
+
+}  // namespace
+
+// ===================================================================== API
+namespace {
+
+int build_jacobi(trplk_ctx* c) {
+  int* bad = nullptr;
+  HIPCHK(c, dalloc(c, &c->dinv, c->n));
+  HIPCHK(c, hipMalloc(&bad, sizeof(int)));
+  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(int), c->s));
+  HIPCHK(c, extract_diag_inv(c->n, c->A.rowptr, c->A.col, c->A.val, c->dinv, bad, c->s));
+  int hb = 0;
+  HIPCHK(c, hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  (void)hipFree(bad);
+  if (hb) return set_err(c, TRPLK_ENOTSPD, "Jacobi: a diagonal entry of A is missing or not positive");
+  return TRPLK_OK;
+}
+
+int compute_norms(trplk_ctx* c) {
+  const int nb = rownorm_blocks(c->n);
+  double* part = nullptr;
+  HIPCHK(c, hipMalloc(&part, sizeof(double) * 2 * nb));
+  HIPCHK(c, row_norms(c->n, c->A.rowptr, c->A.val, part, part + nb, nb, c->s));
+  std::vector<double> h(2 * nb);
+  HIPCHK(c, hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  (void)hipFree(part);
+  double mx = 0.0, fr = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    mx = std::max(mx, h[i]);
+    fr += h[nb + i];
+  }
+  c->normA_inf = mx;
+  c->normA_fro = std::sqrt(fr);
+  return TRPLK_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// G (device CSR owned by the context) -> G^T as CSR, float32 copies for the
+// mixed form, SpMV plans.
+int finish_factor(trplk_ctx* c) {
+  DevCsr& G = c->G;
+  DevCsr& Gt = c->Gt;
+  Gt.n = G.n;
+  Gt.nnz = G.nnz;
+  Gt.owned = true;
+  HIPCHK(c, csr_transpose(G.n, G.nnz, G.rowptr, G.col, G.val, &Gt.rowptr, &Gt.col, &Gt.val, c->s));
+  c->dev_bytes += Gt.nnz * 12 + 4 * (Gt.n + 1);
+  if (c->o.precision == TRPLK_MIXED) {
+    HIPCHK(c, dalloc(c, &G.val32, std::max<int64_t>(G.nnz, 1)));
+    HIPCHK(c, dalloc(c, &Gt.val32, std::max<int64_t>(Gt.nnz, 1)));
+    HIPCHK(c, cast_f32(G.nnz, G.val, G.val32, c->s));
+    HIPCHK(c, cast_f32(Gt.nnz, Gt.val, Gt.val32, c->s));
+  }
+  HIPCHK(c, spmv_plan(G.plan, G.n, G.rowptr, 0, c->s));
+  HIPCHK(c, spmv_plan(Gt.plan, Gt.n, Gt.rowptr, 0, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return TRPLK_OK;
+}
+
+}  // namespace
+
+int trplk_internal_build_fsai(trplk_ctx* c) {
+  free_csr(c->G);
+  free_csr(c->Gt);
+  int bad = 0;
+  int64_t nnz = 0;
+  HIPCHK(c, fsai_build(c->n, c->A.rowptr, c->A.col, c->A.val, c->o.fsai_cap, &c->G.rowptr,
+                       &c->G.col, &c->G.val, &nnz, &bad, c->s));
+  c->G.n = c->n;
+  c->G.nnz = nnz;
+  c->G.owned = true;
+  c->dev_bytes += nnz * 12 + 4 * (c->n + 1);
+  if (bad) return set_err(c, TRPLK_ENOTSPD, "FSAI: missing diagonal or a local matrix is not SPD");
+  return finish_factor(c);
+}
+
+int trplk_internal_set_factor(trplk_ctx* c, const trplk_csr* G, int32_t mem) {
+  if (G->n != c->n) return set_err(c, TRPLK_EINVAL, "factor: dimension mismatch");
+  if (mem == TRPLK_MEM_HOST) {
+    std::string why;
+    int r = validate_host_csr(G, c->n, why);
+    if (r) return set_err(c, r, "factor: " + why);
+    for (int i = 0; i < c->n; ++i) {
+      const int e = G->rowptr[i + 1] - 1;
+      if (e < G->rowptr[i] || G->col[e] != i)
+        return set_err(c, TRPLK_EINVAL, "factor: not lower triangular with a diagonal entry");
+      if (!(G->val[e] > 0.0)) return set_err(c, TRPLK_EINVAL, "factor: diagonal must be positive");
+    }
+  }
+  free_csr(c->G);
+  free_csr(c->Gt);
+  DevCsr& D = c->G;
+  D.n = c->n;
+  D.nnz = G->nnz;
+  D.owned = true;
+  const hipMemcpyKind kd = mem == TRPLK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  HIPCHK(c, dalloc(c, &D.rowptr, D.n + 1));
+  HIPCHK(c, dalloc(c, &D.col, std::max<int64_t>(D.nnz, 1)));
+  HIPCHK(c, dalloc(c, &D.val, std::max<int64_t>(D.nnz, 1)));
+  HIPCHK(c, hipMemcpyAsync(D.rowptr, G->rowptr, sizeof(int) * (D.n + 1), kd, c->s));
+  HIPCHK(c, hipMemcpyAsync(D.col, G->col, sizeof(int) * D.nnz, kd, c->s));
+  HIPCHK(c, hipMemcpyAsync(D.val, G->val, sizeof(double) * D.nnz, kd, c->s));
+  c->prec = TRPLK_PREC_FACTOR;
+  return finish_factor(c);
+}
+
+extern "C" {
+
+void trplk_default_opts(trplk_opts* o) {
+  if (!o) return;
+  *o = trplk_opts{};
+  o->p = 1;
+  o->m = 18;
+  o->k = 8;
+  o->l = 1;
+  o->tol = 1e-8;
+  o->norm = TRPLK_NORM_INF;
+  o->max_cycles = 5000;
+  o->precond = TRPLK_PREC_JACOBI;
+  o->precision = TRPLK_FP64;
+  o->locking = TRPLK_LOCK_AUTO;
+  o->fsai_cap = 0;
+  o->profile = 0;
+  o->mixed_switch = 0.0;
+}
+
+static int check_opts(const trplk_opts* o, int n, std::string& why) {
+  if (o->p < 1) { why = "p must be >= 1"; return TRPLK_EINVAL; }
+  if (o->k < 1) { why = "k must be >= 1"; return TRPLK_EINVAL; }
+  if (o->l < 0) { why = "l must be >= 0"; return TRPLK_EINVAL; }
+  if (o->m > SYEV_MAXB) { why = "m must be <= 64"; return TRPLK_EINVAL; }
+  if (!(o->k + o->l + 1 <= o->m && o->m <= n)) { why = "need k + l + 1 <= m <= n"; return TRPLK_EINVAL; }
+  const bool hard = (o->locking == TRPLK_LOCK_HARD) || (o->locking == TRPLK_LOCK_AUTO && o->p > o->k);
+  if (!hard && o->p > o->k) { why = "soft locking needs p <= k"; return TRPLK_EINVAL; }
+  if (hard && (o->p + o->m > n || o->p > SYEV_MAXB || o->p + o->m > ORTH_MAXCOL)) {
+    why = "hard locking needs p + m <= min(n, 128) and p <= 64";
+    return TRPLK_EINVAL;
+  }
+  if (!(o->tol > 0.0)) { why = "tol must be > 0"; return TRPLK_EINVAL; }
+  if (o->max_cycles < 1) { why = "max_cycles must be >= 1"; return TRPLK_EINVAL; }
+  if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
+  if (o->precision != TRPLK_FP64 && o->precision != TRPLK_MIXED) { why = "bad precision"; return TRPLK_EINVAL; }
+  if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
+  return TRPLK_OK;
+}
+
+int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const trplk_opts* o,
+                 int32_t mem, void* stream) {
+  if (!out) return set_err(nullptr, TRPLK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!A || !o) return set_err(nullptr, TRPLK_EINVAL, "A or opts is NULL");
+  if (mem != TRPLK_MEM_HOST && mem != TRPLK_MEM_DEVICE) return set_err(nullptr, TRPLK_EINVAL, "bad mem");
+  const int n = A->n;
+  if (n < 1) return set_err(nullptr, TRPLK_EINVAL, "n must be >= 1");
+  std::string why;
+  int r = check_opts(o, n, why);
+  if (r) return set_err(nullptr, r, why);
+  if (mem == TRPLK_MEM_HOST) {
+    if ((r = validate_host_csr(A, n, why))) return set_err(nullptr, r, "A: " + why);
+    if (B && (r = validate_host_csr(B, n, why))) return set_err(nullptr, r, "B: " + why);
+  } else {
+    if (!A->rowptr || !A->col || !A->val) return set_err(nullptr, TRPLK_EINVAL, "A: null array");
+    if (A->nnz < 0 || A->nnz >= (int64_t(1) << 31)) return set_err(nullptr, TRPLK_EINVAL, "A: nnz out of range");
+    if (B && (!B->rowptr || !B->col || !B->val || B->n != n)) return set_err(nullptr, TRPLK_EINVAL, "B: bad");
+  }
+  trplk_ctx* c = new trplk_ctx();
+  c->s = static_cast<hipStream_t>(stream);
+  c->o = *o;
+  c->n = n;
+  c->hasB = B != nullptr;
+  c->prec = o->precond;
+  hipEvent_t e0, e1;
+  bool timing = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  auto fail = [&](int code) {
+    std::string msg = c->err;
+    trplk_destroy(c);
+    return set_err(nullptr, code, msg);
+  };
+  const bool mixed = o->precision == TRPLK_MIXED;
+  if ((r = upload_csr(c, c->A, A, mem, mixed))) return fail(r);
+  if (B && (r = upload_csr(c, c->B, B, mem, false))) return fail(r);
+  if ((r = compute_norms(c))) return fail(r);
+  if (timing) (void)hipEventRecord(e0, c->s);
+  if (c->prec == TRPLK_PREC_JACOBI) {
+    if ((r = build_jacobi(c))) return fail(r);
+  } else if (c->prec == TRPLK_PREC_FSAI) {
+    if ((r = trplk_internal_build_fsai(c))) return fail(r);
+  } else if (c->prec == TRPLK_PREC_FACTOR) {
+    // installed later by trplk_set_factor; Jacobi-equivalent until then
+    c->err = "";
+  }
+  if (timing) {
+    (void)hipEventRecord(e1, c->s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c->stats.setup_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  if ((r = ensure_workspace(c))) return fail(r);
+  if (hipStreamSynchronize(c->s) != hipSuccess) return fail(set_err(c, TRPLK_EDEVICE, "sync"));
+  *out = c;
+  return TRPLK_OK;
+}
+
+int trplk_set_factor(trplk_ctx* c, const trplk_csr* G, int32_t mem) {
+  if (!c || !G) return set_err(c, TRPLK_EINVAL, "null argument");
+  return trplk_internal_set_factor(c, G, mem);
+}
+
+int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
+  if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
+  if (!x0) return set_err(c, TRPLK_EINVAL, "x0 is NULL");
+  if (c->prec >= TRPLK_PREC_FSAI && !c->G.val) return set_err(c, TRPLK_EINVAL, "no factor installed");
+  if (mem == TRPLK_MEM_HOST) {
+    for (int64_t i = 0; i < static_cast<int64_t>(c->n) * c->o.k; ++i)
+      if (!std::isfinite(x0[i])) return set_err(c, TRPLK_ENUMERIC, "non-finite start block");
+  }
+  int r = ensure_workspace(c);
+  if (r) return r;
+  Solver S{c, c->n, c->ld, c->s};
+  c->stats.setup_ms = c->stats.setup_ms;
+  const double setup = c->stats.setup_ms;
+  r = S.run(x0, mem, st);
+  c->stats.setup_ms = setup;
+  if (st) st->setup_ms = setup;
+  return r;
+}
+
+int trplk_get_eigpairs(trplk_ctx* c, double* evals, double* evecs, double* resid, int32_t* conv,
+                       int32_t mem) {
+  if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
+  if (!c->solved) return set_err(c, TRPLK_EINVAL, "no solve has completed");
+  const int p = c->o.p;
+  const int nout = c->nout;
+  const int n = c->n;
+  const int64_t ld = c->ld;
+  const hipMemcpyKind kd = mem == TRPLK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  const hipMemcpyKind kh = mem == TRPLK_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+  std::vector<double> ev(p, NAN);
+  for (int i = 0; i < std::min<int>(p, c->theta_out.size()); ++i) ev[i] = c->theta_out[i];
+  if (evals) HIPCHK(c, hipMemcpyAsync(evals, ev.data(), sizeof(double) * p, kh, c->s));
+  if (conv) {
+    std::vector<int32_t> cv(p, 0);
+    for (int i = 0; i < std::min<int>(p, c->conv_out.size()); ++i) cv[i] = c->conv_out[i];
+    HIPCHK(c, hipMemcpyAsync(conv, cv.data(), sizeof(int32_t) * p, kh, c->s));
+    HIPCHK(c, hipStreamSynchronize(c->s));
+  }
+  if (evecs) {
+    HIPCHK(c, hipMemcpy2DAsync(evecs, sizeof(double) * n, c->W, sizeof(double) * ld, sizeof(double) * n,
+                               nout, kd, c->s));
+  }
+  if (resid) {
+    // true residuals ||A x - theta B x|| / ||x|| with fresh float64 products
+    std::vector<double> rr(p, NAN);
+    double* d_th = nullptr;
+    HIPCHK(c, hipMalloc(&d_th, sizeof(double) * std::max(nout, 1)));
+    HIPCHK(c, hipMemcpyAsync(d_th, ev.data(), sizeof(double) * nout, hipMemcpyHostToDevice, c->s));
+    std::vector<double> h(2);
+    for (int i = 0; i < nout; ++i) {
+      const double* x = c->W + i * ld;
+      if (c->hasB) {
+        SpmvArgs b;
+        b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = x;
+        b.mode = SPMV_STORE; b.y = c->tmpB;
+        HIPCHK(c, spmv_f64(c->B.plan, b, c->s));
+      }
+      SpmvArgs a;
+      a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = x; a.xd = x;
+      a.mode = SPMV_RESID; a.y = c->ytmp; a.bx = c->hasB ? c->tmpB : nullptr;
+      a.partial = c->partial; a.theta = d_th; a.theta_idx = i;
+      HIPCHK(c, spmv_f64(c->A.plan, a, c->s));
+      FinishArgs f;
+      f.mode = FIN_SUM; f.partial = c->partial; f.nblk = spmv_partial_blocks(c->A.plan); f.stride = 1;
+      f.out = c->resout; f.cnt = 1;
+      HIPCHK(c, finish(f, c->s));
+      OrthArgs o;
+      o.n = n; o.ld = ld; o.ncol_fixed = 1; o.ncol_max = 1; o.Md0 = x; o.vec0 = x; o.nvec = 1;
+      o.partial = c->partial;
+      HIPCHK(c, orth_pass(ORTH_DOT, o, c->orth_nblk, c->s));
+      FinishArgs g;
+      g.mode = FIN_SUM; g.partial = c->partial; g.nblk = c->orth_nblk; g.stride = orth_stride();
+      g.out = c->resout + 1; g.cnt = 1;
+      HIPCHK(c, finish(g, c->s));
+      HIPCHK(c, hipMemcpyAsync(h.data(), c->resout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(c, hipStreamSynchronize(c->s));
+      rr[i] = std::sqrt(h[0]) / std::sqrt(h[1]);
+    }
+    (void)hipFree(d_th);
+    HIPCHK(c, hipMemcpyAsync(resid, rr.data(), sizeof(double) * p, kh, c->s));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return TRPLK_OK;
+}
+
+int64_t trplk_device_bytes(const trplk_ctx* c) { return c ? c->dev_bytes : 0; }
+
+const char* trplk_last_error(const trplk_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+void trplk_destroy(trplk_ctx* c) {
+  if (!c) return;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  free_csr(c->A);
+  free_csr(c->B);
+  free_csr(c->G);
+  free_csr(c->Gt);
+  void* ptrs[] = {c->dinv, c->W, c->AW, c->BW, c->w, c->wtmp, c->tmpB, c->vtmp, c->ytmp, c->v32,
+                  c->y32, c->wtmp32, c->Xprev, c->T, c->theta, c->Y, c->hbuf, c->partial,
+                  c->resout, c->st, c->rep_d};
+  for (void* p : ptrs) dfree(p);
+  if (c->rep_h) (void)hipHostFree(c->rep_h);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------- kernel-level entries
+namespace {
+
+struct Scratch {
+  double* buf = nullptr;
+  size_t bytes = 0;
+};
+Scratch g_scratch;
+
+double* scratch(size_t bytes) {
+  if (bytes > g_scratch.bytes) {
+    if (g_scratch.buf) (void)hipFree(g_scratch.buf);
+    g_scratch.buf = nullptr;
+    if (hipMalloc(&g_scratch.buf, bytes) != hipSuccess) {
+      g_scratch.bytes = 0;
+      return nullptr;
+    }
+    g_scratch.bytes = bytes;
+  }
+  return g_scratch.buf;
+}
+
+int kernel_err(hipError_t e) {
+  if (e == hipSuccess) return TRPLK_OK;
+  g_create_err = hipGetErrorString(e);
+  return TRPLK_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int trplk_spmv(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+               const double* x, double* y, int32_t lanes, void* stream) {
+  if (n < 0 || (n > 0 && (!rowptr || !col || !val || !x || !y))) return TRPLK_EINVAL;
+  if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SpmvPlan plan;
+  hipError_t e = spmv_plan(plan, n, rowptr, lanes, s);
+  if (e != hipSuccess) return kernel_err(e);
+  SpmvArgs a;
+  a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = x; a.y = y; a.mode = SPMV_STORE;
+  e = spmv_f64(plan, a, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  spmv_plan_free(plan);
+  return kernel_err(e);
+}
+
+int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const float* val,
+                   const float* x, float* y, int32_t lanes, void* stream) {
+  if (n < 0 || (n > 0 && (!rowptr || !col || !val || !x || !y))) return TRPLK_EINVAL;
+  if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SpmvPlan plan;
+  hipError_t e = spmv_plan(plan, n, rowptr, lanes, s);
+  if (e != hipSuccess) return kernel_err(e);
+  SpmvArgs a;
+  a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = x; a.y = y; a.mode = SPMV_STORE;
+  e = spmv_f32(plan, a, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  spmv_plan_free(plan);
+  return kernel_err(e);
+}
+
+int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v, double* h,
+                 void* stream) {
+  if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !v || !h) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nblk = orth_blocks(n);
+  double* part = scratch(sizeof(double) * nblk * orth_stride());
+  if (!part) return TRPLK_ENOMEM;
+  OrthArgs a;
+  a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Md0 = U; a.vec0 = v; a.nvec = 1;
+  a.partial = part;
+  hipError_t e = orth_pass(ORTH_DOT, a, nblk, s);
+  FinishArgs f;
+  f.mode = FIN_SUM; f.partial = part; f.nblk = nblk; f.stride = orth_stride(); f.out = h; f.cnt = c;
+  if (e == hipSuccess) e = finish(f, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* h,
+                         double* w, double* h2, void* stream) {
+  if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !h || !w || !h2) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nblk = orth_blocks(n);
+  double* part = scratch(sizeof(double) * nblk * orth_stride());
+  if (!part) return TRPLK_ENOMEM;
+  OrthArgs a;
+  a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Mu = U; a.Md1 = U; a.h = h; a.w = w;
+  a.partial = part;
+  hipError_t e = orth_pass(ORTH_UPD_DOT, a, nblk, s);
+  FinishArgs f;
+  f.mode = FIN_SUM; f.partial = part; f.nblk = nblk; f.stride = orth_stride(); f.out = h2; f.cnt = c;
+  if (e == hipSuccess) e = finish(f, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_syev(int32_t b, const double* T, double* theta, double* Y, void* stream) {
+  if (b < 1 || b > SYEV_MAXB || !T || !theta || !Y) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = syev(T, b, b, nullptr, 0, theta, Y, b, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_rotate(int32_t n, int32_t b, int32_t k, double* U, int64_t ldu, const double* Y,
+                 int32_t ldy, void* stream) {
+  if (n < 1 || b < 1 || b > SYEV_MAXB || k < 1 || k > b || ldu < n || ldy < b || !U || !Y)
+    return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RotArgs a;
+  a.n = n; a.kout = k; a.b_fixed = b; a.Y = Y; a.ldY = ldy; a.U = U; a.ld = ldu;
+  hipError_t e = rotate(a, rot_blocks(n), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+}  // extern "C"

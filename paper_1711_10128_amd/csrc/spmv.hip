@@ -1,0 +1,256 @@
+// CSR sparse matrix-vector products (the "MV" of the paper, eq. (3.1)).
+//
+// Two kernels share one epilogue:
+//  * row-split: a group of L lanes of a wavefront owns one row (L = 2..64,
+//    picked from the mean row length), loads its entries coalesced and
+//    reduces with cross-lane shuffles; rows of a wavefront are consecutive, so
+//    the value and index streams of the wavefront are contiguous;
+//  * workgroup-per-row for rows longer than LONG_ROW entries (power-law hubs),
+//    listed once at plan time, so a hub row does not stall a wavefront.
+// The epilogue fuses the work that touches the row's own entries of the
+// dense vectors: scaling by 1/beta, writing the new basis column and its
+// products, and forming the next inner direction M (A g - rho B g) for the
+// identity and Jacobi preconditioners.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace trplk {
+
+namespace {
+
+constexpr int SPMV_THREADS = 256;
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) {
+  return static_cast<double>(v);
+}
+
+struct EpiCtx {
+  double s;      // scale
+  double rho;
+  int nb;
+};
+
+template <typename OT>
+__device__ __forceinline__ void epilogue(const SpmvArgs& a, const EpiCtx& e, int row, double sum,
+                                         double& acc) {
+  const double yv = e.s * sum;
+  switch (a.mode) {
+    case SPMV_STORE:
+      static_cast<OT*>(a.y)[row] = static_cast<OT>(yv);
+      break;
+    case SPMV_APPEND: {
+      const int64_t c = static_cast<int64_t>(a.col0 + e.nb) * a.ld;
+      const double g = e.s * a.xd[row];
+      a.U[c + row] = g;
+      a.AU[c + row] = yv;
+      const double bg = a.bx ? e.s * a.bx[row] : g;
+      if (a.BU) a.BU[c + row] = bg;
+      if (a.next != NEXT_NONE) {
+        const double v = yv - e.rho * bg;
+        if (a.next == NEXT_IDENT) {
+          a.wout[row] = v;
+        } else if (a.next == NEXT_JACOBI) {
+          a.wout[row] = a.dinv[row] * v;
+        } else {
+          if (a.vout32) a.vout32[row] = static_cast<float>(v);
+          else a.vout[row] = v;
+        }
+      }
+      break;
+    }
+    case SPMV_DOT:
+      static_cast<OT*>(a.y)[row] = static_cast<OT>(yv);
+      acc += yv * a.xd[row];
+      break;
+    case SPMV_RESID: {
+      const double bx = a.bx ? a.bx[row] : a.xd[row];
+      const double r = yv - a.theta[a.theta_idx] * bx;
+      static_cast<OT*>(a.y)[row] = static_cast<OT>(r);
+      acc += r * r;
+      break;
+    }
+  }
+}
+
+__device__ __forceinline__ void block_partial(double acc, double* partial, int slot) {
+  __shared__ double red[SPMV_THREADS / WAVE];
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
+    partial[slot] = t;
+  }
+}
+
+template <int L, typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rows(const SpmvArgs a) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  const int* __restrict__ rowptr = a.rowptr;
+  const int* __restrict__ col = a.col;
+  const VT* __restrict__ val = static_cast<const VT*>(a.val);
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  constexpr int RPB = SPMV_THREADS / L;
+  const int li = threadIdx.x & (L - 1);
+  double acc = 0.0;
+  for (int row = blockIdx.x * RPB + threadIdx.x / L; row < a.n; row += gridDim.x * RPB) {
+    const int beg = rowptr[row];
+    const int end = rowptr[row + 1];
+    if (end - beg > LONG_ROW) continue;  // the workgroup-per-row kernel owns it
+    AT sum = 0;
+    for (int j = beg + li; j < end; j += L) sum += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+    double s;
+    if constexpr (sizeof(AT) == 4) s = static_cast<double>(group_sumf<L>(sum));
+    else s = group_sum<L>(sum);
+    if (li == 0) epilogue<OT>(a, e, row, s, acc);
+  }
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+}
+
+template <typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
+                                                            int slot0) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  const int row = long_rows[blockIdx.x];
+  const VT* __restrict__ val = static_cast<const VT*>(a.val);
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  const int beg = a.rowptr[row];
+  const int end = a.rowptr[row + 1];
+  AT sum = 0;
+  for (int j = beg + threadIdx.x; j < end; j += SPMV_THREADS)
+    sum += static_cast<AT>(val[j]) * static_cast<AT>(x[a.col[j]]);
+  __shared__ double red[SPMV_THREADS / WAVE];
+  double s = wave_sum(static_cast<double>(sum));
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
+    double acc = 0.0;
+    epilogue<OT>(a, e, row, t, acc);
+    if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) a.partial[slot0 + blockIdx.x] = acc;
+  }
+}
+
+__global__ void k_find_long(int n, const int* rowptr, int* flags) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    flags[i] = (rowptr[i + 1] - rowptr[i]) > LONG_ROW;
+}
+
+int short_blocks(int n, int lanes) {
+  const int rpb = SPMV_THREADS / lanes;
+  const int want = (n + rpb - 1) / rpb;
+  return std::max(1, std::min(want, 8192));
+}
+
+template <typename VT, typename XT, typename AT, typename OT>
+hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const dim3 blk(SPMV_THREADS);
+  const dim3 grd(p.nblk_short);
+  switch (p.lanes) {
+    case 1: hipLaunchKernelGGL((k_spmv_rows<1, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_spmv_rows<2, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_spmv_rows<4, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_spmv_rows<8, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_spmv_rows<16, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_spmv_rows<32, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_spmv_rows<64, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p.nlong > 0) {
+    hipLaunchKernelGGL((k_spmv_long<VT, XT, AT, OT>), dim3(p.nlong), blk, 0, s, a, p.long_rows,
+                       p.nblk_short);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace
+
+int pick_lanes(double mean_len) {
+  int L = 2;
+  while (L < 64 && L < mean_len) L <<= 1;
+  return L;
+}
+
+hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hipStream_t s) {
+  plan.n = n;
+  int nnz = 0;
+  hipError_t e = hipSuccess;
+  if (n > 0) {
+    e = hipMemcpyAsync(&nnz, rowptr_dev + n, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+  }
+  plan.lanes = lanes > 0 ? lanes : pick_lanes(n ? double(nnz) / n : 1.0);
+  plan.nblk_short = short_blocks(std::max(n, 1), plan.lanes);
+  plan.nlong = 0;
+  plan.long_rows = nullptr;
+  if (n == 0) return hipSuccess;
+  int* flags = nullptr;
+  e = hipMalloc(&flags, sizeof(int) * n);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_find_long, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n,
+                     rowptr_dev, flags);
+  std::vector<int> h(n);
+  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(flags);
+  if (e != hipSuccess) return e;
+  std::vector<int> rows;
+  for (int i = 0; i < n; ++i)
+    if (h[i]) rows.push_back(i);
+  plan.nlong = static_cast<int>(rows.size());
+  if (plan.nlong) {
+    e = hipMalloc(&plan.long_rows, sizeof(int) * rows.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(plan.long_rows, rows.data(), sizeof(int) * rows.size(),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  return e;
+}
+
+void spmv_plan_free(SpmvPlan& plan) {
+  if (plan.long_rows) hipFree(plan.long_rows);
+  plan.long_rows = nullptr;
+  plan.nlong = 0;
+}
+
+int spmv_partial_blocks(const SpmvPlan& plan) { return plan.nblk_short + plan.nlong; }
+
+hipError_t spmv_f64(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s) {
+  return launch<double, double, double, double>(plan, a, s);
+}
+
+// float32 values and gather vector with float32 accumulation; the epilogue
+// writes float32 (or float64 when out_f64) for SPMV_STORE / SPMV_DOT and
+// float64 columns for SPMV_APPEND.
+hipError_t spmv_f32(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s) {
+  if (a.out_f64) return launch<float, float, float, double>(plan, a, s);
+  return launch<float, float, float, float>(plan, a, s);
+}
+
+}  // namespace trplk

@@ -1,0 +1,41 @@
+"""The C ABI library loads on a machine without a GPU and exports every
+function include/trplk.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "trplk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(trplk_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("trplk_create", "trplk_solve", "trplk_get_eigpairs", "trplk_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1711_10128_amd as T
+    L = T.lib()
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(T.EXPORTS) <= set(declared())
+
+
+def test_default_opts_and_last_error_without_gpu():
+    import paper_1711_10128_amd as T
+    L = T.lib()
+    o = T._Opts()
+    L.trplk_default_opts(ctypes.byref(o))
+    assert (o.p, o.m, o.k, o.l, o.tol, o.max_cycles) == (1, 18, 8, 1, 1e-8, 5000)
+    # argument validation happens before any device call
+    ctx = ctypes.c_void_p()
+    code = L.trplk_create(ctypes.byref(ctx), None, None, ctypes.byref(o), 0, None)
+    assert code == -1 and not ctx.value
+    assert b"NULL" in L.trplk_last_error(None)

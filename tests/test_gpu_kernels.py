@@ -1,0 +1,139 @@
+"""Kernel-level parity of the HIP building blocks, through the C ABI."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workloads import lap2d, lap3d, fem3d, powerlaw, aniso3d  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_10128_amd as T
+    T.lib()
+    return T
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+MATS = {
+    "lap2d": lambda: lap2d(37),
+    "lap3d": lambda: lap3d(13, 0.05),
+    "fem3d_A": lambda: fem3d(9, 0.5)[0],
+    "fem3d_B": lambda: fem3d(9, 0.5)[1],
+    "aniso": lambda: aniso3d(11, 1.0),
+    # hub rows longer than 256 entries exercise the workgroup-per-row kernel
+    "powerlaw_hubs": lambda: powerlaw(6000, avg_deg=24.0, max_deg=900.0),
+}
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("lanes", [0, 4, 64])
+def test_spmv_f64_parity(T, name, lanes):
+    A = MATS[name]()
+    print(f"spmv f64 {name} n={A.n} nnz={A.nnz} lanes={lanes}", flush=True)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(A.n)
+    ref = A.to_scipy() @ x
+    y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    T.spmv(_dev(A.rowptr), _dev(A.col), _dev(A.val), _dev(x), y, lanes)
+    got = y.cpu().numpy()
+    # each row sum is a different rounding order of the same terms
+    bound = 4 * 2.2e-16 * (abs(A.to_scipy()) @ np.abs(x)) * np.diff(A.rowptr).max()
+    assert np.all(np.abs(got - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["lap3d", "powerlaw_hubs", "fem3d_A"])
+def test_spmv_f32_against_f64(T, name):
+    A = MATS[name]()
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(A.n).astype(np.float32)
+    ref = A.to_scipy().astype(np.float64) @ x.astype(np.float64)
+    y = torch.zeros(A.n, dtype=torch.float32, device="cuda")
+    T.spmv(_dev(A.rowptr), _dev(A.col), _dev(A.val.astype(np.float32)), _dev(x), y, 0)
+    got = y.cpu().numpy().astype(np.float64)
+    scale = abs(A.to_scipy()) @ np.abs(x.astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 1e-6 * scale * np.diff(A.rowptr).max())
+
+
+@pytest.mark.parametrize("n", [1, 63, 257, 1000, 70001])
+@pytest.mark.parametrize("c", [1, 7, 20, 64, 128])
+def test_gemv_t_and_fused_update(T, n, c):
+    print(f"gemv n={n} c={c}", flush=True)
+    rng = np.random.default_rng(n + c)
+    U = rng.standard_normal((c, n))          # row i of U is column i of the basis
+    v = rng.standard_normal(n)
+    h = torch.zeros(c, dtype=torch.float64, device="cuda")
+    T.gemv_t(_dev(U), _dev(v), h)
+    ref = U @ v
+    tol = 8 * 2.2e-16 * (np.abs(U) @ np.abs(v)) * np.log2(n + 2)
+    assert np.all(np.abs(h.cpu().numpy() - ref) <= tol)
+    hh = rng.standard_normal(c)
+    w = _dev(v.copy())
+    h2 = torch.zeros(c, dtype=torch.float64, device="cuda")
+    T.cgs_update_dot(_dev(U), _dev(hh), w, h2)
+    wref = v - U.T @ hh
+    assert np.allclose(w.cpu().numpy(), wref, rtol=1e-13, atol=1e-13 * np.abs(v).max() * c)
+    h2ref = U @ wref
+    tol2 = 16 * 2.2e-16 * (np.abs(U) @ (np.abs(v) + np.abs(U.T) @ np.abs(hh))) * np.log2(n + 2) * c
+    assert np.all(np.abs(h2.cpu().numpy() - h2ref) <= tol2)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 8, 20, 47, 64])
+def test_syev_parity(T, b):
+    rng = np.random.default_rng(b)
+    M = rng.standard_normal((b, b))
+    S = M + M.T
+    if b >= 8:
+        S[0, 1] = S[1, 0] = 0.0
+        S[2, 2] = S[3, 3]  # an exact tie on the diagonal
+    th = torch.zeros(b, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((b, b), dtype=torch.float64, device="cuda")
+    T.syev(_dev(S.T.copy()), th, Y)
+    w = np.linalg.eigh(S)[0]
+    got = th.cpu().numpy()
+    Yc = Y.cpu().numpy().T  # column-major -> numpy
+    nrm = np.linalg.norm(S, 2)
+    assert np.all(np.diff(got) >= 0)
+    assert np.max(np.abs(got - w)) <= 20 * b * 2.2e-16 * nrm
+    assert np.max(np.abs(Yc.T @ Yc - np.eye(b))) <= 20 * b * 2.2e-16
+    assert np.max(np.abs(S @ Yc - Yc * got[None, :])) <= 20 * b * 2.2e-16 * nrm
+
+
+def test_syev_clustered_and_diagonal(T):
+    """Already-diagonal input and a tight cluster: eigenvalues exact to rounding."""
+    d = np.array([3.0, -1.0, 2.0, 2.0 + 1e-13, 0.5])
+    S = np.diag(d)
+    th = torch.zeros(5, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((5, 5), dtype=torch.float64, device="cuda")
+    T.syev(_dev(S.T.copy()), th, Y)
+    assert np.array_equal(th.cpu().numpy(), np.sort(d))
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 123457])
+@pytest.mark.parametrize("b,k", [(4, 1), (8, 8), (20, 8), (40, 20), (48, 24), (64, 32), (64, 64)])
+def test_rotate_mfma_parity(T, n, b, k):
+    """X = U Y(:, :k) in place on the FP64 matrix cores (checks the lane layout
+    of V_MFMA_F64_16X16X4F64 against numpy)."""
+    if k > b:
+        pytest.skip()
+    print(f"rotate n={n} b={b} k={k}", flush=True)
+    rng = np.random.default_rng(n * 7 + b)
+    U = rng.standard_normal((b, n))
+    Y = rng.standard_normal((b, b))
+    Ud = _dev(U.copy())
+    T.rotate(Ud, _dev(Y.T.copy()), k)
+    got = Ud.cpu().numpy()
+    ref = (U.T @ Y[:, :k]).T
+    tol = 4 * b * 2.2e-16 * (np.abs(U.T) @ np.abs(Y[:, :k])).T
+    assert np.all(np.abs(got[:k] - ref) <= tol)
+    # columns beyond k untouched
+    assert np.array_equal(got[k:], U[k:])

@@ -1,0 +1,173 @@
+"""Whole-solve parity of the HIP TRPL+K against the FP64 CPU oracle.
+
+Both sides get byte-identical inputs (the seeded workload generators); the
+eigenvalues must agree to 1e-10 relative (or the FP64 floor 16 eps ||A||),
+the GPU residuals (recomputed with fresh products) must meet tol * ||A||,
+and the cycle counts must agree up to rounding-order effects.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import precond as PC  # noqa: E402
+from oracle import trplk as O  # noqa: E402
+from workloads import make, start_block  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_10128_amd as T
+    T.lib()
+    return T
+
+
+def _oracle(P, prec, X0, **kw):
+    A = P.A.to_scipy()
+    B = None if P.B is None else P.B.to_scipy()
+    if prec == "jacobi":
+        M = O.jacobi(A)
+    elif prec == "fsai":
+        M = O.factorized(PC.fsai(A, kw.pop("cap", None)))
+    else:
+        M = None
+    return O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=M, **kw)
+
+
+def _gpu(T, P, prec, X0, **kw):
+    s = T.Solver(P.A, P.B, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=prec, **kw)
+    st = s.solve(X0)
+    ev, X, res, conv = s.eigpairs()
+    s.close()
+    return st, ev, X, res, conv
+
+
+def _compare(P, st, ev, X, res, conv, ref, cycle_slack=2, eig_rel=1e-10):
+    normA = ref.normA
+    floor = 16 * 2.2e-16 * normA
+    scale = np.abs(ref.theta)
+    if P.B is not None:
+        floor = 16 * 2.2e-16 * np.max(np.abs(ref.theta))
+    print(f"  gpu cycles={st['cycles']} mv={st['matvecs']}  oracle cycles={ref.cycles} "
+          f"mv={ref.matvecs}  max|dtheta|/theta={np.max(np.abs(ev - ref.theta) / scale):.2e} "
+          f"max res/normA={np.max(res) / normA:.2e}", flush=True)
+    assert conv.all()
+    assert np.all(np.abs(ev - ref.theta) <= np.maximum(eig_rel * scale, floor))
+    assert np.all(res <= P.tol * normA * 1.001)
+    assert abs(st["cycles"] - ref.cycles) <= cycle_slack
+    # B-orthonormal eigenvectors
+    Bx = X if P.B is None else P.B.to_scipy() @ X
+    assert np.max(np.abs(X.T @ Bx - np.eye(X.shape[1]))) < 1e-10
+
+
+CASES = [
+    ("lap2d", dict(N=24), "jacobi", {}),
+    ("lap2d", dict(N=64), "jacobi", {}),          # the 64 x 64 workload itself
+    ("lap2d", dict(N=30, p=5, m=18, k=8), "none", {}),
+    ("lap3d", dict(N=16, vmax=0.05, p=10, m=40, k=20), "jacobi", {}),
+    ("lap3d", dict(N=14, vmax=0.05, p=6, m=24, k=12), "fsai", {}),
+    ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "jacobi", {}),
+    ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "fsai", {}),
+    ("powerlaw", dict(n=3000, p=8, m=24, k=12), "jacobi", {}),
+    ("aniso3d", dict(N=10, sigma=1.0, p=12, m=16, k=8, tol=1e-9), "jacobi", {}),  # hard locking
+]
+
+
+@pytest.mark.parametrize("name,kw,prec,extra", CASES,
+                         ids=[f"{c[0]}-{c[2]}-{i}" for i, c in enumerate(CASES)])
+def test_solve_parity(T, name, kw, prec, extra):
+    P = make(name, "small", **kw)
+    print(f"solve {name} {kw} prec={prec} n={P.A.n}", flush=True)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, prec, X0)
+    st, ev, X, res, conv = _gpu(T, P, prec, X0, **extra)
+    # matvec law on the standard problem: k + (m - k) per cycle (Sec. 5)
+    if P.B is None and P.p <= P.k:
+        assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
+    _compare(P, st, ev, X, res, conv, ref)
+
+
+def test_mixed_precision_matches_fp64_oracle(T):
+    """Float32 SpMV / preconditioner with float64 projection: the final pairs
+    still meet the float64 tolerance and match the float64 oracle."""
+    P = make("lap3d", "small", N=16, vmax=0.05, p=8, m=32, k=16)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, "fsai", X0)
+    st, ev, X, res, conv = _gpu(T, P, "fsai", X0, precision="mixed")
+    print(f"  mixed: fp32 cycles {st['fp32_cycles']} of {st['cycles']}", flush=True)
+    _compare(P, st, ev, X, res, conv, ref, cycle_slack=10)
+    assert st["fp32_cycles"] >= 1
+
+
+def test_fsai_factor_matches_oracle(T):
+    """The factor built on the GPU equals the oracle's FSAI factor: the same
+    solve with the oracle's G installed explicitly gives identical results."""
+    P = make("fem3d", "small", Ne=8, sigma=0.5, p=4, m=16, k=8)
+    A = P.A.to_scipy()
+    G = PC.fsai(A)
+    X0 = start_block(P.A.n, P.k, 12)
+    from workloads.generators import CSR
+    s1 = T.Solver(P.A, P.B, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond="fsai")
+    st1 = s1.solve(X0)
+    ev1 = s1.eigpairs()[0]
+    s2 = T.Solver(P.A, P.B, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond="jacobi")
+    s2.set_factor(CSR.from_scipy(G))
+    st2 = s2.solve(X0)
+    ev2 = s2.eigpairs()[0]
+    assert st1["cycles"] == st2["cycles"]
+    assert np.allclose(ev1, ev2, rtol=1e-12)
+
+
+def test_deterministic(T):
+    P = make("lap3d", "small", N=12, vmax=0.05, p=4, m=16, k=8)
+    X0 = start_block(P.A.n, P.k, 12)
+    a = _gpu(T, P, "jacobi", X0)
+    b = _gpu(T, P, "jacobi", X0)
+    assert a[0]["cycles"] == b[0]["cycles"]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_device_resident_inputs(T):
+    """A, X0 handed over as device pointers (torch tensors): same answer."""
+    P = make("lap2d", "small", N=24)
+    X0 = start_block(P.A.n, P.k, 12)
+    Ad = T.DeviceCSR(P.A)
+    Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
+    s = T.Solver(Ad, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol)
+    st = s.solve(Xd)
+    ev = s.eigpairs()[0]
+    _, ev2, _, _, _ = _gpu(T, P, "jacobi", X0)
+    assert np.array_equal(ev, ev2)
+
+
+def test_error_paths(T):
+    P = make("lap2d", "small", N=10)
+    with pytest.raises(T.TrplkError) as e:
+        T.Solver(P.A, None, p=9, m=12, k=8, locking="soft")
+    assert e.value.code == -1
+    with pytest.raises(T.TrplkError):
+        T.Solver(P.A, None, p=2, m=9, k=8, l=1)          # k + l + 1 > m
+    s = T.Solver(P.A, None, p=2, m=12, k=4)
+    X0 = start_block(P.A.n, 4, 1)
+    X0[3, 1] = np.nan
+    with pytest.raises(T.TrplkError) as e:
+        s.solve(X0)
+    assert e.value.code == -4
+    X0 = start_block(P.A.n, 4, 1)
+    X0[:, 2] = X0[:, 1]                                  # rank deficient
+    with pytest.raises(T.TrplkError):
+        s.solve(X0)
+    s.close()
+
+
+def test_max_cycles_partial_results(T):
+    P = make("lap2d", "small", N=40, p=5, m=18, k=8)
+    X0 = start_block(P.A.n, P.k, 12)
+    s = T.Solver(P.A, None, p=5, m=18, k=8, max_cycles=3, precond="none")
+    st = s.solve(X0)
+    assert st["status"] == 1 and st["cycles"] == 3
+    ev, X, res, conv = s.eigpairs()
+    assert not conv.all() and np.all(np.isfinite(ev))
