@@ -54,7 +54,7 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   for (int t = 0; t < NTILE; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int kc = 16 * t + 4 * lg + r;
+      const int kc = 16 * t + lg + 4 * r;
       th[t][r] = (a.theta && kc < kk) ? a.theta[kc] : 0.0;
       rs[t][r] = 0.0;
       xs[t][r] = 0.0;
@@ -84,12 +84,13 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
             D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yf[t][ks], bv, D[t], 0, 0, 0);
         }
       }
-      // lane holds X(row = rb*16 + li, col = 16 t + 4 lg + r)
+      // lane holds X(row = rb*16 + li, col = 16 t + lg + 4 r): the F64 16x16x4
+      // result places output row lg + 4 r of the tile in register r
 #pragma unroll
       for (int t = 0; t < NTILE; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int kc = 16 * t + 4 * lg + r;
+          const int kc = 16 * t + lg + 4 * r;
           if (ok && kc < kk) M[kc * ld + row] = D[t][r];
         }
         if (mi == 0) DX[t] = D[t];
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
           v += __shfl_xor(v, off, WAVE);
           w += __shfl_xor(w, off, WAVE);
         }
-        const int kc = 16 * t + 4 * lg + r;
+        const int kc = 16 * t + lg + 4 * r;
         if (li == 0 && kc < 64) {
           sr[wv][0][kc] = v;
           sr[wv][1][kc] = w;
