@@ -158,7 +158,8 @@ struct OrthArgs {
 };
 
 constexpr int ORTH_MAXCOL = 128;
-int orth_blocks(int n);
+int orth_blocks(int n, int mode);   // grid of a pass (its partial count)
+int orth_blocks_max(int n);
 int orth_stride();  // partial stride per block (doubles)
 hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s);
 
@@ -239,6 +240,7 @@ struct RotArgs {
   int n = 0;
   int kout = 0;                // requested output columns (min with b)
   int b_fixed = 0;             // basis columns when state is null
+  int b_max = 0;               // upper bound of the basis columns (sizes the K loop)
   const DevState* state = nullptr;
   const double* Y = nullptr;   // ldY
   int ldY = 0;

@@ -23,12 +23,12 @@ namespace {
 
 constexpr int OT_THREADS = 512;
 constexpr int NWV = OT_THREADS / WAVE;  // 8
-constexpr int RPL = 4;                  // rows per lane per slab
-constexpr int SLAB = WAVE * RPL;        // 256 rows
 constexpr int STRIDE = 2 * ORTH_MAXCOL; // partial doubles per block
+int g_orth_rpl = 0;                     // rows per lane per slab (0: by pass)
 
-template <int CPW, int MODE, int NV, bool SAME>
+template <int CPW, int MODE, int NV, bool SAME, int RPL>
 __global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
+  constexpr int SLAB = WAVE * RPL;
   if (a.state && a.state->skip) return;
   const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -170,38 +170,79 @@ __global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
   }
 }
 
-template <int CPW>
-hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+template <int CPW, int RPL>
+hipError_t launch_rpl(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(OT_THREADS);
   const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
   if (mode == ORTH_DOT) {
     if (a.nvec == 1) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RPL>), g, b, 0, s, a);
     } else if (same) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RPL>), g, b, 0, s, a);
     } else {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false, RPL>), g, b, 0, s, a);
     }
   } else if (mode == ORTH_UPD_DOT) {
-    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false>), g, b, 0, s, a);
+    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true, RPL>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false, RPL>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD, 1, true>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD, 1, true, RPL>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
+// Rows per lane per slab by pass (measured on MI355X, n = 2.1M, 20..40
+// columns): the pure dot pass streams best with 8 rows per lane, the passes
+// that exchange row sums through LDS every slab with 2.
+int rpl_for(int mode) {
+  if (g_orth_rpl > 0) return g_orth_rpl;
+  return mode == ORTH_DOT ? 8 : 2;
+}
+
+template <int CPW>
+hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  const int rpl = rpl_for(mode);
+  // the 16-column tiles keep fewer rows per lane to stay inside 256 VGPRs
+  if (CPW >= 16 || rpl <= 2) return launch_rpl<CPW, 2>(mode, a, nblk, s);
+  if (rpl >= 8) return launch_rpl<CPW, 8>(mode, a, nblk, s);
+  return launch_rpl<CPW, 4>(mode, a, nblk, s);
+}
+
 // ------------------------------------------------------------- finish --
-__global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
+// One workgroup of 16 wavefronts sums the per-block partials: lane j of
+// wavefront w adds blocks w, w+16, ... of output j (coalesced across lanes),
+// then the 16 partial sums are added in a fixed order.
+constexpr int FIN_THREADS = 1024;
+constexpr int FIN_WAVES = FIN_THREADS / WAVE;
+
+__device__ void fin_sum(const FinishArgs& f, int src, int cnt, double* dst, double (*red)[WAVE]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  for (int c0 = 0; c0 < cnt; c0 += WAVE) {
+    const int idx = c0 + lane;
+    double t = 0.0;
+    if (idx < cnt) {
+      const double* p = f.partial + src + idx;
+      for (int b = wv; b < f.nblk; b += FIN_WAVES) t += p[static_cast<int64_t>(b) * f.stride];
+    }
+    red[wv][lane] = t;
+    __syncthreads();
+    if (wv == 0 && idx < cnt) {
+      double u = 0.0;
+      for (int q = 0; q < FIN_WAVES; ++q) u += red[q][lane];
+      dst[idx] = u;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
   DevState* st = f.state;
   if (st && st->skip) return;
   const int nb = st ? st->nb : 0;
-  __shared__ double sh[ORTH_MAXCOL];
-  auto sum_idx = [&](int idx) {
-    double t = 0.0;
-    for (int b = 0; b < f.nblk; ++b) t += f.partial[static_cast<int64_t>(b) * f.stride + idx];
-    return t;
-  };
+  __shared__ double red[FIN_WAVES][WAVE];
+  __shared__ double v0[2 * ORTH_MAXCOL];
+  __shared__ double v1[ORTH_MAXCOL];
   const int tid = threadIdx.x;
   switch (f.mode) {
     case FIN_TH:
@@ -209,22 +250,18 @@ __global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
       // new column j = nb of T; the dots cover U columns 0..nb (after the
       // ncol_fixed locked columns)
       const int j = nb;
+      fin_sum(f, f.ncol_fixed, j + 1, v0, red);
+      const int nc = f.ncol_fixed + nb + 1;
+      if (f.mode == FIN_TH) fin_sum(f, ORTH_MAXCOL, nc, v1, red);
       for (int r = tid; r <= j; r += blockDim.x) {
-        const double v = sum_idx(f.ncol_fixed + r);
-        f.T[r + static_cast<int64_t>(j) * f.ldT] = v;
-        f.T[j + static_cast<int64_t>(r) * f.ldT] = v;
+        f.T[r + static_cast<int64_t>(j) * f.ldT] = v0[r];
+        f.T[j + static_cast<int64_t>(r) * f.ldT] = v0[r];
       }
       if (f.mode == FIN_TH) {
-        const int nc = f.ncol_fixed + nb + 1;
-        for (int c = tid; c < nc; c += blockDim.x) {
-          const double v = sum_idx(ORTH_MAXCOL + c);
-          f.h[c] = v;
-          sh[c] = v * v;
-        }
-        __syncthreads();
+        for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v1[c];
         if (tid == 0) {
           double t = 0.0;
-          for (int c = 0; c < nc; ++c) t += sh[c];
+          for (int c = 0; c < nc; ++c) t += v1[c] * v1[c];
           st->h1norm2 = t;
         }
       }
@@ -237,16 +274,17 @@ __global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
     }
     case FIN_TCOL: {
       const int j = f.cnt;
+      fin_sum(f, 0, j + 1, v0, red);
       for (int r = tid; r <= j; r += blockDim.x) {
-        const double v = sum_idx(r);
-        f.T[r + static_cast<int64_t>(j) * f.ldT] = v;
-        f.T[j + static_cast<int64_t>(r) * f.ldT] = v;
+        f.T[r + static_cast<int64_t>(j) * f.ldT] = v0[r];
+        f.T[j + static_cast<int64_t>(r) * f.ldT] = v0[r];
       }
       break;
     }
     case FIN_RES: {
+      fin_sum(f, 0, 128, v0, red);
       for (int i = tid; i < f.cnt; i += blockDim.x) {
-        const double r2 = sum_idx(i), x2 = sum_idx(64 + i);
+        const double r2 = v0[i], x2 = v0[64 + i];
         f.out[i] = sqrt(r2 / x2);
         f.out[64 + i] = sqrt(x2);
       }
@@ -255,22 +293,19 @@ __global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
     case FIN_H:
     case FIN_H2: {
       const int nc = f.ncol_fixed + nb + f.extra;
-      for (int c = tid; c < nc; c += blockDim.x) {
-        const double v = sum_idx(c);
-        f.h[c] = v;
-        sh[c] = v * v;
-      }
-      __syncthreads();
+      fin_sum(f, 0, nc, v0, red);
+      for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v0[c];
       if (f.mode == FIN_H && tid == 0) {
         double t = 0.0;
-        for (int c = 0; c < nc; ++c) t += sh[c];
+        for (int c = 0; c < nc; ++c) t += v0[c] * v0[c];
         st->h1norm2 = t;
       }
       break;
     }
     case FIN_NORM: {
+      fin_sum(f, 0, 1, v0, red);
       if (tid == 0) {
-        const double b2 = sum_idx(0);
+        const double b2 = v0[0];
         st->beta2 = b2;
         st->cnt_norm += 1;
         const bool finite = (b2 == b2) && (b2 < 1.0e308);
@@ -284,7 +319,12 @@ __global__ __launch_bounds__(256) void k_finish(const FinishArgs f) {
       break;
     }
     default: {
-      for (int c = tid; c < f.cnt; c += blockDim.x) f.out[c] = sum_idx(c);
+      for (int c0 = 0; c0 < f.cnt; c0 += 2 * ORTH_MAXCOL) {
+        const int cnt = min(2 * ORTH_MAXCOL, f.cnt - c0);
+        fin_sum(f, c0, cnt, v0, red);
+        for (int c = tid; c < cnt; c += blockDim.x) f.out[c0 + c] = v0[c];
+        __syncthreads();
+      }
       break;
     }
   }
@@ -395,10 +435,15 @@ int grid1d(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<in
 
 }  // namespace
 
-int orth_blocks(int n) {
-  const int nslab = (std::max(n, 1) + SLAB - 1) / SLAB;
-  return std::max(1, std::min(nslab, 512));
+int g_orth_maxblk = 0;  // 0: by pass
+
+int orth_blocks(int n, int mode) {
+  const int nslab = (std::max(n, 1) + WAVE * 2 - 1) / (WAVE * 2);
+  const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : (mode == ORTH_DOT ? 256 : 512);
+  return std::max(1, std::min(nslab, cap));
 }
+
+int orth_blocks_max(int n) { return std::max(orth_blocks(n, ORTH_DOT), orth_blocks(n, ORTH_UPD)); }
 
 int orth_stride() { return STRIDE; }
 
@@ -415,7 +460,7 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
 }
 
 hipError_t finish(const FinishArgs& f, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, f);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(FIN_THREADS), 0, s, f);
   return hipGetLastError();
 }
 

@@ -23,10 +23,9 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int RT = 256;          // threads per block (4 wavefronts)
-constexpr int KSMAX = SYEV_MAXB / 4;
+constexpr int RT = 256;  // threads per block (4 wavefronts)
 
-template <int NTILE>
+template <int NTILE, int KS>
 __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   const int b = a.state ? a.state->nb : a.b_fixed;
   const int kk = min(a.kout, b);
@@ -37,13 +36,14 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   const int lg = lane >> 4;   // k index within a K-step / output row group
   const int64_t ld = a.ld;
   const int n = a.n;
+  const bool resid = a.theta && a.AU;
 
   // A operand (16 outputs x 4 inputs): lane holds Y^T[16 t + li][4 ks + lg]
-  double yf[NTILE][KSMAX];
+  double yf[NTILE][KS];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t) {
 #pragma unroll
-    for (int ks = 0; ks < KSMAX; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int kin = 4 * ks + lg, kout = 16 * t + li;
       yf[t][ks] = (kin < b && kout < kk) ? a.Y[kin + static_cast<int64_t>(kout) * a.ldY] : 0.0;
     }
@@ -60,28 +60,34 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
       xs[t][r] = 0.0;
     }
 
+  // matrices in the order A U, B U, U so that at most two result tiles are
+  // live for the residual ||A x - theta B x||
+  double* mats[3] = {a.AU, a.BU, a.U};
   const int nwave = gridDim.x * (RT / WAVE);
   const int ntile_rows = (n + 15) / 16;
   for (int rb = blockIdx.x * (RT / WAVE) + wv; rb < ntile_rows; rb += nwave) {
     const int row = rb * 16 + li;
     const bool ok = row < n;
-    d4 DX[NTILE], DA[NTILE], DB[NTILE];
-    double* mats[3] = {a.U, a.AU, a.BU};
+    d4 DA[NTILE];
 #pragma unroll
     for (int mi = 0; mi < 3; ++mi) {
       double* M = mats[mi];
       if (M == nullptr) continue;
+      double bv[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kin = 4 * ks + lg;
+        bv[ks] = (ks < nks && ok && kin < b) ? M[kin * ld + row] : 0.0;
+      }
       d4 D[NTILE];
 #pragma unroll
       for (int t = 0; t < NTILE; ++t) D[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < KSMAX; ++ks) {
+      for (int ks = 0; ks < KS; ++ks) {
         if (ks < nks) {
-          const int kin = 4 * ks + lg;
-          const double bv = (ok && kin < b) ? M[kin * ld + row] : 0.0;
 #pragma unroll
           for (int t = 0; t < NTILE; ++t)
-            D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yf[t][ks], bv, D[t], 0, 0, 0);
+            D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yf[t][ks], bv[ks], D[t], 0, 0, 0);
         }
       }
       // lane holds X(row = rb*16 + li, col = 16 t + lg + 4 r): the F64 16x16x4
@@ -93,26 +99,31 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
           const int kc = 16 * t + lg + 4 * r;
           if (ok && kc < kk) M[kc * ld + row] = D[t][r];
         }
-        if (mi == 0) DX[t] = D[t];
-        else if (mi == 1) DA[t] = D[t];
-        else DB[t] = D[t];
       }
-    }
-    if (a.theta && a.AU) {
+      if (resid) {
+        if (mi == 0) {
 #pragma unroll
-      for (int t = 0; t < NTILE; ++t)
+          for (int t = 0; t < NTILE; ++t) DA[t] = D[t];
+        } else if (mi == 1 || (mi == 2 && a.BU == nullptr)) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double x = DX[t][r];
-          const double bx = a.BU ? DB[t][r] : x;
-          const double rr = DA[t][r] - th[t][r] * bx;
-          rs[t][r] += rr * rr;
-          xs[t][r] += x * x;
+          for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double rr = DA[t][r] - th[t][r] * D[t][r];
+              rs[t][r] += rr * rr;
+            }
         }
+        if (mi == 2) {
+#pragma unroll
+          for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xs[t][r] += D[t][r] * D[t][r];
+        }
+      }
     }
   }
 
-  if (a.theta && a.AU) {
+  if (resid) {
     // sum over the 16 lanes that hold the same output columns
     __shared__ double sr[RT / WAVE][2][64];
 #pragma unroll
@@ -147,6 +158,18 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   }
 }
 
+template <int NTILE>
+hipError_t launch_nt(const RotArgs& a, int nblk, hipStream_t s) {
+  const int bmax = a.b_max > 0 ? a.b_max : (a.state ? SYEV_MAXB : a.b_fixed);
+  const int ks = (bmax + 3) / 4;
+  const dim3 g(nblk), b(RT);
+  if (ks <= 4) hipLaunchKernelGGL((k_rotate<NTILE, 4>), g, b, 0, s, a);
+  else if (ks <= 8) hipLaunchKernelGGL((k_rotate<NTILE, 8>), g, b, 0, s, a);
+  else if (ks <= 12) hipLaunchKernelGGL((k_rotate<NTILE, 12>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_rotate<NTILE, 16>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int rot_blocks(int n) {
@@ -156,16 +179,13 @@ int rot_blocks(int n) {
 }
 
 hipError_t rotate(const RotArgs& a, int nblk, hipStream_t s) {
-  const int nt = (a.kout + 15) / 16;
-  const dim3 g(nblk), b(RT);
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_rotate<1>, g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_rotate<2>, g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_rotate<3>, g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_rotate<4>, g, b, 0, s, a); break;
+  switch ((a.kout + 15) / 16) {
+    case 1: return launch_nt<1>(a, nblk, s);
+    case 2: return launch_nt<2>(a, nblk, s);
+    case 3: return launch_nt<3>(a, nblk, s);
+    case 4: return launch_nt<4>(a, nblk, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace trplk

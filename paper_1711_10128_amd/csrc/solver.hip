@@ -102,7 +102,7 @@ struct trplk_ctx {
   DevState* st = nullptr;
   Report* rep_h = nullptr;
   Report* rep_d = nullptr;
-  int orth_nblk = 0, rot_nblk = 0;
+  int orth_nblk = 0, rot_nblk = 0;  // orth_nblk: largest pass grid (sizes partials)
   int64_t partial_bytes = 0;
   bool ws_ready = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -280,7 +280,7 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &c->Y, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->hbuf, ORTH_MAXCOL));
   HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
-  c->orth_nblk = orth_blocks(n);
+  c->orth_nblk = orth_blocks_max(n);
   c->rot_nblk = rot_blocks(n);
   int64_t pb = static_cast<int64_t>(c->orth_nblk) * orth_stride();
   pb = std::max<int64_t>(pb, static_cast<int64_t>(c->rot_nblk) * 128);
@@ -343,8 +343,9 @@ struct Solver {
     else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
     else bytes = 8 * cols * n + 16LL * n;
     ProfScope ps(c, PC_ORTH, bytes);
-    return orth_pass(mode, a, c->orth_nblk, s);
+    return orth_pass(mode, a, orth_blocks(n, mode), s);
   }
+  int nblk(int mode) const { return orth_blocks(n, mode); }
 
   hipError_t spmv(const DevCsr& M, const SpmvArgs& a, bool f32, int cls, int64_t extra_bytes) {
     ProfScope ps(c, cls, spmv_bytes(M, f32) + extra_bytes);
@@ -367,7 +368,7 @@ struct Solver {
       a.Md0 = BWq(); a.vec0 = c->w; a.nvec = 1; a.partial = c->partial;
       S.check(orth(ORTH_DOT, a), "orth h1");
       FinishArgs f;
-      f.mode = FIN_H; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.mode = FIN_H; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
       f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
       S.check(fin(f), "fin h1");
     }
@@ -377,7 +378,7 @@ struct Solver {
       a.Mu = Wq(); a.Md1 = BWq(); a.h = c->hbuf; a.w = c->w; a.partial = c->partial;
       S.check(orth(ORTH_UPD_DOT, a), "orth upd-dot");
       FinishArgs f;
-      f.mode = FIN_H2; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.mode = FIN_H2; f.partial = c->partial; f.nblk = nblk(ORTH_UPD_DOT); f.stride = orth_stride();
       f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
       S.check(fin(f), "fin h2");
     }
@@ -399,7 +400,7 @@ struct Solver {
       f.nblk = spmv_partial_blocks(c->B.plan);
       f.stride = 1;
     } else {
-      f.nblk = c->orth_nblk;
+      f.nblk = nblk(ORTH_UPD);
       f.stride = orth_stride();
     }
     S.check(fin(f), "fin norm");
@@ -468,7 +469,7 @@ struct Solver {
     }
     S.check(orth(ORTH_DOT, a), "orth tcol");
     FinishArgs f;
-    f.mode = with_h1 ? FIN_TH : FIN_T; f.partial = c->partial; f.nblk = c->orth_nblk;
+    f.mode = with_h1 ? FIN_TH : FIN_T; f.partial = c->partial; f.nblk = nblk(ORTH_DOT);
     f.stride = orth_stride(); f.state = c->st; f.ncol_fixed = c->u0; f.T = c->T; f.ldT = SYEV_MAXB;
     f.h = c->hbuf;
     S.check(fin(f), "fin tcol");
@@ -507,7 +508,7 @@ struct Solver {
       S.check(syev(c->T, SYEV_MAXB, 0, &c->st->nb, 0, c->theta, c->Y, SYEV_MAXB, s), "syev");
     }
     RotArgs r;
-    r.n = n; r.kout = kout; r.state = c->st; r.Y = c->Y; r.ldY = SYEV_MAXB;
+    r.n = n; r.kout = kout; r.state = c->st; r.Y = c->Y; r.ldY = SYEV_MAXB; r.b_max = c->m;
     r.U = Ucol(0); r.AU = AUcol(0); r.BU = c->hasB ? BUcol(0) : nullptr; r.ld = ld;
     r.theta = c->theta; r.partial = c->partial;
     {
@@ -550,7 +551,7 @@ struct Solver {
       o.vec0 = AUcol(j); o.nvec = 1; o.partial = c->partial;
       S.check(orth(ORTH_DOT, o), "refresh T");
       FinishArgs f;
-      f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+      f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
       f.T = c->T; f.ldT = SYEV_MAXB; f.cnt = j;
       S.check(fin(f), "fin refresh T");
     }
@@ -717,7 +718,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
         a.vec0 = c->AW + j * ld; a.nvec = 1; a.partial = c->partial;
         S.check(orth(ORTH_DOT, a), "TQ");
         FinishArgs f;
-        f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = c->orth_nblk; f.stride = orth_stride();
+        f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
         f.T = c->T; f.ldT = SYEV_MAXB; f.cnt = j;
         S.check(fin(f), "fin TQ");
       }
@@ -1059,9 +1060,9 @@ int trplk_get_eigpairs(trplk_ctx* c, double* evals, double* evecs, double* resid
       OrthArgs o;
       o.n = n; o.ld = ld; o.ncol_fixed = 1; o.ncol_max = 1; o.Md0 = x; o.vec0 = x; o.nvec = 1;
       o.partial = c->partial;
-      HIPCHK(c, orth_pass(ORTH_DOT, o, c->orth_nblk, c->s));
+      HIPCHK(c, orth_pass(ORTH_DOT, o, orth_blocks(n, ORTH_DOT), c->s));
       FinishArgs g;
-      g.mode = FIN_SUM; g.partial = c->partial; g.nblk = c->orth_nblk; g.stride = orth_stride();
+      g.mode = FIN_SUM; g.partial = c->partial; g.nblk = orth_blocks(n, ORTH_DOT); g.stride = orth_stride();
       g.out = c->resout + 1; g.cnt = 1;
       HIPCHK(c, finish(g, c->s));
       HIPCHK(c, hipMemcpyAsync(h.data(), c->resout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
@@ -1169,7 +1170,7 @@ int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const doubl
                  void* stream) {
   if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !v || !h) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nblk = orth_blocks(n);
+  const int nblk = orth_blocks(n, ORTH_DOT);
   double* part = scratch(sizeof(double) * nblk * orth_stride());
   if (!part) return TRPLK_ENOMEM;
   OrthArgs a;
@@ -1187,7 +1188,7 @@ int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, con
                          double* w, double* h2, void* stream) {
   if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !h || !w || !h2) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nblk = orth_blocks(n);
+  const int nblk = orth_blocks(n, ORTH_UPD_DOT);
   double* part = scratch(sizeof(double) * nblk * orth_stride());
   if (!part) return TRPLK_ENOMEM;
   OrthArgs a;

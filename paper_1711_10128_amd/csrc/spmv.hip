@@ -91,6 +91,10 @@ __device__ __forceinline__ void block_partial(double acc, double* partial, int s
   }
 }
 
+// A wavefront owns a tile of 64 consecutive rows.  In sub-iteration q the
+// group g of L lanes reduces row q * (64 / L) + g; afterwards the row sums are
+// redistributed with shuffles so that lane j holds row j of the tile and the
+// epilogue's loads and stores of the dense vectors are fully coalesced.
 template <int L, typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rows(const SpmvArgs a) {
   EpiCtx e{1.0, 0.0, 0};
@@ -104,19 +108,46 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rows(const SpmvArgs a) {
   const int* __restrict__ col = a.col;
   const VT* __restrict__ val = static_cast<const VT*>(a.val);
   const XT* __restrict__ x = static_cast<const XT*>(a.x);
-  constexpr int RPB = SPMV_THREADS / L;
-  const int li = threadIdx.x & (L - 1);
+  constexpr int RPW = WAVE / L;  // rows per sub-iteration
+  constexpr int WPB = SPMV_THREADS / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int li = lane & (L - 1);
+  const int g = lane / L;
+  const int ntile = (a.n + WAVE - 1) / WAVE;
   double acc = 0.0;
-  for (int row = blockIdx.x * RPB + threadIdx.x / L; row < a.n; row += gridDim.x * RPB) {
-    const int beg = rowptr[row];
-    const int end = rowptr[row + 1];
-    if (end - beg > LONG_ROW) continue;  // the workgroup-per-row kernel owns it
-    AT sum = 0;
-    for (int j = beg + li; j < end; j += L) sum += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
-    double s;
-    if constexpr (sizeof(AT) == 4) s = static_cast<double>(group_sumf<L>(sum));
-    else s = group_sum<L>(sum);
-    if (li == 0) epilogue<OT>(a, e, row, s, acc);
+  for (int tile = blockIdx.x * WPB + wv; tile < ntile; tile += gridDim.x * WPB) {
+    const int r0 = tile * WAVE;
+    double mine = 0.0;
+    int mylong = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const int row = r0 + q * RPW + g;
+      AT sum = 0;
+      int islong = 0;
+      if (row < a.n) {
+        const int beg = rowptr[row];
+        const int end = rowptr[row + 1];
+        if (end - beg > LONG_ROW) {
+          islong = 1;  // the workgroup-per-row kernel owns it
+        } else {
+          for (int j = beg + li; j < end; j += L)
+            sum += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+        }
+      }
+      double sd;
+      if constexpr (sizeof(AT) == 4) sd = static_cast<double>(group_sumf<L>(sum));
+      else sd = group_sum<L>(sum);
+      const int src = (lane % RPW) * L;
+      const double t = __shfl(sd, src, WAVE);
+      const int tl = __shfl(islong, src, WAVE);
+      if (lane / RPW == q) {
+        mine = t;
+        mylong = tl;
+      }
+    }
+    const int row = r0 + lane;
+    if (row < a.n && !mylong) epilogue<OT>(a, e, row, mine, acc);
   }
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
@@ -157,9 +188,9 @@ __global__ void k_find_long(int n, const int* rowptr, int* flags) {
     flags[i] = (rowptr[i + 1] - rowptr[i]) > LONG_ROW;
 }
 
-int short_blocks(int n, int lanes) {
-  const int rpb = SPMV_THREADS / lanes;
-  const int want = (n + rpb - 1) / rpb;
+int short_blocks(int n, int /*lanes*/) {
+  const int tiles = (n + WAVE - 1) / WAVE;
+  const int want = (tiles + SPMV_THREADS / WAVE - 1) / (SPMV_THREADS / WAVE);
   return std::max(1, std::min(want, 8192));
 }
 
@@ -189,9 +220,12 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// Lanes per row: the smallest power of two covering half the mean row
+// length (two loads per lane for a typical row; measured best for the
+// 7-point stencil: 4 lanes).
 int pick_lanes(double mean_len) {
   int L = 2;
-  while (L < 64 && L < mean_len) L <<= 1;
+  while (L < 64 && 2 * L < mean_len) L <<= 1;
   return L;
 }
 
