@@ -153,6 +153,49 @@ int trplk_solve(trplk_ctx* ctx, const double* x0, int32_t mem, trplk_stats* st);
 int trplk_get_eigpairs(trplk_ctx* ctx, double* evals, double* evecs, double* resid,
                        int32_t* conv, int32_t mem);
 
+/* ------------------------------------------------------------------------
+ * Learned factor.  A two-layer MLP (float32) maps features of each
+ * lower-triangular nonzero (i, j) of A to a scalar o_ij; the factor is
+ * G(i,i) = exp(o_ii)/sqrt(a_ii), G(i,j) = o_ij/sqrt(a_jj) (j < i), so M =
+ * G^T G is SPD by construction and a zero output layer reproduces Jacobi.
+ * Inputs: [f_i (8), f_j (8), |a_ij|/sqrt(a_ii a_jj)], f = z-scored row
+ * features (degree, a_ii, sum / mean / min / max / std of |a_ij|, j != i,
+ * a_ii / sum).  Parameters: TRPLK_MLP_NPARAM floats packed as W1 (64 x 17,
+ * row-major), b1 (64), w2 (64), b2 (1).  Not in the paper: it replaces the
+ * paper's incomplete factorisations (Sec. 5.3-5.4) with a factor whose
+ * values are learned; FSAI / Jacobi remain the fallbacks.
+ * ------------------------------------------------------------------------ */
+#define TRPLK_MLP_NPARAM 1217
+
+/* Evaluate the MLP on the GPU for A's lower pattern and install M = G^T G
+ * (switches the context to TRPLK_PREC_FACTOR).  params: host array. */
+int trplk_learned_factor(trplk_ctx* ctx, const float* params);
+
+/* Nonzeros of the learned factor's pattern (tril(A)); builds the pattern on
+ * first use.  -1 on error. */
+int64_t trplk_factor_nnz(trplk_ctx* ctx);
+
+/* Values of the factor last evaluated by the MLP, in the CSR order of
+ * tril(A) (trplk_factor_nnz entries). */
+int trplk_factor_values(trplk_ctx* ctx, double* val, int32_t mem);
+
+/* Loss L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2 over the pairs
+ * (E, R) (n x S, column-major, S <= 32, host or device per `mem`) and its
+ * gradient with respect to the MLP parameters (grad: host, TRPLK_MLP_NPARAM
+ * doubles), computed by the training kernels (float32 network, float64 pair
+ * algebra, fixed-order reductions). */
+int trplk_factor_loss_grad(trplk_ctx* ctx, const float* params, int32_t S, const double* E,
+                           const double* R, int32_t mem, double* loss, double* grad);
+
+/* One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * pairs (u, A u) the last trplk_solve on this context left in its basis (the
+ * first S <= min(m, 32) stored columns and their products).  params,
+ * adam_m, adam_v: host arrays of TRPLK_MLP_NPARAM floats, updated in place;
+ * step: Adam step count (>= 1); loss: optional output (before the update).
+ * Call it on several contexts in turn to train on several problems. */
+int trplk_train_step(trplk_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
+                     double lr, int32_t S, double* loss);
+
 /* Bytes of device memory the context holds (matrices, preconditioner and the
  * solver workspace sized for its options). */
 int64_t trplk_device_bytes(const trplk_ctx* ctx);

@@ -69,7 +69,10 @@ _lib = None
 EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_set_factor", "trplk_solve",
            "trplk_get_eigpairs", "trplk_device_bytes", "trplk_last_error", "trplk_destroy",
            "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
-           "trplk_rotate"]
+           "trplk_rotate", "trplk_learned_factor", "trplk_factor_nnz", "trplk_factor_values",
+           "trplk_factor_loss_grad", "trplk_train_step"]
+MLP_NPARAM = 1217
+MLP_NF, MLP_NIN, MLP_NH = 8, 17, 64
 
 
 def lib():
@@ -108,6 +111,16 @@ def lib():
     for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot",
               "trplk_syev", "trplk_rotate"):
         getattr(L, f).restype = ctypes.c_int
+    L.trplk_learned_factor.argtypes = [vp, vp]
+    L.trplk_learned_factor.restype = ctypes.c_int
+    L.trplk_factor_nnz.argtypes = [vp]
+    L.trplk_factor_nnz.restype = i64
+    L.trplk_factor_values.argtypes = [vp, vp, i32]
+    L.trplk_factor_values.restype = ctypes.c_int
+    L.trplk_factor_loss_grad.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
+    L.trplk_factor_loss_grad.restype = ctypes.c_int
+    L.trplk_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp]
+    L.trplk_train_step.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -222,6 +235,43 @@ class Solver:
         _check(lib().trplk_get_eigpairs(self.ctx, vp(ev), vp(X), vp(rs), vp(cv), MEM_HOST), self.ctx)
         return ev, (X.T if X is not None else None), rs, cv.astype(bool)
 
+    # ---- learned factor (M = G^T G, G predicted by the MLP) ----
+    def learned_factor(self, params):
+        """Evaluate the MLP (params: TRPLK_MLP_NPARAM float32) and install M = G^T G."""
+        P = np.ascontiguousarray(params, dtype=np.float32)
+        assert P.shape == (MLP_NPARAM,)
+        _check(lib().trplk_learned_factor(self.ctx, P.ctypes.data_as(ctypes.c_void_p)), self.ctx)
+
+    def factor_values(self):
+        nnz = int(lib().trplk_factor_nnz(self.ctx))
+        v = np.empty(nnz)
+        _check(lib().trplk_factor_values(self.ctx, v.ctypes.data_as(ctypes.c_void_p), MEM_HOST),
+               self.ctx)
+        return v
+
+    def factor_loss_grad(self, params, E, R):
+        P = np.ascontiguousarray(params, dtype=np.float32)
+        E = np.asfortranarray(E, dtype=np.float64)
+        R = np.asfortranarray(R, dtype=np.float64)
+        loss = ctypes.c_double()
+        grad = np.empty(MLP_NPARAM)
+        vp = ctypes.c_void_p
+        _check(lib().trplk_factor_loss_grad(self.ctx, P.ctypes.data_as(vp), E.shape[1],
+                                            E.ctypes.data_as(vp), R.ctypes.data_as(vp), MEM_HOST,
+                                            ctypes.byref(loss), grad.ctypes.data_as(vp)), self.ctx)
+        return loss.value, grad
+
+    def train_step(self, params, m, v, step, lr, S):
+        """One Adam step on the pairs of the last solve; arrays updated in place."""
+        loss = ctypes.c_double()
+        vp = ctypes.c_void_p
+        for a in (params, m, v):
+            assert a.dtype == np.float32 and a.flags.c_contiguous and a.shape == (MLP_NPARAM,)
+        _check(lib().trplk_train_step(self.ctx, params.ctypes.data_as(vp), m.ctypes.data_as(vp),
+                                      v.ctypes.data_as(vp), step, lr, S, ctypes.byref(loss)),
+               self.ctx)
+        return loss.value
+
     def device_bytes(self):
         return int(lib().trplk_device_bytes(self.ctx))
 
@@ -274,3 +324,45 @@ def rotate(U, Y, k):
     b, n = U.shape
     _check(lib().trplk_rotate(n, b, k, _ptr(U), n, _ptr(Y), b, _stream()))
     return U
+
+
+def pack_params(W1, b1, w2, b2):
+    """Flat float32 parameter vector: W1 (64 x 17 row-major), b1, w2, b2."""
+    return np.concatenate([np.asarray(W1, dtype=np.float64).ravel(), np.ravel(b1), np.ravel(w2),
+                           np.ravel(b2)]).astype(np.float32)
+
+
+def unpack_params(P):
+    P = np.asarray(P, dtype=np.float64)
+    k = MLP_NH * MLP_NIN
+    return {"W1": P[:k].reshape(MLP_NH, MLP_NIN), "b1": P[k:k + MLP_NH],
+            "w2": P[k + MLP_NH:k + 2 * MLP_NH], "b2": P[k + 2 * MLP_NH]}
+
+
+def init_params(seed=0):
+    """He-scaled first layer, zero output layer (the factor starts as Jacobi)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((MLP_NH, MLP_NIN)) * np.sqrt(2.0 / MLP_NIN)
+    return pack_params(W1, np.zeros(MLP_NH), np.zeros(MLP_NH), 0.0)
+
+
+def train(solvers, X0s, epochs, lr=1e-3, S=24, params=None, log=None):
+    """Train the factor's MLP on the GPU: solve each instance once (Jacobi or
+    whatever preconditioner its Solver holds) to harvest pairs (u, A u) from
+    its basis, then full-batch Adam over the instances for `epochs` epochs."""
+    P = init_params() if params is None else np.array(params, dtype=np.float32)
+    m = np.zeros(MLP_NPARAM, dtype=np.float32)
+    v = np.zeros(MLP_NPARAM, dtype=np.float32)
+    for s, X0 in zip(solvers, X0s):
+        s.solve(X0)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        tot = 0.0
+        for s in solvers:
+            step += 1
+            tot += s.train_step(P, m, v, step, lr, S)
+        hist.append(tot / len(solvers))
+        if log and ep % 25 == 0:
+            log(f"epoch {ep} loss {hist[-1]:.5f}")
+    return P, hist

@@ -229,6 +229,60 @@ hipError_t fsai_build(int n, const int* rowptr, const int* col, const double* va
 hipError_t csr_transpose(int n, int64_t nnz, const int* rowptr, const int* col, const double* val,
                          int** t_rowptr, int** t_col, double** t_val, hipStream_t s);
 
+// ------------------------------------------------------ learned factor --
+constexpr int MLP_NF = 8;                  // row features
+constexpr int MLP_NIN = 2 * MLP_NF + 1;    // inputs per lower-triangular nonzero
+constexpr int MLP_NH = 64;                 // hidden width
+constexpr int MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH + 1;  // W1, b1, w2, b2
+constexpr int LEARN_MAXS = 32;             // training pairs per instance
+
+struct LearnArgs {
+  int n = 0;
+  int64_t nnz = 0;            // lower-triangular nonzeros (G's pattern)
+  int S = 0;
+  const int* Lrow = nullptr;  // G row pointers
+  const int* lc = nullptr;    // G columns
+  const int* lr = nullptr;    // G row of each nonzero
+  const double* lval = nullptr;  // a_ij on the pattern
+  const int* Trow = nullptr;  // G^T row pointers / columns
+  const int* Tcol = nullptr;
+  const double* gval = nullptr;
+  const double* gvalT = nullptr;
+  const float* Fz = nullptr;
+  const double* dinv = nullptr;
+  const float* P = nullptr;   // parameters (device)
+  const double* Rr = nullptr; // pairs, row-major n x S
+  const double* Er = nullptr;
+  const double* w = nullptr;  // 1 / (S ||e_s||^2)
+  double* Y = nullptr;
+  double* D = nullptr;
+  double* Uu = nullptr;
+  float* dout = nullptr;
+  double* part = nullptr;     // learn_blocks() * MLP_NPARAM
+  double* loss = nullptr;
+  double* grad = nullptr;     // MLP_NPARAM
+};
+
+hipError_t mlp_features(int n, const int* rowptr, const int* col, const double* val, double* F,
+                        float* Fz, double* scratch, hipStream_t s);
+int mlp_scratch_doubles();
+hipError_t tril_count(int n, const int* rowptr, const int* col, int* cnt, hipStream_t s);
+hipError_t tril_fill(int n, const int* rowptr, const int* col, const double* val, const int* lrow,
+                     int* lcol, int* lr, double* lval, hipStream_t s);
+hipError_t mlp_forward(int64_t nnz, const int* lr, const int* lc, const double* lval,
+                       const float* Fz, const double* dinv, const float* P, double* gval,
+                       float* oval, hipStream_t s);
+int learn_blocks();
+hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s);
+hipError_t learn_weights(int n, int S, const double* Er, double* part, double* w, hipStream_t s);
+hipError_t adam_step(float* P, float* m, float* v, const double* grad, int t, float lr,
+                     hipStream_t s);
+hipError_t to_rowmajor(int n, int S, const double* Xc, int64_t ldx, double* Xr, hipStream_t s);
+hipError_t gather_values(int64_t nnz, const double* src, const double* permd, double* dst,
+                         hipStream_t s);
+hipError_t iota_values(int64_t nnz, double* x, hipStream_t s);
+hipError_t exclusive_scan_i32(const int* in, int* out, int n, hipStream_t s);
+
 // ----------------------------------------------------------- eig / rot --
 constexpr int SYEV_MAXB = 64;
 // Jacobi eigensolver of T (b x b, b from *nb_dev or b_fixed when nb_dev is

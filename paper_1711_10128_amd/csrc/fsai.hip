@@ -187,6 +187,10 @@ hipError_t exclusive_scan(const int* in, int* out, int n, hipStream_t s) {
 
 }  // namespace
 
+hipError_t exclusive_scan_i32(const int* in, int* out, int n, hipStream_t s) {
+  return exclusive_scan(in, out, n, s);
+}
+
 hipError_t fsai_build(int n, const int* rowptr, const int* col, const double* val, int cap,
                       int** g_rowptr, int** g_col, double** g_val, int64_t* g_nnz, int* bad_host,
                       hipStream_t s) {

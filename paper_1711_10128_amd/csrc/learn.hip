@@ -1,0 +1,496 @@
+// Learned factorized preconditioner M = G^T G: row features, the two-layer
+// MLP that predicts G on the lower pattern of A, and its training kernels.
+//
+// Network (per lower-triangular nonzero (i, j) of A, float32):
+//   x = [f_i (8), f_j (8), |a_ij| / sqrt(a_ii a_jj)]          (17 inputs)
+//   h = relu(W1 x + b1)  (64),   o = w2 . h + b2
+//   G(i,i) = exp(o) / sqrt(a_ii),   G(i,j) = o / sqrt(a_jj)  (j < i)
+// so G has a positive diagonal (M is SPD by construction) and a zero output
+// layer gives G = D^{-1/2}, i.e. the Jacobi preconditioner.
+// Features f_i: degree, a_ii, sum / mean / min / max / std of |a_ij| (j != i)
+// and a_ii / sum, each z-scored over the rows of A.
+// Loss over pairs (r_s, e_s) = (A u_s, u_s) from the solver's basis:
+//   L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2,
+//   dL/dG(i,j) = sum_s (2 / (S ||e_s||^2)) (y_i d_j + u_i r_j),
+//   y = G r, d = G^T y - e, u = G d   (sampled dense-dense product on the pattern).
+// All reductions are fixed-order (per-block partials, then one block), so a
+// training step is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace trplk {
+
+namespace {
+
+constexpr int NF = MLP_NF;
+constexpr int NIN = MLP_NIN;
+constexpr int NH = MLP_NH;
+constexpr int NP = MLP_NPARAM;
+constexpr int OFF_B1 = NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH;
+
+int g1(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
+
+// ---------------------------------------------------------------- features
+__global__ void k_raw_features(int n, const int* rowptr, const int* col, const double* val,
+                               double* F) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double d = 0.0, s = 0.0, mn = 0.0, mx = 0.0;
+    int deg = 0;
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j) {
+      if (col[j] == i) {
+        d = val[j];
+        continue;
+      }
+      const double o = fabs(val[j]);
+      s += o;
+      mn = deg ? fmin(mn, o) : o;
+      mx = deg ? fmax(mx, o) : o;
+      ++deg;
+    }
+    double sd = 0.0, mean = 0.0;
+    if (deg) {
+      mean = s / deg;
+      double q = 0.0;
+      for (int j = rowptr[i]; j < rowptr[i + 1]; ++j)
+        if (col[j] != i) {
+          const double t = fabs(val[j]) - mean;
+          q += t * t;
+        }
+      sd = sqrt(q / deg);
+    }
+    double* f = F + static_cast<int64_t>(i) * NF;
+    f[0] = deg;
+    f[1] = d;
+    f[2] = s;
+    f[3] = mean;
+    f[4] = mn;
+    f[5] = mx;
+    f[6] = sd;
+    f[7] = deg ? d / s : 0.0;
+  }
+}
+
+// per-block sums of F (pass 0) or of (F - mu)^2 (pass 1), one row of NF per block
+__global__ __launch_bounds__(256) void k_feat_moments(int n, const double* F, const double* mu,
+                                                      double* part) {
+  __shared__ double red[256][NF];
+  double acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double v = F[static_cast<int64_t>(i) * NF + f];
+      if (mu) {
+        const double t = v - mu[f];
+        acc[f] += t * t;
+      } else {
+        acc[f] += v;
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) red[threadIdx.x][f] = acc[f];
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double t = 0.0;
+    for (int q = 0; q < 256; ++q) t += red[q][threadIdx.x];
+    part[blockIdx.x * NF + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_feat_stat(int nblk, int n, const double* part, double* out, int sqrt_mode) {
+  const int f = threadIdx.x;
+  if (f >= NF) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += part[b * NF + f];
+  t /= n;
+  if (sqrt_mode) {
+    t = sqrt(t);
+    if (t == 0.0) t = 1.0;
+  }
+  out[f] = t;
+}
+
+__global__ void k_feat_norm(int n, const double* F, const double* mu, const double* sd, float* Fz) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+       t < static_cast<int64_t>(n) * NF; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int f = static_cast<int>(t % NF);
+    Fz[t] = static_cast<float>((F[t] - mu[f]) / sd[f]);
+  }
+}
+
+// ------------------------------------------------------------ tril pattern
+__global__ void k_tril_count(int n, const int* rowptr, const int* col, int* cnt) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int c = 0;
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j) c += col[j] <= i;
+    cnt[i] = c;
+  }
+}
+
+__global__ void k_tril_fill(int n, const int* rowptr, const int* col, const double* val,
+                            const int* lrow, int* lcol, int* lr, double* lval) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int o = lrow[i];
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j)
+      if (col[j] <= i) {
+        lcol[o] = col[j];
+        lr[o] = i;
+        lval[o] = val[j];
+        ++o;
+      }
+  }
+}
+
+// ------------------------------------------------------------------- MLP
+__device__ __forceinline__ void load_params(const float* P, float* sP) {
+  for (int t = threadIdx.x; t < NP; t += blockDim.x) sP[t] = P[t];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void make_input(const float* Fz, const double* dinv, int i, int j,
+                                           double aij, float* x) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    x[f] = Fz[static_cast<int64_t>(i) * NF + f];
+    x[NF + f] = Fz[static_cast<int64_t>(j) * NF + f];
+  }
+  x[2 * NF] = static_cast<float>(fabs(aij) * sqrt(dinv[i] * dinv[j]));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(int64_t nnz, const int* lr, const int* lc,
+                                                     const double* lval, const float* Fz,
+                                                     const double* dinv, const float* P,
+                                                     double* gval, float* oval) {
+  __shared__ float sP[NP];
+  load_params(P, sP);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = lr[e], j = lc[e];
+    float x[NIN];
+    make_input(Fz, dinv, i, j, lval[e], x);
+    float o = sP[OFF_B2];
+    for (int k = 0; k < NH; ++k) {
+      float pre = sP[OFF_B1 + k];
+#pragma unroll
+      for (int f = 0; f < NIN; ++f) pre += sP[k * NIN + f] * x[f];
+      o += sP[OFF_W2 + k] * fmaxf(pre, 0.0f);
+    }
+    if (oval) oval[e] = o;
+    const double od = static_cast<double>(o);
+    gval[e] = (i == j ? exp(od) : od) * sqrt(dinv[j]);
+  }
+}
+
+// -------------------------------------------------- pair algebra (float64)
+// Y = M X for a CSR M and row-major n x S blocks (S <= 32): 32 lanes per row,
+// lane s owns column s.  mode 1: Y = M X - E.
+__global__ __launch_bounds__(256) void k_spmm(int n, int S, const int* rowptr, const int* col,
+                                              const double* val, const double* X, const double* E,
+                                              double* Y) {
+  const int lane = threadIdx.x & 31;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / 32; i < n;
+       i += (gridDim.x * blockDim.x) / 32) {
+    if (lane >= S) continue;
+    double t = 0.0;
+    for (int j = rowptr[i]; j < rowptr[i + 1]; ++j)
+      t += val[j] * X[static_cast<int64_t>(col[j]) * S + lane];
+    if (E) t -= E[static_cast<int64_t>(i) * S + lane];
+    Y[static_cast<int64_t>(i) * S + lane] = t;
+  }
+}
+
+// per-block partial of sum_s w_s ||D_s||^2 (w_s = 1 / (S ||e_s||^2))
+__global__ __launch_bounds__(256) void k_loss_part(int n, int S, const double* D, const double* w,
+                                                   double* part) {
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+       t < static_cast<int64_t>(n) * S; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double d = D[t];
+    acc += d * d * w[t % S];
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// column norms of a row-major n x S block: per-block partials [S]
+__global__ __launch_bounds__(256) void k_colnorm_part(int n, int S, const double* E, double* part) {
+  __shared__ double red[256][33];
+  double acc[32];
+  for (int s = 0; s < 32; ++s) acc[s] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    for (int s = 0; s < S; ++s) {
+      const double v = E[static_cast<int64_t>(i) * S + s];
+      acc[s] += v * v;
+    }
+  for (int s = 0; s < S; ++s) red[threadIdx.x][s] = acc[s];
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double t = 0.0;
+    for (int q = 0; q < 256; ++q) t += red[q][threadIdx.x];
+    part[blockIdx.x * 32 + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_weights(int nblk, int S, const double* part, double* w) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += part[b * 32 + s];
+  w[s] = 1.0 / (S * t);
+}
+
+// dL/do_e: sampled products on the pattern, then the chain rule through
+// G = exp(o)/sqrt(a_ii) (diagonal) or o/sqrt(a_jj)
+__global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int S, const int* lr, const int* lc,
+                                               const double* gval, const double* dinv,
+                                               const double* Y, const double* D, const double* Uu,
+                                               const double* R, const double* w, float* dout) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = lr[e], j = lc[e];
+    const double* yi = Y + static_cast<int64_t>(i) * S;
+    const double* ui = Uu + static_cast<int64_t>(i) * S;
+    const double* dj = D + static_cast<int64_t>(j) * S;
+    const double* rj = R + static_cast<int64_t>(j) * S;
+    double g = 0.0;
+    for (int s = 0; s < S; ++s) g += 2.0 * w[s] * (yi[s] * dj[s] + ui[s] * rj[s]);
+    const double dodg = (i == j) ? gval[e] : sqrt(dinv[j]);
+    dout[e] = static_cast<float>(g * dodg);
+  }
+}
+
+// MLP backward: per-block partial gradients of sum_e do_e * o_e.  A block
+// takes chunks of BWC nonzeros: forward recompute into LDS, then thread t
+// owns parameters t, t + 256, ... and sums their contributions over the
+// chunk in a fixed order; partials accumulate in registers across chunks.
+constexpr int BWC = 128;
+constexpr int PPT = (NP + 255) / 256;  // parameters per thread
+
+__global__ __launch_bounds__(256) void k_mlp_backward(int64_t nnz, const int* lr, const int* lc,
+                                                      const double* lval, const float* Fz,
+                                                      const double* dinv, const float* P,
+                                                      const float* dout, double* part) {
+  __shared__ float sP[NP];
+  __shared__ float sx[BWC][NIN + 1];
+  __shared__ float sdp[BWC][NH + 1];  // dpre
+  __shared__ float sh[BWC][NH + 1];   // h
+  __shared__ float sdo[BWC];
+  load_params(P, sP);
+  double acc[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) acc[q] = 0.0;
+  const int64_t nchunk = (nnz + BWC - 1) / BWC;
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int64_t e0 = ch * BWC;
+    // forward recompute: threads 0..BWC-1 one nonzero each
+    if (threadIdx.x < BWC) {
+      const int64_t e = e0 + threadIdx.x;
+      float x[NIN];
+      float d = 0.0f;
+      if (e < nnz) {
+        make_input(Fz, dinv, lr[e], lc[e], lval[e], x);
+        d = dout[e];
+      } else {
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) x[f] = 0.0f;
+      }
+#pragma unroll
+      for (int f = 0; f < NIN; ++f) sx[threadIdx.x][f] = x[f];
+      sdo[threadIdx.x] = d;
+      for (int k = 0; k < NH; ++k) {
+        float pre = sP[OFF_B1 + k];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) pre += sP[k * NIN + f] * x[f];
+        const bool on = pre > 0.0f;
+        sh[threadIdx.x][k] = on ? pre : 0.0f;
+        sdp[threadIdx.x][k] = on ? d * sP[OFF_W2 + k] : 0.0f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = threadIdx.x + 256 * q;
+      if (p >= NP) continue;
+      float t = 0.0f;
+      if (p < OFF_B1) {
+        const int k = p / NIN, f = p % NIN;
+        for (int c = 0; c < BWC; ++c) t += sdp[c][k] * sx[c][f];
+      } else if (p < OFF_W2) {
+        const int k = p - OFF_B1;
+        for (int c = 0; c < BWC; ++c) t += sdp[c][k];
+      } else if (p < OFF_B2) {
+        const int k = p - OFF_W2;
+        for (int c = 0; c < BWC; ++c) t += sdo[c] * sh[c][k];
+      } else {
+        for (int c = 0; c < BWC; ++c) t += sdo[c];
+      }
+      acc[q] += static_cast<double>(t);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int p = threadIdx.x + 256 * q;
+    if (p < NP) part[static_cast<int64_t>(blockIdx.x) * NP + p] = acc[q];
+  }
+}
+
+__global__ void k_param_sum(int nblk, const double* part, double* grad) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < NP; p += gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += part[static_cast<int64_t>(b) * NP + p];
+    grad[p] = t;
+  }
+}
+
+__global__ void k_sum_small(int nblk, const double* part, double* out) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += part[b];
+  *out = t;
+}
+
+// Adam (Kingma and Ba), float32 parameters and moments, step count t >= 1
+__global__ void k_adam(float* P, float* m, float* v, const double* grad, int t, float lr, float b1,
+                       float b2, float eps) {
+  const float c1 = 1.0f - powf(b1, static_cast<float>(t));
+  const float c2 = 1.0f - powf(b2, static_cast<float>(t));
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < NP; p += gridDim.x * blockDim.x) {
+    const float g = static_cast<float>(grad[p]);
+    m[p] = b1 * m[p] + (1.0f - b1) * g;
+    v[p] = b2 * v[p] + (1.0f - b2) * g * g;
+    const float mh = m[p] / c1, vh = v[p] / c2;
+    P[p] -= lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+__global__ void k_to_rowmajor(int n, int S, const double* Xc, int64_t ldx, double* Xr) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+       t < static_cast<int64_t>(n) * S; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = t / S, s = t % S;
+    Xr[t] = Xc[s * ldx + i];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers --
+hipError_t mlp_features(int n, const int* rowptr, const int* col, const double* val, double* F,
+                        float* Fz, double* scratch, hipStream_t s) {
+  const int nb = std::min(g1(n), 1024);
+  double* part = scratch;              // nb * NF
+  double* mu = scratch + nb * NF;      // NF
+  double* sd = mu + NF;                // NF
+  hipLaunchKernelGGL(k_raw_features, dim3(g1(n)), dim3(256), 0, s, n, rowptr, col, val, F);
+  hipLaunchKernelGGL(k_feat_moments, dim3(nb), dim3(256), 0, s, n, F, nullptr, part);
+  hipLaunchKernelGGL(k_feat_stat, dim3(1), dim3(64), 0, s, nb, n, part, mu, 0);
+  hipLaunchKernelGGL(k_feat_moments, dim3(nb), dim3(256), 0, s, n, F, mu, part);
+  hipLaunchKernelGGL(k_feat_stat, dim3(1), dim3(64), 0, s, nb, n, part, sd, 1);
+  hipLaunchKernelGGL(k_feat_norm, dim3(g1(static_cast<int64_t>(n) * NF)), dim3(256), 0, s, n, F,
+                     mu, sd, Fz);
+  return hipGetLastError();
+}
+
+int mlp_scratch_doubles() { return 1024 * NF + 2 * NF; }
+
+hipError_t tril_count(int n, const int* rowptr, const int* col, int* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_tril_count, dim3(g1(n)), dim3(256), 0, s, n, rowptr, col, cnt);
+  return hipGetLastError();
+}
+
+hipError_t tril_fill(int n, const int* rowptr, const int* col, const double* val, const int* lrow,
+                     int* lcol, int* lr, double* lval, hipStream_t s) {
+  hipLaunchKernelGGL(k_tril_fill, dim3(g1(n)), dim3(256), 0, s, n, rowptr, col, val, lrow, lcol, lr,
+                     lval);
+  return hipGetLastError();
+}
+
+hipError_t mlp_forward(int64_t nnz, const int* lr, const int* lc, const double* lval,
+                       const float* Fz, const double* dinv, const float* P, double* gval,
+                       float* oval, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g1(nnz)), dim3(256), 0, s, nnz, lr, lc, lval, Fz, dinv, P,
+                     gval, oval);
+  return hipGetLastError();
+}
+
+int learn_blocks() { return 512; }
+
+// One evaluation of the loss and its gradient with respect to the MLP
+// parameters.  Rr, Er: row-major n x S pairs; G given by (Lrow, lc, gval)
+// and its transpose by (Trow, Tcol, perm) with values gval[perm].
+hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s) {
+  const int S = a.S;
+  const int nb = learn_blocks();
+  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
+                     a.Lrow, a.lc, a.gval, a.Rr, nullptr, a.Y);
+  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
+                     a.Trow, a.Tcol, a.gvalT, a.Y, a.Er, a.D);
+  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
+                     a.Lrow, a.lc, a.gval, a.D, nullptr, a.Uu);
+  hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, s, a.n, S, a.D, a.w, a.part);
+  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(64), 0, s, nb, a.part, a.loss);
+  hipLaunchKernelGGL(k_sddmm, dim3(g1(a.nnz)), dim3(256), 0, s, a.nnz, S, a.lr, a.lc, a.gval,
+                     a.dinv, a.Y, a.D, a.Uu, a.Rr, a.w, a.dout);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(nb), dim3(256), 0, s, a.nnz, a.lr, a.lc, a.lval, a.Fz,
+                     a.dinv, a.P, a.dout, a.part);
+  hipLaunchKernelGGL(k_param_sum, dim3(8), dim3(256), 0, s, nb, a.part, a.grad);
+  return hipGetLastError();
+}
+
+hipError_t learn_weights(int n, int S, const double* Er, double* part, double* w, hipStream_t s) {
+  const int nb = 256;
+  hipLaunchKernelGGL(k_colnorm_part, dim3(nb), dim3(256), 0, s, n, S, Er, part);
+  hipLaunchKernelGGL(k_weights, dim3(1), dim3(64), 0, s, nb, S, part, w);
+  return hipGetLastError();
+}
+
+hipError_t gather_values(int64_t nnz, const double* src, const double* permd, double* dst, hipStream_t s);
+
+hipError_t adam_step(float* P, float* m, float* v, const double* grad, int t, float lr,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(8), dim3(256), 0, s, P, m, v, grad, t, lr, 0.9f, 0.999f, 1e-8f);
+  return hipGetLastError();
+}
+
+hipError_t to_rowmajor(int n, int S, const double* Xc, int64_t ldx, double* Xr, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_rowmajor, dim3(g1(static_cast<int64_t>(n) * S)), dim3(256), 0, s, n, S,
+                     Xc, ldx, Xr);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void k_gather(int64_t nnz, const double* src, const double* permd, double* dst) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < nnz;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[t] = src[static_cast<int64_t>(permd[t])];
+}
+__global__ void k_iota(int64_t nnz, double* x) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < nnz;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    x[t] = static_cast<double>(t);
+}
+}  // namespace
+
+hipError_t gather_values(int64_t nnz, const double* src, const double* permd, double* dst,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(g1(nnz)), dim3(256), 0, s, nnz, src, permd, dst);
+  return hipGetLastError();
+}
+
+hipError_t iota_values(int64_t nnz, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(g1(nnz)), dim3(256), 0, s, nnz, x);
+  return hipGetLastError();
+}
+
+}  // namespace trplk

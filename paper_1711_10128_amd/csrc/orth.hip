@@ -170,6 +170,77 @@ __global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
   }
 }
 
+// Update-only pass: wout = w - U h (+ ||wout||^2).  Without dot products
+// no cross-wavefront exchange is needed: every lane owns UPD_RPL rows and
+// streams all columns for them, with h staged in LDS.
+constexpr int UPD_THREADS = 256;
+constexpr int UPD_RPL = 4;
+
+__global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
+  if (a.state && a.state->skip) return;
+  const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
+  __shared__ double hs[ORTH_MAXCOL];
+  __shared__ double red[UPD_THREADS / WAVE];
+  for (int c = threadIdx.x; c < ncol; c += UPD_THREADS) hs[c] = a.h[c];
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int64_t ld = a.ld;
+  const int n = a.n;
+  constexpr int TILE = WAVE * UPD_RPL;
+  const int ntile = (n + TILE - 1) / TILE;
+  double nacc = 0.0;
+  for (int tile = blockIdx.x * (UPD_THREADS / WAVE) + wv; tile < ntile;
+       tile += gridDim.x * (UPD_THREADS / WAVE)) {
+    const int base = tile * TILE + lane;
+    double part[UPD_RPL];
+#pragma unroll
+    for (int r = 0; r < UPD_RPL; ++r) part[r] = 0.0;
+    int c = 0;
+    for (; c + 4 <= ncol; c += 4) {
+      double u[4][UPD_RPL];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < UPD_RPL; ++r) {
+          const int row = base + WAVE * r;
+          u[q][r] = row < n ? a.Mu[(c + q) * ld + row] : 0.0;
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < UPD_RPL; ++r) part[r] += u[q][r] * hs[c + q];
+    }
+    for (; c < ncol; ++c) {
+#pragma unroll
+      for (int r = 0; r < UPD_RPL; ++r) {
+        const int row = base + WAVE * r;
+        part[r] += (row < n ? a.Mu[c * ld + row] : 0.0) * hs[c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < UPD_RPL; ++r) {
+      const int row = base + WAVE * r;
+      if (row < n) {
+        const double wn = a.w[row] - part[r];
+        a.wout[row] = wn;
+        if (a.wout32) a.wout32[row] = static_cast<float>(wn);
+        nacc += wn * wn;
+      }
+    }
+  }
+  if (a.norm) {
+    nacc = wave_sum(nacc);
+    if (lane == 0) red[wv] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < UPD_THREADS / WAVE; ++q) t += red[q];
+      a.partial[static_cast<int64_t>(blockIdx.x) * STRIDE] = t;
+    }
+  }
+}
+
 template <int CPW, int RPL>
 hipError_t launch_rpl(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(OT_THREADS);
@@ -439,6 +510,11 @@ int g_orth_maxblk = 0;  // 0: by pass
 
 int orth_blocks(int n, int mode) {
   const int nslab = (std::max(n, 1) + WAVE * 2 - 1) / (WAVE * 2);
+  if (mode == ORTH_UPD) {
+    const int tiles = (std::max(n, 1) + WAVE * UPD_RPL - 1) / (WAVE * UPD_RPL);
+    const int want = (tiles + UPD_THREADS / WAVE - 1) / (UPD_THREADS / WAVE);
+    return std::max(1, std::min(want, g_orth_maxblk > 0 ? g_orth_maxblk : 1024));
+  }
   const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : (mode == ORTH_DOT ? 256 : 512);
   return std::max(1, std::min(nslab, cap));
 }
@@ -448,6 +524,12 @@ int orth_blocks_max(int n) { return std::max(orth_blocks(n, ORTH_DOT), orth_bloc
 int orth_stride() { return STRIDE; }
 
 hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  if (mode == ORTH_UPD) {
+    const int nc = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
+    if (nc > ORTH_MAXCOL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_upd, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
   // columns a wavefront may own: ceil(max columns / 8)
   int need = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
   if (need > ORTH_MAXCOL) return hipErrorInvalidValue;

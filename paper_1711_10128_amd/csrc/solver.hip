@@ -119,6 +119,40 @@ struct trplk_ctx {
   std::string err;
   int64_t dev_bytes = 0;
   bool fp32_phase = false;
+  // learned factor: pattern of tril(A), its transpose, features, parameters
+  // and the training buffers (built on first use)
+  struct Learn {
+    bool ready = false;
+    bool pairs = false;
+    int S = 0;
+    int64_t nnz = 0;
+    int* Lrow = nullptr;
+    int* Lcol = nullptr;
+    int* lr = nullptr;
+    double* lval = nullptr;
+    int* Trow = nullptr;
+    int* Tcol = nullptr;
+    double* permd = nullptr;
+    double* dinv = nullptr;
+    double* F = nullptr;
+    float* Fz = nullptr;
+    double* gval = nullptr;
+    double* gvalT = nullptr;
+    float* P = nullptr;
+    float* am = nullptr;
+    float* av = nullptr;
+    double* Er = nullptr;
+    double* Rr = nullptr;
+    double* Y = nullptr;
+    double* D = nullptr;
+    double* Uu = nullptr;
+    double* w = nullptr;
+    float* dout = nullptr;
+    double* part = nullptr;
+    double* loss = nullptr;
+    double* grad = nullptr;
+    double* scratch = nullptr;
+  } L;
 };
 
 static std::string g_create_err;
@@ -886,7 +920,212 @@ int trplk_internal_set_factor(trplk_ctx* c, const trplk_csr* G, int32_t mem) {
   return finish_factor(c);
 }
 
+// ------------------------------------------------------- learned factor --
+namespace {
+
+int learn_prepare(trplk_ctx* c) {
+  auto& L = c->L;
+  if (L.ready) return TRPLK_OK;
+  const int n = c->n;
+  hipStream_t s = c->s;
+  int* cnt = nullptr;
+  HIPCHK(c, hipMalloc(&cnt, sizeof(int) * (n + 1)));
+  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(int) * (n + 1), s));
+  HIPCHK(c, tril_count(n, c->A.rowptr, c->A.col, cnt, s));
+  HIPCHK(c, dalloc(c, &L.Lrow, n + 1));
+  HIPCHK(c, exclusive_scan_i32(cnt, L.Lrow, n, s));
+  (void)hipFree(cnt);
+  int nnz = 0;
+  HIPCHK(c, hipMemcpyAsync(&nnz, L.Lrow + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  L.nnz = nnz;
+  HIPCHK(c, dalloc(c, &L.Lcol, nnz));
+  HIPCHK(c, dalloc(c, &L.lr, nnz));
+  HIPCHK(c, dalloc(c, &L.lval, nnz));
+  HIPCHK(c, tril_fill(n, c->A.rowptr, c->A.col, c->A.val, L.Lrow, L.Lcol, L.lr, L.lval, s));
+  // transpose of the pattern carrying the original positions
+  double* iota = nullptr;
+  HIPCHK(c, hipMalloc(&iota, sizeof(double) * std::max(nnz, 1)));
+  HIPCHK(c, iota_values(nnz, iota, s));
+  HIPCHK(c, csr_transpose(n, nnz, L.Lrow, L.Lcol, iota, &L.Trow, &L.Tcol, &L.permd, s));
+  (void)hipFree(iota);
+  c->dev_bytes += 16LL * nnz + 4LL * (n + 1);
+  // features need 1 / a_ii
+  int* bad = nullptr;
+  HIPCHK(c, dalloc(c, &L.dinv, n));
+  HIPCHK(c, hipMalloc(&bad, sizeof(int)));
+  HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(int), s));
+  HIPCHK(c, extract_diag_inv(n, c->A.rowptr, c->A.col, c->A.val, L.dinv, bad, s));
+  int hb = 0;
+  HIPCHK(c, hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  (void)hipFree(bad);
+  if (hb) return set_err(c, TRPLK_ENOTSPD, "learned factor: a diagonal entry is missing or <= 0");
+  HIPCHK(c, dalloc(c, &L.F, static_cast<int64_t>(n) * MLP_NF));
+  HIPCHK(c, dalloc(c, &L.Fz, static_cast<int64_t>(n) * MLP_NF));
+  HIPCHK(c, dalloc(c, &L.scratch, mlp_scratch_doubles()));
+  HIPCHK(c, mlp_features(n, c->A.rowptr, c->A.col, c->A.val, L.F, L.Fz, L.scratch, s));
+  HIPCHK(c, dalloc(c, &L.gval, nnz));
+  HIPCHK(c, dalloc(c, &L.gvalT, nnz));
+  HIPCHK(c, dalloc(c, &L.P, MLP_NPARAM));
+  HIPCHK(c, dalloc(c, &L.am, MLP_NPARAM));
+  HIPCHK(c, dalloc(c, &L.av, MLP_NPARAM));
+  HIPCHK(c, dalloc(c, &L.loss, 1));
+  HIPCHK(c, dalloc(c, &L.grad, MLP_NPARAM));
+  HIPCHK(c, dalloc(c, &L.part, static_cast<int64_t>(learn_blocks()) * MLP_NPARAM));
+  HIPCHK(c, hipStreamSynchronize(s));
+  L.ready = true;
+  return TRPLK_OK;
+}
+
+int learn_alloc_pairs(trplk_ctx* c) {
+  auto& L = c->L;
+  if (L.Er) return TRPLK_OK;
+  const int64_t nS = static_cast<int64_t>(c->n) * LEARN_MAXS;
+  HIPCHK(c, dalloc(c, &L.Er, nS));
+  HIPCHK(c, dalloc(c, &L.Rr, nS));
+  HIPCHK(c, dalloc(c, &L.Y, nS));
+  HIPCHK(c, dalloc(c, &L.D, nS));
+  HIPCHK(c, dalloc(c, &L.Uu, nS));
+  HIPCHK(c, dalloc(c, &L.w, LEARN_MAXS));
+  HIPCHK(c, dalloc(c, &L.dout, L.nnz));
+  return TRPLK_OK;
+}
+
+int learn_forward(trplk_ctx* c, const float* params_host) {
+  auto& L = c->L;
+  HIPCHK(c, hipMemcpyAsync(L.P, params_host, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->s));
+  HIPCHK(c, mlp_forward(L.nnz, L.lr, L.Lcol, L.lval, L.Fz, L.dinv, L.P, L.gval, nullptr, c->s));
+  HIPCHK(c, gather_values(L.nnz, L.gval, L.permd, L.gvalT, c->s));
+  return TRPLK_OK;
+}
+
+int learn_loss_grad_run(trplk_ctx* c) {
+  auto& L = c->L;
+  LearnArgs a;
+  a.n = c->n; a.nnz = L.nnz; a.S = L.S; a.Lrow = L.Lrow; a.lc = L.Lcol; a.lr = L.lr;
+  a.lval = L.lval; a.Trow = L.Trow; a.Tcol = L.Tcol; a.gval = L.gval; a.gvalT = L.gvalT;
+  a.Fz = L.Fz; a.dinv = L.dinv; a.P = L.P; a.Rr = L.Rr; a.Er = L.Er; a.w = L.w; a.Y = L.Y;
+  a.D = L.D; a.Uu = L.Uu; a.dout = L.dout; a.part = L.part; a.loss = L.loss; a.grad = L.grad;
+  HIPCHK(c, learn_loss_grad(a, c->s));
+  return TRPLK_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int trplk_learned_factor(trplk_ctx* c, const float* params) {
+  if (!c || !params) return set_err(c, TRPLK_EINVAL, "null argument");
+  int r;
+  if ((r = learn_prepare(c))) return r;
+  if ((r = learn_forward(c, params))) return r;
+  auto& L = c->L;
+  free_csr(c->G);
+  free_csr(c->Gt);
+  // the installed factor owns copies, so later training steps do not change it
+  const int n = c->n;
+  const int64_t nz = std::max<int64_t>(L.nnz, 1);
+  DevCsr* both[2] = {&c->G, &c->Gt};
+  const int* rp[2] = {L.Lrow, L.Trow};
+  const int* cl[2] = {L.Lcol, L.Tcol};
+  const double* vl[2] = {L.gval, L.gvalT};
+  for (int q = 0; q < 2; ++q) {
+    DevCsr& D = *both[q];
+    D.n = n;
+    D.nnz = L.nnz;
+    D.owned = true;
+    HIPCHK(c, dalloc(c, &D.rowptr, n + 1));
+    HIPCHK(c, dalloc(c, &D.col, nz));
+    HIPCHK(c, dalloc(c, &D.val, nz));
+    HIPCHK(c, hipMemcpyAsync(D.rowptr, rp[q], sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(D.col, cl[q], sizeof(int) * L.nnz, hipMemcpyDeviceToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(D.val, vl[q], sizeof(double) * L.nnz, hipMemcpyDeviceToDevice, c->s));
+  }
+  if (c->o.precision == TRPLK_MIXED) {
+    HIPCHK(c, dalloc(c, &c->G.val32, std::max<int64_t>(L.nnz, 1)));
+    HIPCHK(c, dalloc(c, &c->Gt.val32, std::max<int64_t>(L.nnz, 1)));
+    HIPCHK(c, cast_f32(L.nnz, c->G.val, c->G.val32, c->s));
+    HIPCHK(c, cast_f32(L.nnz, c->Gt.val, c->Gt.val32, c->s));
+  }
+  HIPCHK(c, spmv_plan(c->G.plan, c->n, c->G.rowptr, 0, c->s));
+  HIPCHK(c, spmv_plan(c->Gt.plan, c->n, c->Gt.rowptr, 0, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  c->prec = TRPLK_PREC_FACTOR;
+  return TRPLK_OK;
+}
+
+int64_t trplk_factor_nnz(trplk_ctx* c) {
+  if (!c) return -1;
+  if (learn_prepare(c)) return -1;
+  return c->L.nnz;
+}
+
+int trplk_factor_values(trplk_ctx* c, double* val, int32_t mem) {
+  if (!c || !val) return set_err(c, TRPLK_EINVAL, "null argument");
+  if (!c->L.ready) return set_err(c, TRPLK_EINVAL, "no learned factor");
+  HIPCHK(c, hipMemcpyAsync(val, c->L.gval, sizeof(double) * c->L.nnz,
+                           mem == TRPLK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return TRPLK_OK;
+}
+
+int trplk_factor_loss_grad(trplk_ctx* c, const float* params, int32_t S, const double* E,
+                           const double* R, int32_t mem, double* loss, double* grad) {
+  if (!c || !params || !E || !R || !loss || !grad) return set_err(c, TRPLK_EINVAL, "null argument");
+  if (S < 1 || S > LEARN_MAXS) return set_err(c, TRPLK_EINVAL, "S must be in 1..32");
+  int r;
+  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
+  auto& L = c->L;
+  const int n = c->n;
+  const int64_t nS = static_cast<int64_t>(n) * S;
+  const hipMemcpyKind k = mem == TRPLK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  // column-major inputs staged through D / Uu, then transposed
+  HIPCHK(c, hipMemcpyAsync(L.D, E, sizeof(double) * nS, k, c->s));
+  HIPCHK(c, hipMemcpyAsync(L.Uu, R, sizeof(double) * nS, k, c->s));
+  HIPCHK(c, to_rowmajor(n, S, L.D, n, L.Er, c->s));
+  HIPCHK(c, to_rowmajor(n, S, L.Uu, n, L.Rr, c->s));
+  L.S = S;
+  L.pairs = false;  // these pairs are not the solver's
+  HIPCHK(c, learn_weights(n, S, L.Er, L.part, L.w, c->s));
+  if ((r = learn_forward(c, params))) return r;
+  if ((r = learn_loss_grad_run(c))) return r;
+  HIPCHK(c, hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipMemcpyAsync(grad, L.grad, sizeof(double) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return TRPLK_OK;
+}
+
+int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, int32_t step,
+                     double lr, int32_t S, double* loss) {
+  if (!c || !params || !adam_m || !adam_v) return set_err(c, TRPLK_EINVAL, "null argument");
+  if (step < 1) return set_err(c, TRPLK_EINVAL, "step counts from 1");
+  if (S < 1 || S > LEARN_MAXS || S > c->m) return set_err(c, TRPLK_EINVAL, "S must be in 1..min(32, m)");
+  int r;
+  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
+  auto& L = c->L;
+  const int n = c->n;
+  if (!L.pairs || L.S != S) {
+    if (!c->solved) return set_err(c, TRPLK_EINVAL, "train_step harvests pairs from a completed solve");
+    // pairs (u, A u): the first S stored basis columns and their products
+    HIPCHK(c, to_rowmajor(n, S, c->W, c->ld, L.Er, c->s));
+    HIPCHK(c, to_rowmajor(n, S, c->AW, c->ld, L.Rr, c->s));
+    HIPCHK(c, learn_weights(n, S, L.Er, L.part, L.w, c->s));
+    L.S = S;
+    L.pairs = true;
+  }
+  if ((r = learn_forward(c, params))) return r;
+  if ((r = learn_loss_grad_run(c))) return r;
+  HIPCHK(c, hipMemcpyAsync(L.am, adam_m, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(L.av, adam_v, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->s));
+  HIPCHK(c, adam_step(L.P, L.am, L.av, L.grad, step, static_cast<float>(lr), c->s));
+  HIPCHK(c, hipMemcpyAsync(params, L.P, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipMemcpyAsync(adam_m, L.am, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipMemcpyAsync(adam_v, L.av, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return TRPLK_OK;
+}
 
 void trplk_default_opts(trplk_opts* o) {
   if (!o) return;
@@ -1001,6 +1240,7 @@ int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   }
   int r = ensure_workspace(c);
   if (r) return r;
+  c->L.pairs = false;
   Solver S{c, c->n, c->ld, c->s};
   c->stats.setup_ms = c->stats.setup_ms;
   const double setup = c->stats.setup_ms;
@@ -1093,6 +1333,11 @@ void trplk_destroy(trplk_ctx* c) {
                   c->y32, c->wtmp32, c->Xprev, c->T, c->theta, c->Y, c->hbuf, c->partial,
                   c->resout, c->st, c->rep_d};
   for (void* p : ptrs) dfree(p);
+  auto& L = c->L;
+  void* lp[] = {L.Lrow, L.Lcol, L.lr, L.lval, L.Trow, L.Tcol, L.permd, L.dinv, L.F, L.Fz,
+                L.gval, L.gvalT, L.P, L.am, L.av, L.Er, L.Rr, L.Y, L.D, L.Uu, L.w, L.dout,
+                L.part, L.loss, L.grad, L.scratch};
+  for (void* p : lp) dfree(p);
   if (c->rep_h) (void)hipHostFree(c->rep_h);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

@@ -3,8 +3,9 @@
 // T is at most 64 x 64 (the maximum basis size), so one workgroup holds T
 // and the accumulated rotations in LDS and runs the cyclic two-sided Jacobi
 // method with the round-robin (tournament) ordering: in each round b/2
-// disjoint index pairs are rotated at once, first on rows, then on columns
-// and on the eigenvector matrix, with a barrier between the phases.  Sweeps
+// disjoint index pairs are rotated at once; since the rotations of a round
+// commute, J^T A J splits into independent 2 x 2 blocks, so a round is one
+// parameter phase and one update phase.  Sweeps
 // repeat until the off-diagonal Frobenius norm falls below 1e-15 of the
 // matrix norm.  The rotation angle follows the symmetric 2 x 2 Schur
 // decomposition of Golub and Van Loan (Sec. 8.5.2).  Eigenvalues are
@@ -105,35 +106,33 @@ __global__ __launch_bounds__(NT) void k_syev(const double* T, int ldT, int b_fix
         cs[tid][1] = s;
       }
       __syncthreads();
-      // rows p, q <- J^T A
-      for (int t = tid; t < half * be; t += NT) {
-        const int i = t / be, j = t % be;
-        const int p = pr[i][0], q = pr[i][1];
-        const double c = cs[i][0], s = cs[i][1];
-        const double ap = A[p * LDA + j], aq = A[q * LDA + j];
-        A[p * LDA + j] = c * ap - s * aq;
-        A[q * LDA + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns p, q <- A J, and V <- V J
-      for (int t = tid; t < half * be; t += NT) {
-        const int i = t / be, j = t % be;
-        const int p = pr[i][0], q = pr[i][1];
-        const double c = cs[i][0], s = cs[i][1];
-        const double ap = A[j * LDA + p], aq = A[j * LDA + q];
-        A[j * LDA + p] = c * ap - s * aq;
-        A[j * LDA + q] = s * ap + c * aq;
-        const double vp = V[j * LDA + p], vq = V[j * LDA + q];
-        V[j * LDA + p] = c * vp - s * vq;
-        V[j * LDA + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      if (tid < half) {
-        const int p = pr[tid][0], q = pr[tid][1];
-        if (cs[tid][1] != 0.0) {
-          A[p * LDA + q] = 0.0;
-          A[q * LDA + p] = 0.0;
+      // All rotations of the round commute (disjoint index pairs), so
+      // A <- J^T A J splits into independent 2 x 2 blocks: block (i, j) holds
+      // rows {p_i, q_i} and columns {p_j, q_j}.  V <- V J updates column pairs.
+      for (int t = tid; t < half * half; t += NT) {
+        const int i = t / half, j = t % half;
+        const int p = pr[i][0], q = pr[i][1], u = pr[j][0], v = pr[j][1];
+        const double ci = cs[i][0], si = cs[i][1], cj = cs[j][0], sj = cs[j][1];
+        const double apu = A[p * LDA + u], apv = A[p * LDA + v];
+        const double aqu = A[q * LDA + u], aqv = A[q * LDA + v];
+        const double bpu = ci * apu - si * aqu, bpv = ci * apv - si * aqv;
+        const double bqu = si * apu + ci * aqu, bqv = si * apv + ci * aqv;
+        A[p * LDA + u] = cj * bpu - sj * bpv;
+        A[p * LDA + v] = sj * bpu + cj * bpv;
+        A[q * LDA + u] = cj * bqu - sj * bqv;
+        A[q * LDA + v] = sj * bqu + cj * bqv;
+        if (i == j && si != 0.0) {  // the annihilated pair
+          A[p * LDA + v] = 0.0;
+          A[q * LDA + u] = 0.0;
         }
+      }
+      for (int t = tid; t < half * be; t += NT) {
+        const int j = t / be, row = t % be;
+        const int u = pr[j][0], v = pr[j][1];
+        const double cj = cs[j][0], sj = cs[j][1];
+        const double vu = V[row * LDA + u], vv = V[row * LDA + v];
+        V[row * LDA + u] = cj * vu - sj * vv;
+        V[row * LDA + v] = sj * vu + cj * vv;
       }
       __syncthreads();
     }

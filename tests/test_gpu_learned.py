@@ -1,0 +1,109 @@
+"""Learned factor on the GPU against the CPU oracle (forward values,
+loss and gradient), its Jacobi special case, and what training buys."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import precond as PC  # noqa: E402
+from oracle import trplk as O  # noqa: E402
+from workloads import make, start_block  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_10128_amd as T
+    T.lib()
+    return T
+
+
+def _params(T, seed, scale_w2=0.3):
+    P0 = PC.init_params(seed=seed, zero_last=False)
+    P0["w2"] = P0["w2"] * scale_w2
+    P0["b1"] = np.random.default_rng(seed + 1).standard_normal(PC.NHID) * 0.1
+    P = T.pack_params(P0["W1"], P0["b1"], P0["w2"], 0.05)
+    # the oracle evaluates exactly the float32-rounded parameters
+    return P, T.unpack_params(P)
+
+
+@pytest.mark.parametrize("name,kw", [("powerlaw", dict(n=2000)), ("lap3d", dict(N=10)),
+                                     ("fem3d", dict(Ne=7))])
+def test_forward_matches_oracle(T, name, kw):
+    P = make(name, "small", **kw)
+    A = P.A.to_scipy()
+    Pg, Pd = _params(T, 3)
+    s = T.Solver(P.A, None, p=2, m=10, k=4, precond="jacobi")
+    s.learned_factor(Pg)
+    g = s.factor_values()
+    o, _ = PC.mlp_forward(Pd, PC.mlp_inputs(A))
+    ref = PC.assemble_G(A, o).data
+    assert g.shape == ref.shape
+    assert np.all(np.abs(g - ref) <= 2e-5 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    s.close()
+
+
+def test_zero_output_layer_is_jacobi(T):
+    P = make("powerlaw", "small", n=1500, p=4, m=16, k=8)
+    A = P.A.to_scipy()
+    X0 = start_block(P.A.n, 8, 12)
+    s = T.Solver(P.A, None, p=4, m=16, k=8, precond="jacobi")
+    s.learned_factor(T.init_params(0))
+    g = s.factor_values()
+    L = __import__("scipy.sparse", fromlist=["tril"]).tril(A, format="csr")
+    L.sort_indices()
+    diag = np.repeat(np.arange(A.shape[0]), np.diff(L.indptr)) == L.indices
+    assert np.all(g[~diag] == 0.0)
+    assert np.allclose(g[diag], 1.0 / np.sqrt(A.diagonal()), rtol=1e-15)
+    st = s.solve(X0)
+    ev = s.eigpairs()[0]
+    sj = T.Solver(P.A, None, p=4, m=16, k=8, precond="jacobi")
+    stj = sj.solve(X0)
+    evj = sj.eigpairs()[0]
+    assert st["cycles"] == stj["cycles"]
+    assert np.allclose(ev, evj, rtol=1e-12)
+
+
+@pytest.mark.parametrize("S", [1, 5, 24])
+def test_loss_gradient_matches_oracle(T, S):
+    P = make("powerlaw", "small", n=1200)
+    A = P.A.to_scipy()
+    rng = np.random.default_rng(S)
+    E = rng.standard_normal((A.shape[0], S))
+    R = A @ E
+    Pg, Pd = _params(T, 7)
+    s = T.Solver(P.A, None, p=2, m=10, k=4)
+    loss, grad = s.factor_loss_grad(Pg, E, R)
+    Lr, gr, _ = PC.loss_and_grad_params(Pd, A, R, E)
+    gref = np.concatenate([gr["W1"].ravel(), gr["b1"], gr["w2"], [float(gr["b2"])]])
+    print(f"  loss gpu {loss:.10e} oracle {Lr:.10e}; |dgrad|/|grad| = "
+          f"{np.linalg.norm(grad - gref) / np.linalg.norm(gref):.2e}", flush=True)
+    assert abs(loss - Lr) <= 1e-5 * abs(Lr)
+    assert np.linalg.norm(grad - gref) <= 1e-4 * np.linalg.norm(gref)
+
+
+def test_training_gains_over_jacobi_on_held_out_graphs(T):
+    """Train on 4 power-law graphs with pairs from the solver's own bases;
+    on 2 held-out graphs the learned factor needs fewer products than Jacobi."""
+    kw = dict(p=8, m=24, k=12, l=1, tol=1e-6)
+    train = [make("powerlaw", "small", n=3000, seed=12 + i, **kw) for i in range(4)]
+    test = [make("powerlaw", "small", n=3000, seed=40 + i, **kw) for i in range(2)]
+    solvers = [T.Solver(P.A, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, max_cycles=400)
+               for P in train]
+    X0s = [start_block(P.A.n, P.k, 12) for P in train]
+    Pm, hist = T.train(solvers, X0s, epochs=150, lr=1e-3, S=24)
+    print(f"  loss {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
+    assert hist[-1] < 0.7 * hist[0]
+    for P in test:
+        X0 = start_block(P.A.n, P.k, 99)
+        sj = T.Solver(P.A, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=1e-8)
+        stj = sj.solve(X0)
+        sl = T.Solver(P.A, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=1e-8)
+        sl.learned_factor(Pm)
+        stl = sl.solve(X0)
+        evj, evl = sj.eigpairs()[0], sl.eigpairs()[0]
+        print(f"  held-out: jacobi {stj['matvecs']} MV, learned {stl['matvecs']} MV", flush=True)
+        assert stl["matvecs"] < stj["matvecs"]
+        assert np.allclose(evj, evl, rtol=1e-9)
