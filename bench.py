@@ -6,9 +6,11 @@ apply, inner Krylov loop with full B-reorthogonalisation, +K augmentation,
 Rayleigh-Ritz, thick restart and locking) from the same seeded start block,
 on a matrix already resident in HBM.
 
-Workload (default): 3-D 7-point Laplacian on 128^3 plus a random diagonal
+Default workload: 3-D 7-point Laplacian on 128^3 plus a random diagonal
 potential U[0, 0.05] (n = 2,097,152, nnz = 14,581,760), p = 10, m = 40,
-k = 20, l = 1, tol = 1e-8 * ||A||_inf.  Prints one JSON line.
+k = 20, l = 1, tol = 1e-8 * ||A||_inf, Jacobi, float64.  --workload selects
+the other four (2-D Laplacian 64^2, Q1 FEM pencil 97^3, power-law graph
+n = 1e6, anisotropic diffusion 256^3).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,18 +28,73 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+# workload name -> generator arguments, solver sizes, timed (precond, precision)
+WORKLOADS = {
+    "lap2d": dict(gen=dict(N=64), p=5, m=20, k=8, form=("jacobi", "fp64"),
+                  desc="2-D 5-point Laplacian 64^2"),
+    "lap3d": dict(gen=dict(N=128, vmax=0.05), p=10, m=40, k=20, form=("jacobi", "fp64"),
+                  desc="3-D 7-point Laplacian 128^3 + V~U[0,0.05]"),
+    "fem3d": dict(gen=dict(Ne=97, sigma=0.5), p=16, m=48, k=24, form=("fsai", "mixed"),
+                  desc="Q1 FEM pencil 97^3 elements, lognormal sigma=0.5, consistent mass"),
+    "powerlaw": dict(gen=dict(n=1_000_000), p=20, m=48, k=24, form=("learned", "fp64"),
+                     desc="shifted Laplacian of a Chung-Lu power-law graph, n=1e6"),
+    "aniso3d": dict(gen=dict(N=256, sigma=1.0), p=50, m=64, k=32, form=("learned", "mixed"),
+                    desc="anisotropic 7-point diffusion 256^3, lognormal sigma=1"),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--N", type=int, default=128, help="grid edge of the 3-D workload")
-    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "fsai", "none"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--variants", type=int, default=1, help="also time the FSAI and mixed forms")
+    ap.add_argument("--workload", default="lap3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--size", type=int, default=0,
+                    help="override the grid edge / node count (0 = the workload's own size)")
+    ap.add_argument("--precond", default="", help="timed form's preconditioner (default per workload)")
+    ap.add_argument("--precision", default="", choices=["", "fp64", "mixed"])
+    ap.add_argument("--variants", type=int, default=1, help="also time the other forms once")
     ap.add_argument("--cpu-cycles", type=int, default=1, help="oracle cycles in the CPU sample (0 = skip)")
+    ap.add_argument("--train-count", type=int, default=6, help="learned factor: training instances")
+    ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--profile-only", action="store_true", help="one profiled solve (for rocprofv3 runs)")
     return ap.parse_args()
+
+
+def make_workload(name, size, seed=12):
+    from workloads import make
+    W = WORKLOADS[name]
+    gen = dict(W["gen"])
+    if size:
+        key = {"lap2d": "N", "lap3d": "N", "fem3d": "Ne", "powerlaw": "n", "aniso3d": "N"}[name]
+        gen[key] = size
+    return make(name, "full", seed=seed, p=W["p"], m=W["m"], k=W["k"], l=1, tol=1e-8, **gen)
+
+
+def train_factor(T, name, args, log):
+    """Train the learned factor on smaller instances of the same generator
+    (seeds 12, 13, ...), harvesting pairs from Jacobi solves on the GPU."""
+    from workloads import start_block
+    W = WORKLOADS[name]
+    default_small = {"powerlaw": 200_000, "aniso3d": 48, "lap3d": 48, "fem3d": 33, "lap2d": 48}
+    size = args.train_size or default_small[name]
+    solvers, X0s = [], []
+    for i in range(args.train_count):
+        P = make_workload(name, size, seed=12 + i)
+        solvers.append(T.Solver(P.A, P.B, p=min(P.p, P.k), m=P.m, k=P.k, l=1, tol=1e-6,
+                                precond="jacobi", max_cycles=300))
+        X0s.append(start_block(P.A.n, P.k, 12 + i))
+    t0 = time.time()
+    # pairs: every stored basis column (the kept Ritz vectors and the last
+    # cycle's Krylov vectors), so the loss sees the whole spectrum
+    params, hist = T.train(solvers, X0s, epochs=args.epochs, lr=1e-3, S=min(64, W["m"]))
+    for s in solvers:
+        s.close()
+    log(f"# trained on {args.train_count} x {name}(size {size}) in {time.time() - t0:.1f}s: "
+        f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    return params, {"train_instances": args.train_count, "train_size": size,
+                    "epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1]}
 
 
 def main():
@@ -49,25 +106,40 @@ def main():
     import torch
 
     import paper_1711_10128_amd as T
-    from workloads import make, start_block
+    from workloads import start_block
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    W = WORKLOADS[args.workload]
+    precond = args.precond or W["form"][0]
+    precision = args.precision or W["form"][1]
     t0 = time.time()
-    P = make("lap3d", "full", N=args.N, vmax=0.05, p=10, m=40, k=20, l=1, tol=1e-8)
+    P = make_workload(args.workload, args.size)
     X0 = start_block(P.A.n, P.k, P.seed)
-    gen_s = time.time() - t0
-    print(f"# workload lap3d N={args.N} n={P.A.n} nnz={P.A.nnz} generated in {gen_s:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"# workload {args.workload} n={P.A.n} nnz={P.A.nnz} generated in {time.time() - t0:.1f}s")
     Ad = T.DeviceCSR(P.A)
+    Bd = T.DeviceCSR(P.B) if P.B is not None else None
     Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
     torch.cuda.synchronize()
 
-    def make_solver(precond, precision, profile=False):
-        return T.Solver(Ad, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=precond,
-                        precision=precision, profile=profile)
+    learned = None
+    learn_info = None
+    need_learned = precond == "learned" or (args.variants and args.workload in ("powerlaw", "aniso3d", "lap3d"))
+    if need_learned:
+        learned, learn_info = train_factor(T, args.workload, args, log)
+
+    def make_solver(pc, pr, profile=False):
+        base = "jacobi" if pc == "learned" else pc
+        s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
+                     precision=pr, profile=profile)
+        if pc == "learned":
+            s.learned_factor(learned)
+        return s
 
     # ---- timed region: K solves of the selected form ----
-    S = make_solver(args.precond, args.precision)
+    S = make_solver(precond, precision)
     if args.profile_only:
         st = S.solve(Xd)
         torch.cuda.synchronize()
@@ -86,16 +158,26 @@ def main():
     st = stats[-1]
     ev, X, res, conv = S.eigpairs(vectors=False)
     normA = st["normA"]
-    assert conv.all() and np.all(res <= P.tol * normA * 1.001), "solve did not converge"
-    # eigenvalues against the closed form bounds: lambda(A0) <= lambda <= lambda(A0) + 0.05
-    i = np.arange(1, args.N + 1)
-    s1 = 4 * np.sin(i * np.pi / (2 * (args.N + 1))) ** 2
-    lam0 = np.sort((s1[:, None, None] + s1[None, :, None] + s1[None, None, :]).ravel())[:P.p]
-    weyl_ok = bool(np.all(ev >= lam0 - 1e-12) and np.all(ev <= lam0 + 0.05 + 1e-12))
+    converged = bool(conv.all() and np.all(res <= P.tol * normA * 1.001))
+    checks = {}
+    if args.workload == "lap3d":
+        N = P.meta["N"]
+        i = np.arange(1, N + 1)
+        s1 = 4 * np.sin(i * np.pi / (2 * (N + 1))) ** 2
+        lam0 = np.sort((s1[:, None, None] + s1[None, :, None] + s1[None, None, :]).ravel())[:P.p]
+        checks["eigs_within_weyl_bounds"] = bool(np.all(ev >= lam0 - 1e-12) and np.all(ev <= lam0 + 0.05 + 1e-12))
+    if args.workload == "lap2d":
+        N = P.meta["N"]
+        i = np.arange(1, N + 1)
+        s1 = 4 * np.sin(i * np.pi / (2 * (N + 1))) ** 2
+        lam = np.sort((s1[:, None] + s1[None, :]).ravel())[:P.p]
+        checks["max_rel_err_vs_closed_form"] = float(np.max(np.abs(ev - lam) / lam))
+    if args.workload == "powerlaw":
+        checks["lambda1_minus_shift_rel"] = float(abs(ev[0] - 0.01) / 0.01)
     S.close()
 
     # ---- kernel profile of the same solve (HIP events around each launch) ----
-    Sp = make_solver(args.precond, args.precision, profile=True)
+    Sp = make_solver(precond, precision, profile=True)
     sp = Sp.solve(Xd)
     Sp.close()
     classes = {}
@@ -119,14 +201,16 @@ def main():
         g = spmv["GBs"]
         spmv_roof = {"achieved": round(g, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(g / HBM_PEAK_GBS, 4), "launches": spmv["launches"],
-                     "avg_launch_us": round(spmv["ms"] / spmv["launches"] * 1e3, 2),
-                     "note": "working set 217 MB fits the 256 MB MALL"}
+                     "avg_launch_us": round(spmv["ms"] / spmv["launches"] * 1e3, 2)}
 
-    # ---- other forms (one untimed-contract solve each) ----
+    # ---- other forms (one warm solve each, outside the timed region) ----
     variants = {}
     if args.variants:
-        for pc, pr in (("jacobi", "fp64"), ("fsai", "fp64"), ("fsai", "mixed"), ("jacobi", "mixed")):
-            if (pc, pr) == (args.precond, args.precision):
+        forms = [("jacobi", "fp64"), ("fsai", "fp64"), ("fsai", "mixed"), ("jacobi", "mixed")]
+        if learned is not None:
+            forms += [("learned", "fp64"), ("learned", "mixed")]
+        for pc, pr in forms:
+            if (pc, pr) == (precond, precision):
                 continue
             V = make_solver(pc, pr)
             V.solve(Xd)
@@ -141,26 +225,26 @@ def main():
                 "s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
                 "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
                 "max_resid_rel": float(np.max(rv) / normA),
-                "max_rel_eig_diff_vs_main": float(np.max(np.abs(evv - ev) / np.abs(ev)))}
+                "max_rel_eig_diff_vs_timed": float(np.max(np.abs(evv - ev) / np.abs(ev)))}
 
     # ---- CPU oracle sample: a few cycles of the FP64 NumPy/SciPy oracle ----
     cpu = None
     if args.cpu_cycles > 0:
         from oracle import trplk as O
         A = P.A.to_scipy()
+        B = None if P.B is None else P.B.to_scipy()
         cores = len(os.sched_getaffinity(0))
         c0 = time.perf_counter()
-        r = O.solve(A, None, P.p, P.m, P.k, P.l, P.tol, X0,
-                    apply_M=O.jacobi(A) if args.precond == "jacobi" else None,
+        r = O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=O.jacobi(A),
                     max_cycles=args.cpu_cycles)
         c1 = time.perf_counter()
         per_cycle = (c1 - c0) / r.cycles
         cpu = {"value": round(per_cycle * st["cycles"], 2), "unit": "s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{r.cycles} oracle cycles (plus its start-block Rayleigh-Ritz) on the same "
-                         f"input took {c1 - c0:.1f} s; scaled by the {st['cycles']} cycles the GPU "
-                         f"needed (the oracle runs the same cycle count at smaller sizes). NumPy "
-                         f"BLAS threads = {cores}; SciPy SpMV single-threaded",
+               "sample": f"{r.cycles} cycle(s) of the FP64 oracle (Jacobi, plus its start-block "
+                         f"Rayleigh-Ritz) on the same input took {c1 - c0:.1f} s; value = that per-cycle "
+                         f"time x the {st['cycles']} cycles of the timed GPU form. NumPy BLAS "
+                         f"threads = {cores}; SciPy SpMV single-threaded",
                "per_cycle_s": round(per_cycle, 3)}
 
     out = {
@@ -174,21 +258,26 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"lap3d {args.N}^3 7-point + V~U[0,0.05], p=10 m=40 k=20 l=1 "
-                               f"tol=1e-8 {args.precond} {args.precision}",
-                   "n": P.A.n, "nnz": P.A.nnz},
+        "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l=1 tol=1e-8, "
+                               f"{precond} {precision}",
+                   "name": args.workload, "n": P.A.n, "nnz": P.A.nnz,
+                   "generalized": P.B is not None},
+        "converged": converged,
         "matvecs": st["matvecs"],
+        "bmatvecs": st["bmatvecs"],
         "cycles": st["cycles"],
         "device_solve_ms": round(st["solve_ms"], 3),
+        "setup_ms": round(st["setup_ms"], 3),
         "max_resid_rel": float(np.max(res) / normA),
-        "eigs_within_weyl_bounds": weyl_ok,
+        "checks": checks,
         "roofline": roofline,
         "spmv_roofline": spmv_roof,
         "kernel_classes": {k: {kk: (round(v, 3) if isinstance(v, float) else v)
                                for kk, v in c.items()} for k, c in classes.items()},
         "variants": variants,
+        "learned": learn_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

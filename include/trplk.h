@@ -94,6 +94,9 @@ typedef struct trplk_opts {
   int32_t profile;    /* 1 = time the SpMV and orthogonalisation kernels with HIP events */
   double mixed_switch; /* MIXED: switch SpMV to float64 once all target residuals are below
                           mixed_switch * ||A||; 0 selects the default 1e-5 */
+  int32_t fallback_window; /* FSAI / FACTOR: when the target residual has not halved for this
+                              many cycles, continue with Jacobi (M may change between cycles,
+                              Sec. 3); 0 selects 50, negative disables */
 } trplk_opts;
 
 typedef struct trplk_stats {
@@ -104,6 +107,8 @@ typedef struct trplk_stats {
   int64_t precs;       /* preconditioner applications */
   int32_t fp32_cycles; /* cycles that used the float32 SpMV (MIXED) */
   int32_t status;      /* TRPLK_OK or TRPLK_ENOCONV */
+  int32_t fallback_cycle; /* cycle at which the preconditioner fell back to Jacobi, 0 = never */
+  int32_t pad_;
   double normA;        /* the ||A|| used in the stopping test */
   double solve_ms;     /* device time of trplk_solve (HIP events on the context stream) */
   double setup_ms;     /* device time of trplk_create's preconditioner setup */
@@ -179,8 +184,10 @@ int64_t trplk_factor_nnz(trplk_ctx* ctx);
  * tril(A) (trplk_factor_nnz entries). */
 int trplk_factor_values(trplk_ctx* ctx, double* val, int32_t mem);
 
-/* Loss L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2 over the pairs
- * (E, R) (n x S, column-major, S <= 32, host or device per `mem`) and its
+/* Loss L = (1/S) sum_s [1 - <M r_s, e_s>^2 / (||M r_s||^2 ||e_s||^2)], M = G^T G
+ * (the squared sine of the angle between the preconditioned residual and the
+ * correction; the inner Krylov space is invariant to the scale of M r), over
+ * the pairs (E, R) (n x S, column-major, S <= 64, host or device per `mem`) and its
  * gradient with respect to the MLP parameters (grad: host, TRPLK_MLP_NPARAM
  * doubles), computed by the training kernels (float32 network, float64 pair
  * algebra, fixed-order reductions). */
@@ -189,7 +196,8 @@ int trplk_factor_loss_grad(trplk_ctx* ctx, const float* params, int32_t S, const
 
 /* One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the
  * pairs (u, A u) the last trplk_solve on this context left in its basis (the
- * first S <= min(m, 32) stored columns and their products).  params,
+ * first S <= min(m, 64) stored columns and their products: the kept Ritz
+ * vectors followed by the last cycle's inner Krylov vectors).  params,
  * adam_m, adam_v: host arrays of TRPLK_MLP_NPARAM floats, updated in place;
  * step: Adam step count (>= 1); loss: optional output (before the update).
  * Call it on several contexts in turn to train on several problems. */

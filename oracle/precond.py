@@ -19,8 +19,14 @@ Learned factor: a two-layer MLP maps features of each lower-triangular
 nonzero (i, j) to a scalar o_ij.  G[i, i] = exp(o_ii) / sqrt(a_ii) and
 G[i, j] = o_ij / sqrt(a_jj) for j < i, so G has a positive diagonal (M is SPD
 by construction) and a zero output layer gives G = D^{-1/2}, i.e. M equals
-the Jacobi preconditioner.  The loss over pairs (r_s, e_s) = (A u_s, u_s) is
-L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2.
+the Jacobi preconditioner.  The loss over pairs (r_s, e_s) = (A u_s, u_s)
+from the solver's basis is the mean squared sine of the angle between the
+preconditioned residual M r_s and e_s,
+L = (1/S) sum_s [1 - <M r_s, e_s>^2 / (||M r_s||^2 ||e_s||^2)],
+which does not depend on the scale of M r_s: the Krylov space the inner
+iteration builds from C = (I - X X^T B) M (A - rho B) (Sec. 3) depends on M
+only up to a scalar per vector, so an absolute-scale target (M A = I) would
+ask for gains the sparse factor cannot give on the low modes.
 """
 from __future__ import annotations
 
@@ -177,24 +183,26 @@ def assemble_G(A, o):
 
 
 def loss_and_grad_G(G, R, E):
-    """Loss L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2 and dL/dG on G's pattern.
+    """Angle loss L and dL/dG on G's pattern (values in G's CSR order).
 
-    R, E are n x S (columns are the pairs).  The gradient of one pair is
-    (2 / ||e||^2) (y d^T + u r^T) with y = G r, d = G^T y - e, u = G d,
-    restricted to the nonzeros of G.  Returns (L, gradient values in G's CSR
-    order).
+    R, E are n x S (columns are the pairs).  With y = G r, q = G^T y = M r,
+    a = <q, e>, b = ||q||^2, c = ||e||^2 the pair's loss is 1 - a^2/(b c) and
+    its gradient is y z^T + (G z) r^T with
+    z = (-2 a / (b c) e + 2 a^2 / (b^2 c) q) / S, restricted to the nonzeros.
     """
     G = sp.csr_matrix(G)
     S = R.shape[1]
     Y = G @ R
-    D = G.T @ Y - E
-    Uu = G @ D
-    en = np.sum(E * E, axis=0)
-    L = float(np.sum(np.sum(D * D, axis=0) / en)) / S
-    wgt = 2.0 / (en * S)
+    Q = G.T @ Y
+    a = np.sum(Q * E, axis=0)
+    b = np.sum(Q * Q, axis=0)
+    c = np.sum(E * E, axis=0)
+    L = float(np.mean(1.0 - a * a / (b * c)))
+    Z = ((-2.0 * a / (b * c))[None, :] * E + (2.0 * a * a / (b * b * c))[None, :] * Q) / S
+    Uz = G @ Z
     r = np.repeat(np.arange(G.shape[0]), np.diff(G.indptr))
-    c = G.indices
-    grad = np.sum((Y[r] * D[c] + Uu[r] * R[c]) * wgt[None, :], axis=1)
+    col = G.indices
+    grad = np.sum(Y[r] * Z[col] + Uz[r] * R[col], axis=1)
     return L, grad
 
 

@@ -41,14 +41,15 @@ class _Opts(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("locking", ctypes.c_int32),
                 ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("mixed_switch", ctypes.c_double)]
+                ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("nconv", ctypes.c_int32),
                 ("matvecs", ctypes.c_int64), ("bmatvecs", ctypes.c_int64),
                 ("precs", ctypes.c_int64), ("fp32_cycles", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("normA", ctypes.c_double),
+                ("status", ctypes.c_int32), ("fallback_cycle", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("normA", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
                 ("spmv_bytes", ctypes.c_int64),
@@ -173,7 +174,7 @@ class Solver:
 
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
-                 profile=False, mixed_switch=0.0):
+                 profile=False, mixed_switch=0.0, fallback_window=0):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -181,6 +182,7 @@ class Solver:
         o.norm, o.max_cycles = NORM[norm], max_cycles
         o.precond, o.precision, o.locking = PREC[precond], PRECISION[precision], LOCKING[locking]
         o.fsai_cap, o.profile, o.mixed_switch = fsai_cap, int(bool(profile)), mixed_switch
+        o.fallback_window = fallback_window
         self.opts = o
         self.n = int(A.n)
         self.p = p

@@ -234,7 +234,7 @@ constexpr int MLP_NF = 8;                  // row features
 constexpr int MLP_NIN = 2 * MLP_NF + 1;    // inputs per lower-triangular nonzero
 constexpr int MLP_NH = 64;                 // hidden width
 constexpr int MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH + 1;  // W1, b1, w2, b2
-constexpr int LEARN_MAXS = 32;             // training pairs per instance
+constexpr int LEARN_MAXS = 64;             // training pairs per instance
 
 struct LearnArgs {
   int n = 0;
@@ -253,10 +253,12 @@ struct LearnArgs {
   const float* P = nullptr;   // parameters (device)
   const double* Rr = nullptr; // pairs, row-major n x S
   const double* Er = nullptr;
-  const double* w = nullptr;  // 1 / (S ||e_s||^2)
-  double* Y = nullptr;
-  double* D = nullptr;
-  double* Uu = nullptr;
+  const double* en = nullptr; // ||e_s||^2
+  double* Y = nullptr;        // G r
+  double* Q = nullptr;        // G^T G r
+  double* Z = nullptr;
+  double* Uz = nullptr;       // G z
+  double* coef = nullptr;     // 128
   float* dout = nullptr;
   double* part = nullptr;     // learn_blocks() * MLP_NPARAM
   double* loss = nullptr;
@@ -274,7 +276,7 @@ hipError_t mlp_forward(int64_t nnz, const int* lr, const int* lc, const double* 
                        float* oval, hipStream_t s);
 int learn_blocks();
 hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s);
-hipError_t learn_weights(int n, int S, const double* Er, double* part, double* w, hipStream_t s);
+hipError_t learn_colnorms(int n, int S, const double* Er, double* part, double* en, hipStream_t s);
 hipError_t adam_step(float* P, float* m, float* v, const double* grad, int t, float lr,
                      hipStream_t s);
 hipError_t to_rowmajor(int n, int S, const double* Xc, int64_t ldx, double* Xr, hipStream_t s);

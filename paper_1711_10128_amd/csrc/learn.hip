@@ -9,10 +9,14 @@
 // layer gives G = D^{-1/2}, i.e. the Jacobi preconditioner.
 // Features f_i: degree, a_ii, sum / mean / min / max / std of |a_ij| (j != i)
 // and a_ii / sum, each z-scored over the rows of A.
-// Loss over pairs (r_s, e_s) = (A u_s, u_s) from the solver's basis:
-//   L = (1/S) sum_s ||G^T G r_s - e_s||^2 / ||e_s||^2,
-//   dL/dG(i,j) = sum_s (2 / (S ||e_s||^2)) (y_i d_j + u_i r_j),
-//   y = G r, d = G^T y - e, u = G d   (sampled dense-dense product on the pattern).
+// Loss over pairs (r_s, e_s) = (A u_s, u_s) from the solver's basis: the
+// mean squared sine of the angle between M r_s and e_s (independent of the
+// scale of M r_s, as the inner Krylov space is):
+//   L = (1/S) sum_s [1 - a_s^2 / (b_s c_s)],  q = G^T G r, a = <q, e>,
+//   b = ||q||^2, c = ||e||^2;
+//   dL/dG(i,j) = sum_s (y_i z_j + (G z)_i r_j),  y = G r,
+//   z = (-2 a / (b c) e + 2 a^2 / (b^2 c) q) / S  (a sampled dense-dense
+//   product on the pattern).
 // All reductions are fixed-order (per-block partials, then one block), so a
 // training step is bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -187,14 +191,14 @@ __global__ __launch_bounds__(256) void k_mlp_forward(int64_t nnz, const int* lr,
 }
 
 // -------------------------------------------------- pair algebra (float64)
-// Y = M X for a CSR M and row-major n x S blocks (S <= 32): 32 lanes per row,
-// lane s owns column s.  mode 1: Y = M X - E.
+// Y = M X for a CSR M and row-major n x S blocks (S <= 64): a wavefront per
+// row, lane s owns column s.  With E: Y = M X - E.
 __global__ __launch_bounds__(256) void k_spmm(int n, int S, const int* rowptr, const int* col,
                                               const double* val, const double* X, const double* E,
                                               double* Y) {
-  const int lane = threadIdx.x & 31;
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / 32; i < n;
-       i += (gridDim.x * blockDim.x) / 32) {
+  const int lane = threadIdx.x & 63;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / 64; i < n;
+       i += (gridDim.x * blockDim.x) / 64) {
     if (lane >= S) continue;
     double t = 0.0;
     for (int j = rowptr[i]; j < rowptr[i + 1]; ++j)
@@ -204,67 +208,106 @@ __global__ __launch_bounds__(256) void k_spmm(int n, int S, const int* rowptr, c
   }
 }
 
-// per-block partial of sum_s w_s ||D_s||^2 (w_s = 1 / (S ||e_s||^2))
-__global__ __launch_bounds__(256) void k_loss_part(int n, int S, const double* D, const double* w,
+// per-block partials of a_s = <Q_s, E_s> (slot s) and b_s = ||Q_s||^2
+// (slot 64 + s): lane s of each wavefront owns column s
+__global__ __launch_bounds__(256) void k_pair_dots(int n, int S, const double* Q, const double* E,
                                                    double* part) {
-  double acc = 0.0;
+  __shared__ double ra[4][64], rb[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x / 64;
+  double a = 0.0, b = 0.0;
+  if (lane < S)
+    for (int i = blockIdx.x * 4 + wv; i < n; i += gridDim.x * 4) {
+      const double q = Q[static_cast<int64_t>(i) * S + lane];
+      a += q * E[static_cast<int64_t>(i) * S + lane];
+      b += q * q;
+    }
+  ra[wv][lane] = a;
+  rb[wv][lane] = b;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    part[blockIdx.x * 128 + t] = ra[0][t] + ra[1][t] + ra[2][t] + ra[3][t];
+    part[blockIdx.x * 128 + 64 + t] = rb[0][t] + rb[1][t] + rb[2][t] + rb[3][t];
+  }
+}
+
+// coefficients of z and the loss; coef[s] = -2a/(bcS), coef[64+s] = 2a^2/(b^2 c S)
+__global__ void k_pair_coef(int nblk, int S, const double* part, const double* en, double* coef,
+                            double* loss) {
+  __shared__ double ls[64];
+  const int s = threadIdx.x;
+  double l = 0.0;
+  if (s < S) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < nblk; ++q) {
+      a += part[q * 128 + s];
+      b += part[q * 128 + 64 + s];
+    }
+    const double c = en[s];
+    coef[s] = -2.0 * a / (b * c * S);
+    coef[64 + s] = 2.0 * a * a / (b * b * c * S);
+    l = 1.0 - a * a / (b * c);
+  }
+  if (s < 64) ls[s] = l;
+  __syncthreads();
+  if (s == 0) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += ls[q];
+    *loss = t / S;
+  }
+}
+
+__global__ void k_make_z(int n, int S, const double* coef, const double* E, const double* Q,
+                         double* Z) {
   for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
        t < static_cast<int64_t>(n) * S; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double d = D[t];
-    acc += d * d * w[t % S];
+    const int s = static_cast<int>(t % S);
+    Z[t] = coef[s] * E[t] + coef[64 + s] * Q[t];
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // column norms of a row-major n x S block: per-block partials [S]
+// column norms of a row-major n x S block: lane s of each wavefront sums
+// column s over the wavefront's rows; per-block partials [64]
 __global__ __launch_bounds__(256) void k_colnorm_part(int n, int S, const double* E, double* part) {
-  __shared__ double red[256][33];
-  double acc[32];
-  for (int s = 0; s < 32; ++s) acc[s] = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    for (int s = 0; s < S; ++s) {
-      const double v = E[static_cast<int64_t>(i) * S + s];
-      acc[s] += v * v;
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x / 64;
+  double acc = 0.0;
+  if (lane < S)
+    for (int i = blockIdx.x * 4 + wv; i < n; i += gridDim.x * 4) {
+      const double v = E[static_cast<int64_t>(i) * S + lane];
+      acc += v * v;
     }
-  for (int s = 0; s < S; ++s) red[threadIdx.x][s] = acc[s];
+  red[wv][lane] = acc;
   __syncthreads();
-  if (threadIdx.x < S) {
-    double t = 0.0;
-    for (int q = 0; q < 256; ++q) t += red[q][threadIdx.x];
-    part[blockIdx.x * 32 + threadIdx.x] = t;
-  }
+  if (threadIdx.x < 64)
+    part[blockIdx.x * 64 + threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] +
+                                          red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-__global__ void k_weights(int nblk, int S, const double* part, double* w) {
+__global__ void k_colnorms(int nblk, int S, const double* part, double* en) {
   const int s = threadIdx.x;
   if (s >= S) return;
   double t = 0.0;
-  for (int b = 0; b < nblk; ++b) t += part[b * 32 + s];
-  w[s] = 1.0 / (S * t);
+  for (int b = 0; b < nblk; ++b) t += part[b * 64 + s];
+  en[s] = t;
 }
 
 // dL/do_e: sampled products on the pattern, then the chain rule through
 // G = exp(o)/sqrt(a_ii) (diagonal) or o/sqrt(a_jj)
 __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int S, const int* lr, const int* lc,
                                                const double* gval, const double* dinv,
-                                               const double* Y, const double* D, const double* Uu,
-                                               const double* R, const double* w, float* dout) {
+                                               const double* Y, const double* Z, const double* Uz,
+                                               const double* R, float* dout) {
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int i = lr[e], j = lc[e];
     const double* yi = Y + static_cast<int64_t>(i) * S;
-    const double* ui = Uu + static_cast<int64_t>(i) * S;
-    const double* dj = D + static_cast<int64_t>(j) * S;
+    const double* ui = Uz + static_cast<int64_t>(i) * S;
+    const double* zj = Z + static_cast<int64_t>(j) * S;
     const double* rj = R + static_cast<int64_t>(j) * S;
     double g = 0.0;
-    for (int s = 0; s < S; ++s) g += 2.0 * w[s] * (yi[s] * dj[s] + ui[s] * rj[s]);
+    for (int s = 0; s < S; ++s) g += yi[s] * zj[s] + ui[s] * rj[s];
     const double dodg = (i == j) ? gval[e] : sqrt(dinv[j]);
     dout[e] = static_cast<float>(g * dodg);
   }
@@ -432,26 +475,27 @@ int learn_blocks() { return 512; }
 hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s) {
   const int S = a.S;
   const int nb = learn_blocks();
-  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
-                     a.Lrow, a.lc, a.gval, a.Rr, nullptr, a.Y);
-  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
-                     a.Trow, a.Tcol, a.gvalT, a.Y, a.Er, a.D);
-  hipLaunchKernelGGL(k_spmm, dim3(g1(static_cast<int64_t>(a.n) * 32)), dim3(256), 0, s, a.n, S,
-                     a.Lrow, a.lc, a.gval, a.D, nullptr, a.Uu);
-  hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, s, a.n, S, a.D, a.w, a.part);
-  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(64), 0, s, nb, a.part, a.loss);
-  hipLaunchKernelGGL(k_sddmm, dim3(g1(a.nnz)), dim3(256), 0, s, a.nnz, S, a.lr, a.lc, a.gval,
-                     a.dinv, a.Y, a.D, a.Uu, a.Rr, a.w, a.dout);
-  hipLaunchKernelGGL(k_mlp_backward, dim3(nb), dim3(256), 0, s, a.nnz, a.lr, a.lc, a.lval, a.Fz,
-                     a.dinv, a.P, a.dout, a.part);
-  hipLaunchKernelGGL(k_param_sum, dim3(8), dim3(256), 0, s, nb, a.part, a.grad);
+  const dim3 gs(g1(static_cast<int64_t>(a.n) * 64)), bs(256);
+  // y = G r, q = G^T y
+  hipLaunchKernelGGL(k_spmm, gs, bs, 0, s, a.n, S, a.Lrow, a.lc, a.gval, a.Rr, nullptr, a.Y);
+  hipLaunchKernelGGL(k_spmm, gs, bs, 0, s, a.n, S, a.Trow, a.Tcol, a.gvalT, a.Y, nullptr, a.Q);
+  hipLaunchKernelGGL(k_pair_dots, dim3(256), dim3(256), 0, s, a.n, S, a.Q, a.Er, a.part);
+  hipLaunchKernelGGL(k_pair_coef, dim3(1), dim3(64), 0, s, 256, S, a.part, a.en, a.coef, a.loss);
+  hipLaunchKernelGGL(k_make_z, dim3(g1(static_cast<int64_t>(a.n) * S)), bs, 0, s, a.n, S, a.coef,
+                     a.Er, a.Q, a.Z);
+  hipLaunchKernelGGL(k_spmm, gs, bs, 0, s, a.n, S, a.Lrow, a.lc, a.gval, a.Z, nullptr, a.Uz);
+  hipLaunchKernelGGL(k_sddmm, dim3(g1(a.nnz)), bs, 0, s, a.nnz, S, a.lr, a.lc, a.gval, a.dinv, a.Y,
+                     a.Z, a.Uz, a.Rr, a.dout);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(nb), bs, 0, s, a.nnz, a.lr, a.lc, a.lval, a.Fz, a.dinv,
+                     a.P, a.dout, a.part);
+  hipLaunchKernelGGL(k_param_sum, dim3(8), bs, 0, s, nb, a.part, a.grad);
   return hipGetLastError();
 }
 
-hipError_t learn_weights(int n, int S, const double* Er, double* part, double* w, hipStream_t s) {
+hipError_t learn_colnorms(int n, int S, const double* Er, double* part, double* en, hipStream_t s) {
   const int nb = 256;
   hipLaunchKernelGGL(k_colnorm_part, dim3(nb), dim3(256), 0, s, n, S, Er, part);
-  hipLaunchKernelGGL(k_weights, dim3(1), dim3(64), 0, s, nb, S, part, w);
+  hipLaunchKernelGGL(k_colnorms, dim3(1), dim3(64), 0, s, nb, S, part, en);
   return hipGetLastError();
 }
 

@@ -146,6 +146,8 @@ struct trplk_ctx {
     double* Y = nullptr;
     double* D = nullptr;
     double* Uu = nullptr;
+    double* Z = nullptr;
+    double* coef = nullptr;
     double* w = nullptr;
     float* dout = nullptr;
     double* part = nullptr;
@@ -627,6 +629,10 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   std::vector<double> th(c->rep_h->theta, c->rep_h->theta + k);
   std::vector<double> res(c->rep_h->res, c->rep_h->res + k);
   std::vector<double> locked_theta;
+  const int prec_saved = c->prec;
+  const int window = o.fallback_window == 0 ? 50 : o.fallback_window;
+  double best_res = 0.0;
+  int best_cycle = 0, best_target = -1;
   int t = 0;         // target among the active Ritz pairs
   int kact = k;      // active Ritz vectors kept
   int nprev = 0;     // previous Ritz vectors held in Xprev
@@ -720,6 +726,23 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       }
       if (kact <= 0) return set_err(c, TRPLK_EINVAL, "restart size exhausted by locking");
     }
+    // a factor preconditioner that stops making progress hands over to
+    // Jacobi; the residuals (float64, true A and B) judge convergence
+    if (window > 0 && c->prec >= TRPLK_PREC_FSAI) {
+      const int target = hard ? c->u0 : t;
+      const double rt = res.empty() ? 0.0 : res[hard ? 0 : std::min<int>(t, res.size() - 1)];
+      if (target != best_target) {
+        best_target = target;
+        best_res = rt;
+        best_cycle = cycle;
+      } else if (rt < 0.5 * best_res) {
+        best_res = rt;
+        best_cycle = cycle;
+      } else if (cycle - best_cycle >= window) {
+        c->prec = TRPLK_PREC_JACOBI;
+        stt.fallback_cycle = cycle;
+      }
+    }
     // mixed form: float64 SpMV once every target residual is small
     if (c->fp32_phase) {
       double worst = 0.0;
@@ -736,6 +759,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       }
     }
   }
+  c->prec = prec_saved;
   if (cycle > o.max_cycles) cycle = o.max_cycles;
   stt.cycles = cycle;
   if (c->fp32_phase) stt.fp32_cycles = cycle;
@@ -987,6 +1011,8 @@ int learn_alloc_pairs(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &L.Y, nS));
   HIPCHK(c, dalloc(c, &L.D, nS));
   HIPCHK(c, dalloc(c, &L.Uu, nS));
+  HIPCHK(c, dalloc(c, &L.Z, nS));
+  HIPCHK(c, dalloc(c, &L.coef, 128));
   HIPCHK(c, dalloc(c, &L.w, LEARN_MAXS));
   HIPCHK(c, dalloc(c, &L.dout, L.nnz));
   return TRPLK_OK;
@@ -1005,8 +1031,9 @@ int learn_loss_grad_run(trplk_ctx* c) {
   LearnArgs a;
   a.n = c->n; a.nnz = L.nnz; a.S = L.S; a.Lrow = L.Lrow; a.lc = L.Lcol; a.lr = L.lr;
   a.lval = L.lval; a.Trow = L.Trow; a.Tcol = L.Tcol; a.gval = L.gval; a.gvalT = L.gvalT;
-  a.Fz = L.Fz; a.dinv = L.dinv; a.P = L.P; a.Rr = L.Rr; a.Er = L.Er; a.w = L.w; a.Y = L.Y;
-  a.D = L.D; a.Uu = L.Uu; a.dout = L.dout; a.part = L.part; a.loss = L.loss; a.grad = L.grad;
+  a.Fz = L.Fz; a.dinv = L.dinv; a.P = L.P; a.Rr = L.Rr; a.Er = L.Er; a.en = L.w; a.Y = L.Y;
+  a.Q = L.D; a.Z = L.Z; a.Uz = L.Uu; a.coef = L.coef; a.dout = L.dout; a.part = L.part;
+  a.loss = L.loss; a.grad = L.grad;
   HIPCHK(c, learn_loss_grad(a, c->s));
   return TRPLK_OK;
 }
@@ -1073,7 +1100,7 @@ int trplk_factor_values(trplk_ctx* c, double* val, int32_t mem) {
 int trplk_factor_loss_grad(trplk_ctx* c, const float* params, int32_t S, const double* E,
                            const double* R, int32_t mem, double* loss, double* grad) {
   if (!c || !params || !E || !R || !loss || !grad) return set_err(c, TRPLK_EINVAL, "null argument");
-  if (S < 1 || S > LEARN_MAXS) return set_err(c, TRPLK_EINVAL, "S must be in 1..32");
+  if (S < 1 || S > LEARN_MAXS) return set_err(c, TRPLK_EINVAL, "S must be in 1..64");
   int r;
   if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
   auto& L = c->L;
@@ -1087,7 +1114,7 @@ int trplk_factor_loss_grad(trplk_ctx* c, const float* params, int32_t S, const d
   HIPCHK(c, to_rowmajor(n, S, L.Uu, n, L.Rr, c->s));
   L.S = S;
   L.pairs = false;  // these pairs are not the solver's
-  HIPCHK(c, learn_weights(n, S, L.Er, L.part, L.w, c->s));
+  HIPCHK(c, learn_colnorms(n, S, L.Er, L.part, L.w, c->s));
   if ((r = learn_forward(c, params))) return r;
   if ((r = learn_loss_grad_run(c))) return r;
   HIPCHK(c, hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->s));
@@ -1100,7 +1127,7 @@ int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, 
                      double lr, int32_t S, double* loss) {
   if (!c || !params || !adam_m || !adam_v) return set_err(c, TRPLK_EINVAL, "null argument");
   if (step < 1) return set_err(c, TRPLK_EINVAL, "step counts from 1");
-  if (S < 1 || S > LEARN_MAXS || S > c->m) return set_err(c, TRPLK_EINVAL, "S must be in 1..min(32, m)");
+  if (S < 1 || S > LEARN_MAXS || S > c->m) return set_err(c, TRPLK_EINVAL, "S must be in 1..min(64, m)");
   int r;
   if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
   auto& L = c->L;
@@ -1110,7 +1137,7 @@ int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, 
     // pairs (u, A u): the first S stored basis columns and their products
     HIPCHK(c, to_rowmajor(n, S, c->W, c->ld, L.Er, c->s));
     HIPCHK(c, to_rowmajor(n, S, c->AW, c->ld, L.Rr, c->s));
-    HIPCHK(c, learn_weights(n, S, L.Er, L.part, L.w, c->s));
+    HIPCHK(c, learn_colnorms(n, S, L.Er, L.part, L.w, c->s));
     L.S = S;
     L.pairs = true;
   }
@@ -1202,9 +1229,9 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
   if (B && (r = upload_csr(c, c->B, B, mem, false))) return fail(r);
   if ((r = compute_norms(c))) return fail(r);
   if (timing) (void)hipEventRecord(e0, c->s);
-  if (c->prec == TRPLK_PREC_JACOBI) {
-    if ((r = build_jacobi(c))) return fail(r);
-  } else if (c->prec == TRPLK_PREC_FSAI) {
+  // the Jacobi diagonal is also the fallback of the factor preconditioners
+  if ((r = build_jacobi(c))) return fail(r);
+  if (c->prec == TRPLK_PREC_FSAI) {
     if ((r = trplk_internal_build_fsai(c))) return fail(r);
   } else if (c->prec == TRPLK_PREC_FACTOR) {
     // installed later by trplk_set_factor; Jacobi-equivalent until then
@@ -1244,7 +1271,9 @@ int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   Solver S{c, c->n, c->ld, c->s};
   c->stats.setup_ms = c->stats.setup_ms;
   const double setup = c->stats.setup_ms;
+  const int prec0 = c->prec;
   r = S.run(x0, mem, st);
+  c->prec = prec0;  // a fallback inside the solve does not outlive it
   c->stats.setup_ms = setup;
   if (st) st->setup_ms = setup;
   return r;
@@ -1335,8 +1364,8 @@ void trplk_destroy(trplk_ctx* c) {
   for (void* p : ptrs) dfree(p);
   auto& L = c->L;
   void* lp[] = {L.Lrow, L.Lcol, L.lr, L.lval, L.Trow, L.Tcol, L.permd, L.dinv, L.F, L.Fz,
-                L.gval, L.gvalT, L.P, L.am, L.av, L.Er, L.Rr, L.Y, L.D, L.Uu, L.w, L.dout,
-                L.part, L.loss, L.grad, L.scratch};
+                L.gval, L.gvalT, L.P, L.am, L.av, L.Er, L.Rr, L.Y, L.D, L.Uu, L.Z, L.coef, L.w,
+                L.dout, L.part, L.loss, L.grad, L.scratch};
   for (void* p : lp) dfree(p);
   if (c->rep_h) (void)hipHostFree(c->rep_h);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

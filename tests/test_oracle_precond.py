@@ -149,6 +149,26 @@ def test_loss_gradient_params_finite_differences():
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (key, ix, fd, an)
 
 
+def test_angle_loss_closed_forms():
+    """The loss is 0 when M r is parallel to e (any scale) and 1 when they are
+    orthogonal; G = c I gives M = c^2 I, so with r = A e the loss is the
+    squared sine of the angle between A e and e."""
+    n = 6
+    I = sp.identity(n, format="csr")
+    rng = np.random.default_rng(2)
+    E = rng.standard_normal((n, 3))
+    L, _ = PC.loss_and_grad_G(3.0 * I, E, E)
+    assert abs(L) < 1e-15
+    R = np.zeros((n, 1)); R[0, 0] = 1.0
+    Eo = np.zeros((n, 1)); Eo[1, 0] = 1.0
+    assert abs(PC.loss_and_grad_G(I, R, Eo)[0] - 1.0) < 1e-15
+    Ad = np.diag(np.arange(1.0, n + 1))
+    e = rng.standard_normal((n, 1))
+    r = Ad @ e
+    cos2 = float((r[:, 0] @ e[:, 0]) ** 2 / ((r[:, 0] @ r[:, 0]) * (e[:, 0] @ e[:, 0])))
+    assert abs(PC.loss_and_grad_G(2.0 * I, r, e)[0] - (1 - cos2)) < 1e-14
+
+
 def test_adam_training_lowers_loss():
     """A few Adam steps on solver-generated pairs lower the loss below the
     Jacobi starting point."""
@@ -166,4 +186,4 @@ def test_adam_training_lowers_loss():
         L, g, _ = PC.loss_and_grad_params(params, A, R, E, x)
         PC.adam_step(params, g, st, lr=1e-3)
     L1 = PC.loss_and_grad_params(params, A, R, E, x)[0]
-    assert L1 < 0.97 * L0
+    assert L1 < 0.9 * L0
