@@ -43,6 +43,28 @@ WORKLOADS = {
 }
 
 
+KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients)",
+                "orth_upd_dot": "k_orth<ORTH_UPD_DOT> (w -= U h1; h2 = U^T w)",
+                "orth_upd": "k_upd (w -= U h2; ||w||^2)",
+                "spmv": "k_spmv_rows (SpMV + append epilogue)",
+                "prec": "k_spmv_rows (factor apply G, G^T)", "rot": "k_rotate (MFMA restart rotation)"}
+
+
+def measured_traffic(args, dom):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary of this exact configuration, or None when there is none."""
+    if args.workload != "lap3d" or args.size or args.precond or args.precision:
+        return None
+    path = os.path.join(ROOT, "profiles", "lap3d_128_jacobi_fp64_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 4 and parts[0] == "TRAFFIC" and parts[1] == dom:
+            return int(parts[2])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +81,8 @@ def parse():
     ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--profile-only", action="store_true", help="one profiled solve (for rocprofv3 runs)")
+    ap.add_argument("--max-cycles", type=int, default=5000,
+                    help="cap the restart cycles (a capped run reports per-cycle time)")
     return ap.parse_args()
 
 
@@ -126,14 +150,15 @@ def main():
 
     learned = None
     learn_info = None
-    need_learned = precond == "learned" or (args.variants and args.workload in ("powerlaw", "aniso3d", "lap3d"))
+    need_learned = precond == "learned" or (args.variants and not args.profile_only and
+                                             args.workload in ("powerlaw", "aniso3d", "lap3d"))
     if need_learned:
         learned, learn_info = train_factor(T, args.workload, args, log)
 
     def make_solver(pc, pr, profile=False):
         base = "jacobi" if pc == "learned" else pc
         s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
-                     precision=pr, profile=profile)
+                     precision=pr, profile=profile, max_cycles=args.max_cycles)
         if pc == "learned":
             s.learned_factor(learned)
         return s
@@ -143,15 +168,25 @@ def main():
     if args.profile_only:
         st = S.solve(Xd)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_only": True, "cycles": st["cycles"], "ms": st["solve_ms"]}))
+        # calibration for the HBM counters: plain copies of a known size
+        nb = 256 << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "cycles": st["cycles"], "ms": st["solve_ms"],
+                          "calibration_copy_bytes": nb}))
         return
     for _ in range(args.warmup):
-        S.solve(Xd)
+        w = S.solve(Xd)
+        log(f"# warmup solve: {w['cycles']} cycles, {w['solve_ms']:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         stats.append(S.solve(Xd))
+        log(f"# step {i}: {stats[-1]['cycles']} cycles, {stats[-1]['solve_ms']:.1f} ms")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ms_per_step = (t2 - t1) * 1e3 / args.steps
@@ -159,6 +194,8 @@ def main():
     ev, X, res, conv = S.eigpairs(vectors=False)
     normA = st["normA"]
     converged = bool(conv.all() and np.all(res <= P.tol * normA * 1.001))
+    if st["status"] == 1:
+        log(f"# capped at {st['cycles']} cycles: {int(conv.sum())} of {P.p} pairs converged")
     checks = {}
     if args.workload == "lap3d":
         N = P.meta["N"]
@@ -180,6 +217,7 @@ def main():
     Sp = make_solver(precond, precision, profile=True)
     sp = Sp.solve(Xd)
     Sp.close()
+    log(f"# profiled solve: {sp['solve_ms']:.1f} ms")
     classes = {}
     for cls in ("spmv", "orth", "prec", "rot", "rr"):
         ms = sp[f"{cls}_ms"]
@@ -187,13 +225,21 @@ def main():
             nbytes = sp.get(f"{cls}_bytes", 0)
             classes[cls] = {"ms": ms, "launches": sp[f"{cls}_launches"], "bytes": nbytes,
                             "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 and nbytes else None}
-    dom = max((c for c in classes if classes[c]["bytes"]), key=lambda c: classes[c]["ms"])
+    # the orthogonalisation by pass (one kernel each)
+    for q, name in enumerate(("orth_dot", "orth_upd_dot", "orth_upd")):
+        if sp["pass_launches"][q]:
+            ms, nbytes = sp["pass_ms"][q], sp["pass_bytes"][q]
+            classes[name] = {"ms": ms, "launches": sp["pass_launches"][q], "bytes": nbytes,
+                             "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    kernels = [c for c in classes if c != "orth" and classes[c]["bytes"]]
+    dom = max(kernels, key=lambda c: classes[c]["ms"])
     d = classes[dom]
     per_launch_bytes = d["bytes"] / d["launches"]
     avg_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES.get(dom, dom), "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args, dom),
                 "bytes_per_launch": int(per_launch_bytes), "avg_launch_us": round(avg_ms * 1e3, 2)}
     spmv = classes.get("spmv")
     spmv_roof = None
@@ -221,6 +267,7 @@ def main():
             b = time.perf_counter()
             evv, _, rv, cv = V.eigpairs(vectors=False)
             V.close()
+            log(f"# variant {pc}-{pr}: {sv['cycles']} cycles, {b - a:.3f} s")
             variants[f"{pc}-{pr}"] = {
                 "s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
                 "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
@@ -265,6 +312,8 @@ def main():
                    "name": args.workload, "n": P.A.n, "nnz": P.A.nnz,
                    "generalized": P.B is not None},
         "converged": converged,
+        "capped": st["status"] == 1,
+        "ms_per_cycle": round(st["solve_ms"] / max(1, st["cycles"]), 3),
         "matvecs": st["matvecs"],
         "bmatvecs": st["bmatvecs"],
         "cycles": st["cycles"],

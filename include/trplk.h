@@ -118,6 +118,9 @@ typedef struct trplk_stats {
   double prec_ms;      int64_t prec_launches;     int64_t prec_bytes;
   double rot_ms;       int64_t rot_launches;      int64_t rot_bytes;
   double rr_ms;        int64_t rr_launches;
+  /* the orthogonalisation split by pass: [0] dots (T column + first
+     coefficients), [1] fused update + dots, [2] update + norm */
+  double pass_ms[3];   int64_t pass_launches[3];  int64_t pass_bytes[3];
 } trplk_stats;
 
 typedef struct trplk_ctx trplk_ctx;

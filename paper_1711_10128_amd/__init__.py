@@ -59,10 +59,16 @@ class _Stats(ctypes.Structure):
                 ("prec_bytes", ctypes.c_int64),
                 ("rot_ms", ctypes.c_double), ("rot_launches", ctypes.c_int64),
                 ("rot_bytes", ctypes.c_int64),
-                ("rr_ms", ctypes.c_double), ("rr_launches", ctypes.c_int64)]
+                ("rr_ms", ctypes.c_double), ("rr_launches", ctypes.c_int64),
+                ("pass_ms", ctypes.c_double * 3), ("pass_launches", ctypes.c_int64 * 3),
+                ("pass_bytes", ctypes.c_int64 * 3)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if not isinstance(v, (int, float)) else v
+        return d
 
 
 _lib = None

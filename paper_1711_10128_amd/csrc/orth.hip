@@ -293,8 +293,19 @@ __device__ void fin_sum(const FinishArgs& f, int src, int cnt, double* dst, doub
     const int idx = c0 + lane;
     double t = 0.0;
     if (idx < cnt) {
+      // four independent loads in flight per step (fixed summation order)
       const double* p = f.partial + src + idx;
-      for (int b = wv; b < f.nblk; b += FIN_WAVES) t += p[static_cast<int64_t>(b) * f.stride];
+      const int64_t st = f.stride;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      int b = wv;
+      for (; b + 3 * FIN_WAVES < f.nblk; b += 4 * FIN_WAVES) {
+        t0 += p[b * st];
+        t1 += p[(b + FIN_WAVES) * st];
+        t2 += p[(b + 2 * FIN_WAVES) * st];
+        t3 += p[(b + 3 * FIN_WAVES) * st];
+      }
+      for (; b < f.nblk; b += FIN_WAVES) t0 += p[b * st];
+      t = (t0 + t1) + (t2 + t3);
     }
     red[wv][lane] = t;
     __syncthreads();

@@ -264,7 +264,8 @@ void free_csr(DevCsr& D) {
 }
 
 // ------------------------------------------------------------ profiling --
-enum { PC_SPMV = 0, PC_ORTH = 1, PC_PREC = 2, PC_ROT = 3, PC_RR = 4 };
+enum { PC_SPMV = 0, PC_ORTH = 1, PC_PREC = 2, PC_ROT = 3, PC_RR = 4, PC_DOT = 5, PC_UPDDOT = 6,
+       PC_UPD = 7 };
 
 struct ProfScope {
   trplk_ctx* c;
@@ -378,7 +379,7 @@ struct Solver {
     if (mode == ORTH_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 8LL * n * a.nvec;
     else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
     else bytes = 8 * cols * n + 16LL * n;
-    ProfScope ps(c, PC_ORTH, bytes);
+    ProfScope ps(c, mode == ORTH_DOT ? PC_DOT : mode == ORTH_UPD_DOT ? PC_UPDDOT : PC_UPD, bytes);
     return orth_pass(mode, a, orth_blocks(n, mode), s);
   }
   int nblk(int mode) const { return orth_blocks(n, mode); }
@@ -821,7 +822,14 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       if (hipEventElapsedTime(&e, pr.a, pr.b) != hipSuccess) continue;
       switch (pr.cls) {
         case PC_SPMV: stt.spmv_ms += e; stt.spmv_launches++; stt.spmv_bytes += pr.bytes; break;
-        case PC_ORTH: stt.orth_ms += e; stt.orth_launches++; stt.orth_bytes += pr.bytes; break;
+        case PC_DOT:
+        case PC_UPDDOT:
+        case PC_UPD: {
+          stt.orth_ms += e; stt.orth_launches++; stt.orth_bytes += pr.bytes;
+          const int q = pr.cls - PC_DOT;
+          stt.pass_ms[q] += e; stt.pass_launches[q]++; stt.pass_bytes[q] += pr.bytes;
+          break;
+        }
         case PC_PREC: stt.prec_ms += e; stt.prec_launches++; stt.prec_bytes += pr.bytes; break;
         case PC_ROT: stt.rot_ms += e; stt.rot_launches++; stt.rot_bytes += pr.bytes; break;
         case PC_RR: stt.rr_ms += e; stt.rr_launches++; break;

@@ -109,8 +109,9 @@ __global__ __launch_bounds__(NT) void k_syev(const double* T, int ldT, int b_fix
       // All rotations of the round commute (disjoint index pairs), so
       // A <- J^T A J splits into independent 2 x 2 blocks: block (i, j) holds
       // rows {p_i, q_i} and columns {p_j, q_j}.  V <- V J updates column pairs.
-      for (int t = tid; t < half * half; t += NT) {
-        const int i = t / half, j = t % half;
+      // thread (i0, j): j = tid % 32 < half, i = i0, i0 + 8, ... (no divisions)
+      for (int i = tid >> 5, j = tid & 31; i < half; i += NT / 32) {
+        if (j >= half) break;
         const int p = pr[i][0], q = pr[i][1], u = pr[j][0], v = pr[j][1];
         const double ci = cs[i][0], si = cs[i][1], cj = cs[j][0], sj = cs[j][1];
         const double apu = A[p * LDA + u], apv = A[p * LDA + v];
@@ -126,8 +127,8 @@ __global__ __launch_bounds__(NT) void k_syev(const double* T, int ldT, int b_fix
           A[q * LDA + u] = 0.0;
         }
       }
-      for (int t = tid; t < half * be; t += NT) {
-        const int j = t / be, row = t % be;
+      for (int j = tid >> 6, row = tid & 63; j < half; j += NT / 64) {
+        if (row >= be) break;
         const int u = pr[j][0], v = pr[j][1];
         const double cj = cs[j][0], sj = cs[j][1];
         const double vu = V[row * LDA + u], vv = V[row * LDA + v];
