@@ -112,6 +112,7 @@ struct SpmvPlan {
   int nlong = 0;            // rows with more than LONG_ROW entries
   int* long_rows = nullptr; // device list of those rows
   int nblk_short = 0;       // grid of the short-row kernel
+  int maxlen = 0;           // longest row
 };
 constexpr int LONG_ROW = 256;
 

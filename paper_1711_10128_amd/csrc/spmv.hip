@@ -152,6 +152,71 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rows(const SpmvArgs a) {
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
 
+// Rows of at most 2L entries (stencils, FEM rows with L = 16): every lane
+// handles exactly two entry slots of its row, so the whole 64-row tile's
+// loads (row pointers, values, columns, gathers) are straight-line code the
+// compiler issues ahead of the arithmetic.
+template <int L, typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_short(const SpmvArgs a) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  const int* __restrict__ rowptr = a.rowptr;
+  const int* __restrict__ col = a.col;
+  const VT* __restrict__ val = static_cast<const VT*>(a.val);
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  constexpr int RPW = WAVE / L;
+  constexpr int WPB = SPMV_THREADS / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int li = lane & (L - 1);
+  const int g = lane / L;
+  const int ntile = (a.n + WAVE - 1) / WAVE;
+  double acc = 0.0;
+  for (int tile = blockIdx.x * WPB + wv; tile < ntile; tile += gridDim.x * WPB) {
+    const int r0 = tile * WAVE;
+    int beg[L], end[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const int row = min(r0 + q * RPW + g, a.n);
+      beg[q] = rowptr[row];
+      end[q] = row < a.n ? rowptr[row + 1] : beg[q];
+    }
+    VT v0[L], v1[L];
+    int c0[L], c1[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const int j0 = beg[q] + li, j1 = j0 + L;
+      const bool k0 = j0 < end[q], k1 = j1 < end[q];
+      v0[q] = k0 ? val[j0] : VT(0);
+      c0[q] = k0 ? col[j0] : 0;
+      v1[q] = k1 ? val[j1] : VT(0);
+      c1[q] = k1 ? col[j1] : 0;
+    }
+    AT s[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q)
+      s[q] = static_cast<AT>(v0[q]) * static_cast<AT>(x[c0[q]]) +
+             static_cast<AT>(v1[q]) * static_cast<AT>(x[c1[q]]);
+    double mine = 0.0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      double sd;
+      if constexpr (sizeof(AT) == 4) sd = static_cast<double>(group_sumf<L>(s[q]));
+      else sd = group_sum<L>(s[q]);
+      const double t = __shfl(sd, (lane % RPW) * L, WAVE);
+      if (lane / RPW == q) mine = t;
+    }
+    const int row = r0 + lane;
+    if (row < a.n) epilogue<OT>(a, e, row, mine, acc);
+  }
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+}
+
 template <typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
                                                             int slot0) {
@@ -183,9 +248,14 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, co
   }
 }
 
-__global__ void k_find_long(int n, const int* rowptr, int* flags) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    flags[i] = (rowptr[i + 1] - rowptr[i]) > LONG_ROW;
+__global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen) {
+  int mx = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int len = rowptr[i + 1] - rowptr[i];
+    flags[i] = len > LONG_ROW;
+    mx = max(mx, len);
+  }
+  atomicMax(maxlen, mx);
 }
 
 int short_blocks(int n, int /*lanes*/) {
@@ -199,6 +269,16 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
+  if (p.nlong == 0 && p.maxlen <= 2 * p.lanes) {
+    switch (p.lanes) {
+      case 2: hipLaunchKernelGGL((k_spmv_short<2, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_spmv_short<4, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 8: hipLaunchKernelGGL((k_spmv_short<8, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_spmv_short<16, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_spmv_short<32, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
   switch (p.lanes) {
     case 1: hipLaunchKernelGGL((k_spmv_rows<1, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_spmv_rows<2, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
@@ -244,14 +324,17 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
   plan.long_rows = nullptr;
   if (n == 0) return hipSuccess;
   int* flags = nullptr;
-  e = hipMalloc(&flags, sizeof(int) * n);
+  e = hipMalloc(&flags, sizeof(int) * (n + 1));
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(flags + n, 0, sizeof(int), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_find_long, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n,
-                     rowptr_dev, flags);
-  std::vector<int> h(n);
-  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+                     rowptr_dev, flags, flags + n);
+  std::vector<int> h(n + 1);
+  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(flags);
+  (void)hipFree(flags);
+  plan.maxlen = h[n];
   if (e != hipSuccess) return e;
   std::vector<int> rows;
   for (int i = 0; i < n; ++i)
@@ -268,7 +351,7 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
 }
 
 void spmv_plan_free(SpmvPlan& plan) {
-  if (plan.long_rows) hipFree(plan.long_rows);
+  if (plan.long_rows) (void)hipFree(plan.long_rows);
   plan.long_rows = nullptr;
   plan.nlong = 0;
 }
