@@ -238,12 +238,15 @@ int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const f
                    const float* x, float* y, int32_t lanes, void* stream);
 
 /* h = U^T v for U n x c (column-major, leading dimension ldu), c <= 128:
- * the projection coefficients of the Gram-Schmidt step (Sec. 3). */
+ * the projection coefficients of the Gram-Schmidt step (Sec. 3).  Device
+ * pointers; U and v must be 16-byte aligned and ldu even (the pass loads
+ * row pairs), otherwise TRPLK_EINVAL. */
 int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v,
                  double* h, void* stream);
 
 /* w <- w - U h followed by h2 = U^T w (one read of U): the fused second
- * pass of classical Gram-Schmidt applied twice. */
+ * pass of classical Gram-Schmidt applied twice.  Same layout and alignment
+ * rules as trplk_gemv_t (U and w 16-byte aligned, ldu even). */
 int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* h,
                          double* w, double* h2, void* stream);
 

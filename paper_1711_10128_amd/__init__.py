@@ -307,16 +307,19 @@ def spmv(rowptr, col, val, x, y, lanes=0):
     return y
 
 
-def gemv_t(U, v, h):
-    """h = U^T v for U given as a (c, n) contiguous tensor (column-major n x c)."""
-    c, n = U.shape
-    _check(lib().trplk_gemv_t(n, c, _ptr(U), n, _ptr(v), _ptr(h), _stream()))
+def gemv_t(U, v, h, n=None):
+    """h = U^T v for U given as a (c, ld) contiguous tensor (column-major
+    ld x c, the first n rows used; ld even)."""
+    c, ld = U.shape
+    n = ld if n is None else n
+    _check(lib().trplk_gemv_t(n, c, _ptr(U), ld, _ptr(v), _ptr(h), _stream()))
     return h
 
 
-def cgs_update_dot(U, h, w, h2):
-    c, n = U.shape
-    _check(lib().trplk_cgs_update_dot(n, c, _ptr(U), n, _ptr(h), _ptr(w), _ptr(h2), _stream()))
+def cgs_update_dot(U, h, w, h2, n=None):
+    c, ld = U.shape
+    n = ld if n is None else n
+    _check(lib().trplk_cgs_update_dot(n, c, _ptr(U), ld, _ptr(h), _ptr(w), _ptr(h2), _stream()))
     return w, h2
 
 

@@ -1,19 +1,26 @@
 // Tall-skinny Gram-Schmidt passes over the basis, the finishing reductions
 // and the small vector kernels of the inner step.
 //
-// The basis U is n x c (c <= 128) column-major.  One workgroup of 8
-// wavefronts walks slabs of 256 rows; wavefront w owns the columns
-// w, w+8, w+16, ... and lane j the rows j, j+64, j+128, j+192 of the slab, so
-// each column load is a contiguous 512-byte run.  Dot products accumulate in
-// registers across all slabs of the workgroup and are reduced once at the
-// end; the update w - U h needs the sum over all columns of a row, which the
-// 8 wavefronts combine through a double-buffered LDS array (one barrier per
-// slab).  The fused pass w <- w - U h, h2 = U^T w reads U once.
+// The basis U is n x c (c <= 128) column-major.  Every pass streams U once
+// with 16-byte loads of row pairs; when U is much larger than the caches the
+// loads are non-temporal, so the streamed basis does not evict the vectors
+// and the matrix that the next kernels re-read.  Rows are handled in pairs
+// (2p, 2p+1); slabs that lie wholly inside the n rows load without any
+// bounds test, and only the last, partial slab takes a guarded per-row path.
+//
+// Dot passes: one workgroup of 8 wavefronts walks slabs of row pairs;
+// wavefront w owns the columns w, w+8, w+16, ... and lane j the pairs
+// j, j+64, ... of the slab.  Dot products accumulate in registers across
+// all slabs of the workgroup and are reduced once at the end.  The fused
+// pass w <- w - U h, h2 = U^T w needs the sum over all columns of a row,
+// which the 8 wavefronts combine through a double-buffered LDS array (one
+// barrier per slab), so it reads U once.
 // Reductions are deterministic: fixed per-lane order, fixed shuffle tree,
 // and a fixed-order sum over blocks in the finishing kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -24,11 +31,67 @@ namespace {
 constexpr int OT_THREADS = 512;
 constexpr int NWV = OT_THREADS / WAVE;  // 8
 constexpr int STRIDE = 2 * ORTH_MAXCOL; // partial doubles per block
-int g_orth_rpl = 0;                     // rows per lane per slab (0: by pass)
+constexpr int ORTH_RP = 1;              // row pairs per lane per slab: dot passes
+constexpr int UPD_RP = 4;               // update-only pass
+int64_t g_orth_nt_bytes = int64_t(128) << 20;  // non-temporal from this basis size
 
-template <int CPW, int MODE, int NV, bool SAME, int RPL>
+using d2 = double __attribute__((ext_vector_type(2)));
+
+template <bool FULL, bool NT>
+__device__ __forceinline__ d2 ld_pair(const double* col, int p, int n) {
+  const int r = 2 * p;
+  if constexpr (FULL) {
+    const d2* q = reinterpret_cast<const d2*>(col + r);
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+  } else {
+    d2 v;
+    v.x = r < n ? col[r] : 0.0;
+    v.y = r + 1 < n ? col[r + 1] : 0.0;
+    return v;
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void st_pair(double* col, int p, int n, d2 v) {
+  const int r = 2 * p;
+  if constexpr (FULL) {
+    *reinterpret_cast<d2*>(col + r) = v;
+  } else {
+    if (r < n) col[r] = v.x;
+    if (r + 1 < n) col[r + 1] = v.y;
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void st_pair32(float* col, int p, int n, d2 v) {
+  const int r = 2 * p;
+  if constexpr (FULL) {
+    float2 f;
+    f.x = static_cast<float>(v.x);
+    f.y = static_cast<float>(v.y);
+    *reinterpret_cast<float2*>(col + r) = f;
+  } else {
+    if (r < n) col[r] = static_cast<float>(v.x);
+    if (r + 1 < n) col[r + 1] = static_cast<float>(v.y);
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ double pair_sq(int p, int n, d2 v) {
+  const int r = 2 * p;
+  if constexpr (FULL) return v.x * v.x + v.y * v.y;
+  else return (r < n ? v.x * v.x : 0.0) + (r + 1 < n ? v.y * v.y : 0.0);
+}
+
+using Full = std::integral_constant<bool, true>;
+using Part = std::integral_constant<bool, false>;
+
+// MODE ORTH_DOT: acc[i][v] = (column c of Md_v) . vec_v over the block's
+// slabs.  MODE ORTH_UPD_DOT: w <- w - Mu h, then acc[i][0] = Md1(:,c) . w.
+template <int CPW, int MODE, int NV, bool SAME, int RP, bool NT>
 __global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
-  constexpr int SLAB = WAVE * RPL;
+  constexpr int SLABP = WAVE * RP;  // row pairs per slab
   if (a.state && a.state->skip) return;
   const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -45,137 +108,128 @@ __global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
   }
-  double nacc = 0.0;
-  __shared__ double red[2][NWV][SLAB];
+  __shared__ d2 red[2][NWV][SLABP];
   int buf = 0;
-  const int nslab = (n + SLAB - 1) / SLAB;
+  const int npair = (n + 1) / 2;
+  const int nslab = (npair + SLABP - 1) / SLABP;
+  const int nfull = n / (2 * SLABP);  // slabs wholly inside the rows
 
   const double* vec0 = a.vec0;
   if (a.vec0_base) vec0 = a.vec0_base + static_cast<int64_t>(a.vec0_col0 + a.state->nb) * ld;
 
-  for (int sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
-    const int base = sl * SLAB + lane;
+  auto slab = [&](int sl, auto full) {
+    constexpr bool F = decltype(full)::value;
+    const int base = sl * SLABP + lane;
     if constexpr (MODE == ORTH_DOT) {
-      double vv[NV][RPL];
+      d2 vv[NV][RP];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int row = base + WAVE * r;
-        const bool ok = row < n;
-        vv[0][r] = ok ? vec0[row] : 0.0;
-        if constexpr (NV == 2) vv[1][r] = ok ? a.vec1[row] : 0.0;
+      for (int r = 0; r < RP; ++r) {
+        vv[0][r] = ld_pair<F, false>(vec0, base + WAVE * r, n);
+        if constexpr (NV == 2) vv[1][r] = ld_pair<F, false>(a.vec1, base + WAVE * r, n);
+      }
+      // every load of the slab is issued before the first product
+      constexpr int NU = (NV == 2 && !SAME) ? 2 : 1;
+      d2 u[NU][CPW][RP];
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) {
+        const int c = wv + NWV * i;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          u[0][i][r] = c < ncol ? ld_pair<F, NT>(a.Md0 + c * ld, base + WAVE * r, n) : d2{0.0, 0.0};
+          if constexpr (NU == 2)
+            u[NU - 1][i][r] =
+                c < ncol ? ld_pair<F, NT>(a.Md1 + c * ld, base + WAVE * r, n) : d2{0.0, 0.0};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          acc[i][0] += u[0][i][r].x * vv[0][r].x;
+          acc[i][0] += u[0][i][r].y * vv[0][r].y;
+          if constexpr (NV == 2) {
+            acc[i][1] += u[NU - 1][i][r].x * vv[1][r].x;
+            acc[i][1] += u[NU - 1][i][r].y * vv[1][r].y;
+          }
+        }
+      }
+    } else {
+      d2 u[CPW][RP];
+      d2 part[RP];
+      d2 win[RP];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        part[r] = d2{0.0, 0.0};
+        win[r] = ld_pair<F, false>(a.w, base + WAVE * r, n);
+      }
+#pragma unroll
+      for (int i = 0; i < CPW; ++i) {
+        const int c = wv + NWV * i;
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          u[i][r] = c < ncol ? ld_pair<F, NT>(a.Mu + c * ld, base + WAVE * r, n) : d2{0.0, 0.0};
+          part[r].x += u[i][r].x * hc[i];
+          part[r].y += u[i][r].y * hc[i];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RP; ++r) red[buf][wv][lane + WAVE * r] = part[r];
+      __syncthreads();
+      d2 wn[RP];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        d2 t{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < NWV; ++q) {
+          const d2 x = red[buf][q][lane + WAVE * r];
+          t.x += x.x;
+          t.y += x.y;
+        }
+        wn[r].x = win[r].x - t.x;
+        wn[r].y = win[r].y - t.y;
+      }
+      buf ^= 1;
+      if (wv == 0) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) st_pair<F>(a.w, base + WAVE * r, n, wn[r]);
       }
 #pragma unroll
       for (int i = 0; i < CPW; ++i) {
         const int c = wv + NWV * i;
         if (c < ncol) {
-          const double* p0 = a.Md0 + c * ld;
-          const double* p1 = SAME ? p0 : a.Md1 + c * ld;
 #pragma unroll
-          for (int r = 0; r < RPL; ++r) {
-            const int row = base + WAVE * r;
-            const bool ok = row < n;
-            const double u0 = ok ? p0[row] : 0.0;
-            acc[i][0] += u0 * vv[0][r];
-            if constexpr (NV == 2) {
-              const double u1 = SAME ? u0 : (ok ? p1[row] : 0.0);
-              acc[i][NV - 1] += u1 * vv[NV - 1][r];
-            }
-          }
-        }
-      }
-    } else {
-      double u[CPW][RPL];
-      double part[RPL];
-      double win[RPL];
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int row = base + WAVE * r;
-        part[r] = 0.0;
-        win[r] = row < n ? a.w[row] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < CPW; ++i) {
-        const int c = wv + NWV * i;
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int row = base + WAVE * r;
-          u[i][r] = (c < ncol && row < n) ? a.Mu[c * ld + row] : 0.0;
-          part[r] += u[i][r] * hc[i];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) red[buf][wv][lane + WAVE * r] = part[r];
-      __syncthreads();
-      double wn[RPL];
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < NWV; ++q) t += red[buf][q][lane + WAVE * r];
-        wn[r] = win[r] - t;
-      }
-      buf ^= 1;
-      if constexpr (MODE == ORTH_UPD_DOT) {
-        if (wv == 0) {
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) {
-            const int row = base + WAVE * r;
-            if (row < n) a.w[row] = wn[r];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-          const int c = wv + NWV * i;
-          if (c < ncol) {
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-              const int row = base + WAVE * r;
-              const double ud = SAME ? u[i][r] : (row < n ? a.Md1[c * ld + row] : 0.0);
-              acc[i][0] += ud * wn[r];
-            }
-          }
-        }
-      } else {
-        if (wv == 0) {
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) {
-            const int row = base + WAVE * r;
-            if (row < n) {
-              a.wout[row] = wn[r];
-              if (a.wout32) a.wout32[row] = static_cast<float>(wn[r]);
-              nacc += wn[r] * wn[r];
-            }
+          for (int r = 0; r < RP; ++r) {
+            const d2 ud = SAME ? u[i][r] : ld_pair<F, NT>(a.Md1 + c * ld, base + WAVE * r, n);
+            acc[i][0] += ud.x * wn[r].x;
+            acc[i][0] += ud.y * wn[r].y;
           }
         }
       }
     }
+  };
+  for (int sl = blockIdx.x; sl < nslab; sl += gridDim.x) {
+    if (sl < nfull) slab(sl, Full{});
+    else slab(sl, Part{});
   }
 
   double* out = a.partial + static_cast<int64_t>(blockIdx.x) * STRIDE;
-  if constexpr (MODE == ORTH_UPD) {
-    if (a.norm && wv == 0) {
-      nacc = wave_sum(nacc);
-      if (lane == 0) out[0] = nacc;
-    }
-  } else {
 #pragma unroll
-    for (int i = 0; i < CPW; ++i) {
-      const int c = wv + NWV * i;
+  for (int i = 0; i < CPW; ++i) {
+    const int c = wv + NWV * i;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double s = wave_sum(acc[i][v]);
-        if (lane == 0 && c < ncol) out[v * ORTH_MAXCOL + c] = s;
-      }
+    for (int v = 0; v < NV; ++v) {
+      const double s = wave_sum(acc[i][v]);
+      if (lane == 0 && c < ncol) out[v * ORTH_MAXCOL + c] = s;
     }
   }
 }
 
 // Update-only pass: wout = w - U h (+ ||wout||^2).  Without dot products
-// no cross-wavefront exchange is needed: every lane owns UPD_RPL rows and
-// streams all columns for them, with h staged in LDS.
+// no cross-wavefront exchange is needed: every lane owns UPD_RP row pairs
+// and streams all columns for them, with h staged in LDS.
 constexpr int UPD_THREADS = 256;
-constexpr int UPD_RPL = 4;
 
+template <bool NT>
 __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
   if (a.state && a.state->skip) return;
   const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
@@ -187,47 +241,57 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
   const int wv = threadIdx.x / WAVE;
   const int64_t ld = a.ld;
   const int n = a.n;
-  constexpr int TILE = WAVE * UPD_RPL;
-  const int ntile = (n + TILE - 1) / TILE;
+  constexpr int TILEP = WAVE * UPD_RP;
+  const int npair = (n + 1) / 2;
+  const int ntile = (npair + TILEP - 1) / TILEP;
+  const int nfull = n / (2 * TILEP);
   double nacc = 0.0;
-  for (int tile = blockIdx.x * (UPD_THREADS / WAVE) + wv; tile < ntile;
-       tile += gridDim.x * (UPD_THREADS / WAVE)) {
-    const int base = tile * TILE + lane;
-    double part[UPD_RPL];
+  auto tile_body = [&](int tile, auto full) {
+    constexpr bool F = decltype(full)::value;
+    const int base = tile * TILEP + lane;
+    d2 part[UPD_RP];
 #pragma unroll
-    for (int r = 0; r < UPD_RPL; ++r) part[r] = 0.0;
+    for (int r = 0; r < UPD_RP; ++r) part[r] = d2{0.0, 0.0};
     int c = 0;
     for (; c + 4 <= ncol; c += 4) {
-      double u[4][UPD_RPL];
+      d2 u[4][UPD_RP];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < UPD_RPL; ++r) {
-          const int row = base + WAVE * r;
-          u[q][r] = row < n ? a.Mu[(c + q) * ld + row] : 0.0;
+        for (int r = 0; r < UPD_RP; ++r)
+          u[q][r] = ld_pair<F, NT>(a.Mu + (c + q) * ld, base + WAVE * r, n);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < UPD_RP; ++r) {
+          part[r].x += u[q][r].x * hs[c + q];
+          part[r].y += u[q][r].y * hs[c + q];
         }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < UPD_RPL; ++r) part[r] += u[q][r] * hs[c + q];
     }
     for (; c < ncol; ++c) {
 #pragma unroll
-      for (int r = 0; r < UPD_RPL; ++r) {
-        const int row = base + WAVE * r;
-        part[r] += (row < n ? a.Mu[c * ld + row] : 0.0) * hs[c];
+      for (int r = 0; r < UPD_RP; ++r) {
+        const d2 u = ld_pair<F, NT>(a.Mu + c * ld, base + WAVE * r, n);
+        part[r].x += u.x * hs[c];
+        part[r].y += u.y * hs[c];
       }
     }
 #pragma unroll
-    for (int r = 0; r < UPD_RPL; ++r) {
-      const int row = base + WAVE * r;
-      if (row < n) {
-        const double wn = a.w[row] - part[r];
-        a.wout[row] = wn;
-        if (a.wout32) a.wout32[row] = static_cast<float>(wn);
-        nacc += wn * wn;
-      }
+    for (int r = 0; r < UPD_RP; ++r) {
+      const int p = base + WAVE * r;
+      const d2 w = ld_pair<F, false>(a.w, p, n);
+      d2 wn;
+      wn.x = w.x - part[r].x;
+      wn.y = w.y - part[r].y;
+      st_pair<F>(a.wout, p, n, wn);
+      if (a.wout32) st_pair32<F>(a.wout32, p, n, wn);
+      nacc += pair_sq<F>(p, n, wn);
     }
+  };
+  for (int tile = blockIdx.x * (UPD_THREADS / WAVE) + wv; tile < ntile;
+       tile += gridDim.x * (UPD_THREADS / WAVE)) {
+    if (tile < nfull) tile_body(tile, Full{});
+    else tile_body(tile, Part{});
   }
   if (a.norm) {
     nacc = wave_sum(nacc);
@@ -241,42 +305,39 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
   }
 }
 
-template <int CPW, int RPL>
-hipError_t launch_rpl(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+template <int CPW, int RP, bool NT>
+hipError_t launch_rp(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(OT_THREADS);
   const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
   if (mode == ORTH_DOT) {
     if (a.nvec == 1) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RPL>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RP, NT>), g, b, 0, s, a);
     } else if (same) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RPL>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RP, NT>), g, b, 0, s, a);
     } else {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false, RPL>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false, RP, NT>), g, b, 0, s, a);
     }
-  } else if (mode == ORTH_UPD_DOT) {
-    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true, RPL>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false, RPL>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD, 1, true, RPL>), g, b, 0, s, a);
+    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true, RP, NT>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false, RP, NT>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
-// Rows per lane per slab by pass (measured on MI355X, n = 2.1M, 20..40
-// columns): the pure dot pass streams best with 8 rows per lane, the passes
-// that exchange row sums through LDS every slab with 2.
-int rpl_for(int mode) {
-  if (g_orth_rpl > 0) return g_orth_rpl;
-  return mode == ORTH_DOT ? 8 : 2;
+template <int CPW, bool NT>
+hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  return launch_rp<CPW, ORTH_RP, NT>(mode, a, nblk, s);
 }
 
-template <int CPW>
-hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
-  const int rpl = rpl_for(mode);
-  // the 16-column tiles keep fewer rows per lane to stay inside 256 VGPRs
-  if (CPW >= 16 || rpl <= 2) return launch_rpl<CPW, 2>(mode, a, nblk, s);
-  if (rpl >= 8) return launch_rpl<CPW, 8>(mode, a, nblk, s);
-  return launch_rpl<CPW, 4>(mode, a, nblk, s);
+template <bool NT>
+hipError_t launch_width(int mode, const OrthArgs& a, int need, int nblk, hipStream_t s) {
+  // columns a wavefront may own: ceil(max columns / 8)
+  const int cpw = (std::max(need, 1) + NWV - 1) / NWV;
+  if (cpw <= 1) return launch_cpw<1, NT>(mode, a, nblk, s);
+  if (cpw <= 2) return launch_cpw<2, NT>(mode, a, nblk, s);
+  if (cpw <= 4) return launch_cpw<4, NT>(mode, a, nblk, s);
+  if (cpw <= 8) return launch_cpw<8, NT>(mode, a, nblk, s);
+  return launch_cpw<16, NT>(mode, a, nblk, s);
 }
 
 // ------------------------------------------------------------- finish --
@@ -520,13 +581,14 @@ int grid1d(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<in
 int g_orth_maxblk = 0;  // 0: by pass
 
 int orth_blocks(int n, int mode) {
-  const int nslab = (std::max(n, 1) + WAVE * 2 - 1) / (WAVE * 2);
+  const int npair = (std::max(n, 1) + 1) / 2;
   if (mode == ORTH_UPD) {
-    const int tiles = (std::max(n, 1) + WAVE * UPD_RPL - 1) / (WAVE * UPD_RPL);
+    const int tiles = (npair + WAVE * UPD_RP - 1) / (WAVE * UPD_RP);
     const int want = (tiles + UPD_THREADS / WAVE - 1) / (UPD_THREADS / WAVE);
     return std::max(1, std::min(want, g_orth_maxblk > 0 ? g_orth_maxblk : 1024));
   }
-  const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : (mode == ORTH_DOT ? 256 : 512);
+  const int nslab = (npair + WAVE * ORTH_RP - 1) / (WAVE * ORTH_RP);
+  const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : 512;
   return std::max(1, std::min(nslab, cap));
 }
 
@@ -535,21 +597,17 @@ int orth_blocks_max(int n) { return std::max(orth_blocks(n, ORTH_DOT), orth_bloc
 int orth_stride() { return STRIDE; }
 
 hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
+  const int need = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
+  if (need > ORTH_MAXCOL) return hipErrorInvalidValue;
+  // 16-byte row-pair loads: every column and vector must start 16-byte aligned
+  if (a.ld % 2 != 0) return hipErrorInvalidValue;
+  const bool nt = static_cast<int64_t>(need) * a.n * 8 >= g_orth_nt_bytes;
   if (mode == ORTH_UPD) {
-    const int nc = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
-    if (nc > ORTH_MAXCOL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_upd, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    if (nt) hipLaunchKernelGGL(k_upd<true>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    else hipLaunchKernelGGL(k_upd<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
     return hipGetLastError();
   }
-  // columns a wavefront may own: ceil(max columns / 8)
-  int need = a.ncol_max > 0 ? a.ncol_max : a.ncol_fixed + a.ncol_extra;
-  if (need > ORTH_MAXCOL) return hipErrorInvalidValue;
-  const int cpw = (std::max(need, 1) + NWV - 1) / NWV;
-  if (cpw <= 1) return launch_cpw<1>(mode, a, nblk, s);
-  if (cpw <= 2) return launch_cpw<2>(mode, a, nblk, s);
-  if (cpw <= 4) return launch_cpw<4>(mode, a, nblk, s);
-  if (cpw <= 8) return launch_cpw<8>(mode, a, nblk, s);
-  return launch_cpw<16>(mode, a, nblk, s);
+  return nt ? launch_width<true>(mode, a, need, nblk, s) : launch_width<false>(mode, a, need, nblk, s);
 }
 
 hipError_t finish(const FinishArgs& f, hipStream_t s) {

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1448,9 +1449,13 @@ int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const f
   return kernel_err(e);
 }
 
+// the Gram-Schmidt passes load row pairs with 16-byte loads
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v, double* h,
                  void* stream) {
   if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !v || !h) return TRPLK_EINVAL;
+  if (ldu % 2 != 0 || !aligned16(U) || !aligned16(v)) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nblk = orth_blocks(n, ORTH_DOT);
   double* part = scratch(sizeof(double) * nblk * orth_stride());
@@ -1469,6 +1474,7 @@ int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const doubl
 int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* h,
                          double* w, double* h2, void* stream) {
   if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !h || !w || !h2) return TRPLK_EINVAL;
+  if (ldu % 2 != 0 || !aligned16(U) || !aligned16(w)) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nblk = orth_blocks(n, ORTH_UPD_DOT);
   double* part = scratch(sizeof(double) * nblk * orth_stride());

@@ -39,3 +39,16 @@ def test_default_opts_and_last_error_without_gpu():
     code = L.trplk_create(ctypes.byref(ctx), None, None, ctypes.byref(o), 0, None)
     assert code == -1 and not ctx.value
     assert b"NULL" in L.trplk_last_error(None)
+
+
+def test_orth_entries_reject_misaligned_layouts_without_gpu():
+    # the Gram-Schmidt passes load row pairs: an odd leading dimension or a
+    # pointer off a 16-byte boundary is refused before any device call
+    import paper_1711_10128_amd as T
+    L = T.lib()
+    good, odd = ctypes.c_void_p(4096), ctypes.c_void_p(4104)
+    assert L.trplk_gemv_t(10, 2, good, 11, good, good, None) == -1
+    assert L.trplk_gemv_t(10, 2, odd, 10, good, good, None) == -1
+    assert L.trplk_gemv_t(10, 2, good, 10, odd, good, None) == -1
+    assert L.trplk_cgs_update_dot(10, 2, good, 11, good, good, good, None) == -1
+    assert L.trplk_cgs_update_dot(10, 2, good, 10, good, odd, good, None) == -1

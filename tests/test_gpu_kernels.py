@@ -71,15 +71,18 @@ def test_gemv_t_and_fused_update(T, n, c):
     rng = np.random.default_rng(n + c)
     U = rng.standard_normal((c, n))          # row i of U is column i of the basis
     v = rng.standard_normal(n)
+    ld = n + (n % 2)                         # row pairs: even leading dimension
+    Ud = torch.full((c, ld), float("nan"), dtype=torch.float64, device="cuda")
+    Ud[:, :n] = _dev(U)                      # padding rows must never be read
     h = torch.zeros(c, dtype=torch.float64, device="cuda")
-    T.gemv_t(_dev(U), _dev(v), h)
+    T.gemv_t(Ud, _dev(v), h, n=n)
     ref = U @ v
     tol = 8 * 2.2e-16 * (np.abs(U) @ np.abs(v)) * np.log2(n + 2)
     assert np.all(np.abs(h.cpu().numpy() - ref) <= tol)
     hh = rng.standard_normal(c)
     w = _dev(v.copy())
     h2 = torch.zeros(c, dtype=torch.float64, device="cuda")
-    T.cgs_update_dot(_dev(U), _dev(hh), w, h2)
+    T.cgs_update_dot(Ud, _dev(hh), w, h2, n=n)
     wref = v - U.T @ hh
     assert np.allclose(w.cpu().numpy(), wref, rtol=1e-13, atol=1e-13 * np.abs(v).max() * c)
     h2ref = U @ wref
