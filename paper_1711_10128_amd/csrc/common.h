@@ -113,6 +113,8 @@ struct SpmvPlan {
   int* long_rows = nullptr; // device list of those rows
   int nblk_short = 0;       // grid of the short-row kernel
   int maxlen = 0;           // longest row
+  int maxtile = 0;          // most entries in a 64-row tile
+  int kmax = 0;             // CSR-stream entries per lane (8, 16), 0: row-split kernels
 };
 constexpr int LONG_ROW = 256;
 

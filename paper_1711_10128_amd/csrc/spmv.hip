@@ -1,6 +1,11 @@
 // CSR sparse matrix-vector products (the "MV" of the paper, eq. (3.1)).
 //
-// Two kernels share one epilogue:
+// Three kernels share one epilogue:
+//  * CSR-stream (Greathouse and Daga's CSR-Adaptive row blocks, with the
+//    block fixed at 64 rows): when every 64-row tile holds at most 64*KMAX
+//    entries, a wavefront loads its tile's contiguous run of values and
+//    indices with every lane busy, stages the products in LDS and lane j
+//    sums row j; this is the kernel for stencil and mesh matrices;
 //  * row-split: a group of L lanes of a wavefront owns one row (L = 2..64,
 //    picked from the mean row length), loads its entries coalesced and
 //    reduces with cross-lane shuffles; rows of a wavefront are consecutive, so
@@ -217,6 +222,59 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_short(const SpmvArgs a) {
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
 
+// CSR-stream tile kernel.  The plan guarantees that rowptr[r0 + 64] -
+// rowptr[r0] <= 64 * KMAX for every tile, so the masked loads below cover
+// the whole tile.  Row sums run in entry order.
+template <int KMAX, typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  constexpr int WPB = SPMV_THREADS / WAVE;
+  __shared__ AT prod[WPB][WAVE * KMAX];
+  const int* __restrict__ rowptr = a.rowptr;
+  const int* __restrict__ col = a.col;
+  const VT* __restrict__ val = static_cast<const VT*>(a.val);
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int n = a.n;
+  const int ntile = (n + WAVE - 1) / WAVE;
+  double acc = 0.0;
+  for (int tile = blockIdx.x * WPB + wv; tile < ntile; tile += gridDim.x * WPB) {
+    const int r0 = tile * WAVE;
+    const int row = r0 + lane;
+    const int rb = rowptr[min(row, n)];
+    const int rt = rowptr[min(r0 + WAVE, n)];
+    const int s0 = __shfl(rb, 0, WAVE);
+    const int cnt = rt - s0;
+    VT v[KMAX];
+    int c[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const bool ok = lane + WAVE * k < cnt;
+      const int idx = s0 + lane + WAVE * k;
+      v[k] = ok ? val[idx] : VT(0);
+      c[k] = ok ? col[idx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      prod[wv][lane + WAVE * k] = static_cast<AT>(v[k]) * static_cast<AT>(x[c[k]]);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int nx = __shfl_down(rb, 1, WAVE);
+    const int end = (lane == WAVE - 1 || row + 1 > n) ? rt : nx;
+    AT sum = 0;
+    for (int j = rb - s0; j < end - s0; ++j) sum += prod[wv][j];
+    if (row < n) epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+}
+
 template <typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
                                                             int slot0) {
@@ -248,20 +306,27 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, co
   }
 }
 
-__global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen) {
-  int mx = 0;
+// Row lengths: long-row flags, the longest row and the fullest 64-row tile.
+__global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen, int* maxtile) {
+  int mx = 0, mt = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int len = rowptr[i + 1] - rowptr[i];
     flags[i] = len > LONG_ROW;
     mx = max(mx, len);
+    if (i % WAVE == 0) mt = max(mt, rowptr[min(i + WAVE, n)] - rowptr[i]);
   }
   atomicMax(maxlen, mx);
+  atomicMax(maxtile, mt);
 }
 
-int short_blocks(int n, int /*lanes*/) {
+// Grid of the tile kernels: one 64-row tile per wavefront up to a cap.
+// The CSR-stream kernel is latency-bound and runs best with every block
+// resident at once (8 blocks of 4 wavefronts per compute unit, measured on
+// MI355X for n = 2.1M); the row-split kernels with a deeper grid.
+int short_blocks(int n, bool stream) {
   const int tiles = (n + WAVE - 1) / WAVE;
   const int want = (tiles + SPMV_THREADS / WAVE - 1) / (SPMV_THREADS / WAVE);
-  return std::max(1, std::min(want, 8192));
+  return std::max(1, std::min(want, stream ? 2048 : 8192));
 }
 
 template <typename VT, typename XT, typename AT, typename OT>
@@ -269,6 +334,14 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
+  if (p.kmax == 8) {
+    hipLaunchKernelGGL((k_spmv_stream<8, VT, XT, AT, OT>), grd, blk, 0, s, a);
+    return hipGetLastError();
+  }
+  if (p.kmax == 16) {
+    hipLaunchKernelGGL((k_spmv_stream<16, VT, XT, AT, OT>), grd, blk, 0, s, a);
+    return hipGetLastError();
+  }
   if (p.nlong == 0 && p.maxlen <= 2 * p.lanes) {
     switch (p.lanes) {
       case 2: hipLaunchKernelGGL((k_spmv_short<2, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
@@ -319,23 +392,34 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
     if (e != hipSuccess) return e;
   }
   plan.lanes = lanes > 0 ? lanes : pick_lanes(n ? double(nnz) / n : 1.0);
-  plan.nblk_short = short_blocks(std::max(n, 1), plan.lanes);
+  plan.kmax = 0;
+  plan.nblk_short = short_blocks(std::max(n, 1), false);
   plan.nlong = 0;
   plan.long_rows = nullptr;
   if (n == 0) return hipSuccess;
   int* flags = nullptr;
-  e = hipMalloc(&flags, sizeof(int) * (n + 1));
+  e = hipMalloc(&flags, sizeof(int) * (n + 2));
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(flags + n, 0, sizeof(int), s);
-  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(flags + n, 0, 2 * sizeof(int), s);
+  if (e != hipSuccess) {
+    (void)hipFree(flags);
+    return e;
+  }
   hipLaunchKernelGGL(k_find_long, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n,
-                     rowptr_dev, flags, flags + n);
-  std::vector<int> h(n + 1);
-  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s);
+                     rowptr_dev, flags, flags + n, flags + n + 1);
+  std::vector<int> h(n + 2);
+  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * (n + 2), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(flags);
   plan.maxlen = h[n];
+  plan.maxtile = h[n + 1];
   if (e != hipSuccess) return e;
+  // an explicit lane count asks for the row-split kernels
+  if (lanes <= 0 && plan.maxtile <= WAVE * 16) {
+    plan.kmax = plan.maxtile <= WAVE * 8 ? 8 : 16;
+    plan.nblk_short = short_blocks(n, true);
+    return hipSuccess;  // the stream kernel covers long rows too
+  }
   std::vector<int> rows;
   for (int i = 0; i < n; ++i)
     if (h[i]) rows.push_back(i);
@@ -356,7 +440,9 @@ void spmv_plan_free(SpmvPlan& plan) {
   plan.nlong = 0;
 }
 
-int spmv_partial_blocks(const SpmvPlan& plan) { return plan.nblk_short + plan.nlong; }
+int spmv_partial_blocks(const SpmvPlan& plan) {
+  return plan.kmax ? plan.nblk_short : plan.nblk_short + plan.nlong;
+}
 
 hipError_t spmv_f64(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s) {
   return launch<double, double, double, double>(plan, a, s);
