@@ -46,8 +46,9 @@ WORKLOADS = {
 KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients)",
                 "orth_upd_dot": "k_orth<ORTH_UPD_DOT> (w -= U h1; h2 = U^T w)",
                 "orth_upd": "k_upd (w -= U h2; ||w||^2)",
-                "spmv": "k_spmv_rows (SpMV + append epilogue)",
-                "prec": "k_spmv_rows (factor apply G, G^T)", "rot": "k_rotate (MFMA restart rotation)"}
+                "spmv": "k_spmv_stream / k_spmv_rows (SpMV + append epilogue)",
+                "prec": "k_spmv_stream / k_spmv_rows (factor apply G, G^T)",
+                "rot": "k_rotate (MFMA restart rotation)"}
 
 
 def measured_traffic(args, dom):
