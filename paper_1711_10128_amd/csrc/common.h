@@ -114,7 +114,8 @@ struct SpmvPlan {
   int nblk_short = 0;       // grid of the short-row kernel
   int maxlen = 0;           // longest row
   int maxtile = 0;          // most entries in a 64-row tile
-  int kmax = 0;             // CSR-stream entries per lane (8, 16), 0: row-split kernels
+  int kmax = 0;             // CSR-stream entries per lane (8), 0: row-split kernels
+  int tile_rows = 64;       // CSR-stream rows per wavefront tile (64, 32, 16, 8)
 };
 constexpr int LONG_ROW = 256;
 

@@ -2,10 +2,10 @@
 //
 // Three kernels share one epilogue:
 //  * CSR-stream (Greathouse and Daga's CSR-Adaptive row blocks, with the
-//    block fixed at 64 rows): when every 64-row tile holds at most 64*KMAX
+//    block fixed at 64, 32, 16 or 8 rows): when every tile holds at most 512
 //    entries, a wavefront loads its tile's contiguous run of values and
-//    indices with every lane busy, stages the products in LDS and lane j
-//    sums row j; this is the kernel for stencil and mesh matrices;
+//    indices with every lane busy, stages the products in LDS and 64/rows
+//    lanes sum each row; this is the kernel for stencil and mesh matrices;
 //  * row-split: a group of L lanes of a wavefront owns one row (L = 2..64,
 //    picked from the mean row length), loads its entries coalesced and
 //    reduces with cross-lane shuffles; rows of a wavefront are consecutive, so
@@ -222,10 +222,14 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_short(const SpmvArgs a) {
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
 
-// CSR-stream tile kernel.  The plan guarantees that rowptr[r0 + 64] -
-// rowptr[r0] <= 64 * KMAX for every tile, so the masked loads below cover
-// the whole tile.  Row sums run in entry order.
-template <int KMAX, typename VT, typename XT, typename AT, typename OT>
+// CSR-stream tile kernel.  A wavefront owns ROWS consecutive rows; the plan
+// guarantees that rowptr[r0 + ROWS] - rowptr[r0] <= 64 * KMAX for every
+// tile, so the masked loads below cover the whole tile.  Lane i loads
+// entries s0+i, s0+i+64, ... and stages the products in LDS; then
+// G = 64 / ROWS lanes sum each row's segment (lane rl + ROWS*g takes the
+// entries g, g+G, ... of row rl, combined by a fixed shuffle tree) and lane
+// rl < ROWS runs the epilogue of row r0 + rl.
+template <int KMAX, int ROWS, typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) {
   EpiCtx e{1.0, 0.0, 0};
   if (a.state) {
@@ -235,6 +239,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
     if (a.use_beta) e.s = a.state->inv_beta;
   }
   constexpr int WPB = SPMV_THREADS / WAVE;
+  constexpr int G = WAVE / ROWS;
   __shared__ AT prod[WPB][WAVE * KMAX];
   const int* __restrict__ rowptr = a.rowptr;
   const int* __restrict__ col = a.col;
@@ -242,14 +247,16 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
   const XT* __restrict__ x = static_cast<const XT*>(a.x);
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
+  const int rl = lane % ROWS;
+  const int g = lane / ROWS;
   const int n = a.n;
-  const int ntile = (n + WAVE - 1) / WAVE;
+  const int ntile = (n + ROWS - 1) / ROWS;
   double acc = 0.0;
   for (int tile = blockIdx.x * WPB + wv; tile < ntile; tile += gridDim.x * WPB) {
-    const int r0 = tile * WAVE;
-    const int row = r0 + lane;
+    const int r0 = tile * ROWS;
+    const int row = r0 + rl;
     const int rb = rowptr[min(row, n)];
-    const int rt = rowptr[min(r0 + WAVE, n)];
+    const int rt = rowptr[min(r0 + ROWS, n)];
     const int s0 = __shfl(rb, 0, WAVE);
     const int cnt = rt - s0;
     VT v[KMAX];
@@ -265,11 +272,14 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
     for (int k = 0; k < KMAX; ++k)
       prod[wv][lane + WAVE * k] = static_cast<AT>(v[k]) * static_cast<AT>(x[c[k]]);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const int nx = __shfl_down(rb, 1, WAVE);
-    const int end = (lane == WAVE - 1 || row + 1 > n) ? rt : nx;
+    // lanes rl + 1 < ROWS hold the next row's start
+    const int nx = __shfl(rb, (rl + 1) & (WAVE - 1), WAVE);
+    const int end = (rl == ROWS - 1 || row + 1 > n) ? rt : nx;
     AT sum = 0;
-    for (int j = rb - s0; j < end - s0; ++j) sum += prod[wv][j];
-    if (row < n) epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
+    for (int j = rb - s0 + g; j < end - s0; j += G) sum += prod[wv][j];
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o * ROWS, WAVE);
+    if (g == 0 && row < n) epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
@@ -306,25 +316,31 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, co
   }
 }
 
-// Row lengths: long-row flags, the longest row and the fullest 64-row tile.
+// Row lengths: long-row flags, the longest row and the fullest tile of
+// 64, 32, 16 and 8 rows (maxtile[0..3]).
 __global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen, int* maxtile) {
-  int mx = 0, mt = 0;
+  int mx = 0, mt[4] = {0, 0, 0, 0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int len = rowptr[i + 1] - rowptr[i];
     flags[i] = len > LONG_ROW;
     mx = max(mx, len);
-    if (i % WAVE == 0) mt = max(mt, rowptr[min(i + WAVE, n)] - rowptr[i]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rows = WAVE >> q;
+      if (i % rows == 0) mt[q] = max(mt[q], rowptr[min(i + rows, n)] - rowptr[i]);
+    }
   }
   atomicMax(maxlen, mx);
-  atomicMax(maxtile, mt);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) atomicMax(maxtile + q, mt[q]);
 }
 
 // Grid of the tile kernels: one 64-row tile per wavefront up to a cap.
 // The CSR-stream kernel is latency-bound and runs best with every block
 // resident at once (8 blocks of 4 wavefronts per compute unit, measured on
 // MI355X for n = 2.1M); the row-split kernels with a deeper grid.
-int short_blocks(int n, bool stream) {
-  const int tiles = (n + WAVE - 1) / WAVE;
+int short_blocks(int n, bool stream, int rows = WAVE) {
+  const int tiles = (n + rows - 1) / rows;
   const int want = (tiles + SPMV_THREADS / WAVE - 1) / (SPMV_THREADS / WAVE);
   return std::max(1, std::min(want, stream ? 2048 : 8192));
 }
@@ -335,20 +351,24 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
   if (p.kmax == 8) {
-    hipLaunchKernelGGL((k_spmv_stream<8, VT, XT, AT, OT>), grd, blk, 0, s, a);
+    switch (p.tile_rows) {
+      case 64: hipLaunchKernelGGL((k_spmv_stream<8, 64, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 32: hipLaunchKernelGGL((k_spmv_stream<8, 32, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_spmv_stream<8, 16, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_spmv_stream<8, 8, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+    }
     return hipGetLastError();
   }
-  if (p.kmax == 16) {
-    hipLaunchKernelGGL((k_spmv_stream<16, VT, XT, AT, OT>), grd, blk, 0, s, a);
-    return hipGetLastError();
-  }
-  if (p.nlong == 0 && p.maxlen <= 2 * p.lanes) {
+  // two entry slots per lane cover every row: the straight-line kernel with
+  // exactly p.lanes lanes per row (2..32; wider rows use the loop kernel)
+  if (p.nlong == 0 && p.maxlen <= 2 * p.lanes && p.lanes >= 2 && p.lanes <= 32) {
     switch (p.lanes) {
       case 2: hipLaunchKernelGGL((k_spmv_short<2, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
       case 4: hipLaunchKernelGGL((k_spmv_short<4, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
       case 8: hipLaunchKernelGGL((k_spmv_short<8, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
       case 16: hipLaunchKernelGGL((k_spmv_short<16, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_spmv_short<32, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      case 32: hipLaunchKernelGGL((k_spmv_short<32, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
+      default: return hipErrorInvalidValue;  // lane counts are powers of two
     }
     return hipGetLastError();
   }
@@ -393,32 +413,42 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
   }
   plan.lanes = lanes > 0 ? lanes : pick_lanes(n ? double(nnz) / n : 1.0);
   plan.kmax = 0;
+  plan.tile_rows = WAVE;
   plan.nblk_short = short_blocks(std::max(n, 1), false);
   plan.nlong = 0;
   plan.long_rows = nullptr;
   if (n == 0) return hipSuccess;
   int* flags = nullptr;
-  e = hipMalloc(&flags, sizeof(int) * (n + 2));
+  e = hipMalloc(&flags, sizeof(int) * (n + 5));
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(flags + n, 0, 2 * sizeof(int), s);
+  e = hipMemsetAsync(flags + n, 0, 5 * sizeof(int), s);
   if (e != hipSuccess) {
     (void)hipFree(flags);
     return e;
   }
   hipLaunchKernelGGL(k_find_long, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n,
                      rowptr_dev, flags, flags + n, flags + n + 1);
-  std::vector<int> h(n + 2);
-  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * (n + 2), hipMemcpyDeviceToHost, s);
+  std::vector<int> h(n + 5);
+  e = hipMemcpyAsync(h.data(), flags, sizeof(int) * (n + 5), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(flags);
   plan.maxlen = h[n];
   plan.maxtile = h[n + 1];
   if (e != hipSuccess) return e;
-  // an explicit lane count asks for the row-split kernels
-  if (lanes <= 0 && plan.maxtile <= WAVE * 16) {
-    plan.kmax = plan.maxtile <= WAVE * 8 ? 8 : 16;
-    plan.nblk_short = short_blocks(n, true);
-    return hipSuccess;  // the stream kernel covers long rows too
+  // CSR-stream with the tallest tile (64, 32, 16 or 8 rows) that never
+  // exceeds 512 entries; an explicit lane count asks for the row-split kernels
+  if (lanes <= 0) {
+    for (int q = 0; q < 4; ++q) {
+      if (h[n + 1 + q] <= WAVE * 8) {
+        plan.kmax = 8;
+        plan.tile_rows = WAVE >> q;
+        break;
+      }
+    }
+    if (plan.kmax) {
+      plan.nblk_short = short_blocks(n, true, plan.tile_rows);
+      return hipSuccess;  // the stream kernel covers long rows too
+    }
   }
   std::vector<int> rows;
   for (int i = 0; i < n; ++i)

@@ -32,23 +32,29 @@ MATS = {
     "aniso": lambda: aniso3d(11, 1.0),
     # hub rows longer than 256 entries exercise the workgroup-per-row kernel
     "powerlaw_hubs": lambda: powerlaw(6000, avg_deg=24.0, max_deg=900.0),
-    # 64-row tiles of 513..1024 entries: the 16-entries-per-lane stream kernel
+    # rows of 6..25 entries: CSR-stream with shorter tiles
     "powerlaw_flat": lambda: powerlaw(3000, avg_deg=6.0, max_deg=8.0),
+    # rows of ~20..60 entries: 8-row tiles
+    "powerlaw_dense": lambda: powerlaw(2000, avg_deg=24.0, max_deg=32.0),
 }
 
 
-def _max_tile(A):
+def _stream_rows(A):
+    """Tile height the SpMV plan picks with lanes=0: the tallest of 64, 32,
+    16, 8 rows whose fullest tile holds at most 512 entries, else 0 (the
+    row-split and long-row kernels)."""
     rp = A.rowptr
-    return max(int(rp[min(r + 64, A.n)] - rp[r]) for r in range(0, A.n, 64))
+    for rows in (64, 32, 16, 8):
+        if max(int(rp[min(r + rows, A.n)] - rp[r]) for r in range(0, A.n, rows)) <= 512:
+            return rows
+    return 0
 
 
 def test_spmv_cases_cover_every_kernel():
-    # lanes=0 picks CSR-stream with 8 entries per lane for tiles of <= 512
-    # entries, 16 for <= 1024, and the row-split kernels above that
-    tiles = {k: _max_tile(f()) for k, f in MATS.items()}
-    assert tiles["lap3d"] <= 512
-    assert 512 < tiles["powerlaw_flat"] <= 1024
-    assert tiles["fem3d_A"] > 1024 and tiles["powerlaw_hubs"] > 1024
+    picked = {k: _stream_rows(f()) for k, f in MATS.items()}
+    assert picked["lap3d"] == 64 and picked["fem3d_A"] == 16
+    assert picked["powerlaw_flat"] == 32 and picked["powerlaw_dense"] == 8
+    assert picked["powerlaw_hubs"] == 0
 
 
 @pytest.mark.parametrize("name", list(MATS))
