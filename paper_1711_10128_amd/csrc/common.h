@@ -116,7 +116,11 @@ struct SpmvPlan {
   int maxtile = 0;          // most entries in a 64-row tile
   int kmax = 0;             // CSR-stream entries per lane (8), 0: row-split kernels
   int tile_rows = 64;       // CSR-stream rows per wavefront tile (64, 32, 16, 8)
+  bool adaptive = false;    // CSR-Adaptive blocks (+ long rows) for irregular matrices
+  int nblocks = 0;          // adaptive blocks
+  int2* blocks = nullptr;   // device [first row, end row) per block
 };
+constexpr int ADAPT_MAXNNZ = 512;  // entries per adaptive block (LDS per wavefront)
 constexpr int LONG_ROW = 256;
 
 int pick_lanes(double mean_len);

@@ -1,12 +1,16 @@
 // CSR sparse matrix-vector products (the "MV" of the paper, eq. (3.1)).
 //
-// Three kernels share one epilogue:
+// The kernels share one epilogue:
 //  * CSR-stream (Greathouse and Daga's CSR-Adaptive row blocks, with the
 //    block fixed at 64, 32, 16 or 8 rows): when every tile holds at most 512
 //    entries, a wavefront loads its tile's contiguous run of values and
 //    indices with every lane busy, stages the products in LDS and 64/rows
 //    lanes sum each row; this is the kernel for stencil and mesh matrices;
-//  * row-split: a group of L lanes of a wavefront owns one row (L = 2..64,
+//  * CSR-Adaptive for irregular matrices (power-law graphs): the same tile
+//    steps over variable blocks of at most 64 rows and 512 entries listed at
+//    plan time; longer rows go to the workgroup-per-row kernel;
+//  * row-split (on request of an explicit lane count): a group of L lanes
+//    of a wavefront owns one row (L = 2..64,
 //    picked from the mean row length), loads its entries coalesced and
 //    reduces with cross-lane shuffles; rows of a wavefront are consecutive, so
 //    the value and index streams of the wavefront are contiguous;
@@ -285,6 +289,70 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
 
+// CSR-Adaptive row blocks for irregular matrices: the plan lists blocks of
+// at most 64 consecutive rows and 512 entries (rows with more entries go to
+// the workgroup-per-row kernel).  The tile steps are those of the stream
+// kernel; the number of lanes per row, G, is the largest power of two with
+// G * rows <= 64, chosen per block.
+template <typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_adapt(const SpmvArgs a, const int2* blocks,
+                                                             int nblocks) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  constexpr int WPB = SPMV_THREADS / WAVE;
+  constexpr int KMAX = ADAPT_MAXNNZ / WAVE;
+  __shared__ AT prod[WPB][ADAPT_MAXNNZ];
+  const int* __restrict__ rowptr = a.rowptr;
+  const int* __restrict__ col = a.col;
+  const VT* __restrict__ val = static_cast<const VT*>(a.val);
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  double acc = 0.0;
+  for (int b = blockIdx.x * WPB + wv; b < nblocks; b += gridDim.x * WPB) {
+    const int2 blk = blocks[b];
+    const int r0 = blk.x;
+    const int nr = blk.y - blk.x;  // 1..64
+    const int rb = rowptr[r0 + min(lane, nr)];
+    const int s0 = __shfl(rb, 0, WAVE);
+    const int cnt = rowptr[blk.y] - s0;
+    VT v[KMAX];
+    int c[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const bool ok = lane + WAVE * k < cnt;
+      const int idx = s0 + lane + WAVE * k;
+      v[k] = ok ? val[idx] : VT(0);
+      c[k] = ok ? col[idx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      prod[wv][lane + WAVE * k] = static_cast<AT>(v[k]) * static_cast<AT>(x[c[k]]);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    int G = 1;
+    while (2 * G * nr <= WAVE) G *= 2;
+    const int rl = lane / G;
+    const int g = lane % G;
+    // every lane takes part in both shuffles (a lane outside a divergent
+    // branch would read as zero); the last row's end is the block's end
+    const int lo = __shfl(rb, min(rl, WAVE - 1), WAVE) - s0;
+    const int nx = __shfl(rb, min(rl + 1, WAVE - 1), WAVE) - s0;
+    const int hi = rl + 1 < nr ? nx : cnt;
+    AT sum = 0;
+    if (rl < nr)
+      for (int j = lo + g; j < hi; j += G) sum += prod[wv][j];
+    for (int o = 1; o < G; o <<= 1) sum += __shfl_xor(sum, o, WAVE);
+    if (g == 0 && rl < nr) epilogue<OT>(a, e, r0 + rl, static_cast<double>(sum), acc);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+}
+
 template <typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
                                                             int slot0) {
@@ -350,6 +418,19 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
+  if (p.nblocks > 0 || p.adaptive) {
+    hipError_t e = hipSuccess;
+    if (p.nblocks > 0) {
+      hipLaunchKernelGGL((k_spmv_adapt<VT, XT, AT, OT>), grd, blk, 0, s, a, p.blocks, p.nblocks);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && p.nlong > 0) {
+      hipLaunchKernelGGL((k_spmv_long<VT, XT, AT, OT>), dim3(p.nlong), blk, 0, s, a, p.long_rows,
+                         p.nblk_short);
+      e = hipGetLastError();
+    }
+    return e;
+  }
   if (p.kmax == 8) {
     switch (p.tile_rows) {
       case 64: hipLaunchKernelGGL((k_spmv_stream<8, 64, VT, XT, AT, OT>), grd, blk, 0, s, a); break;
@@ -402,6 +483,48 @@ int pick_lanes(double mean_len) {
   return L;
 }
 
+// Irregular matrices: blocks of consecutive rows with at most 64 rows and
+// ADAPT_MAXNNZ entries, built on the host from a copy of the row pointers;
+// rows longer than ADAPT_MAXNNZ entries are listed for the long-row kernel.
+hipError_t adaptive_plan(SpmvPlan& plan, int n, const int* rowptr_dev, hipStream_t s) {
+  std::vector<int> rp(static_cast<size_t>(n) + 1);
+  hipError_t e = hipMemcpyAsync(rp.data(), rowptr_dev, sizeof(int) * (n + 1),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<int2> blocks;
+  std::vector<int> longs;
+  int i = 0;
+  while (i < n) {
+    if (rp[i + 1] - rp[i] > ADAPT_MAXNNZ) {
+      longs.push_back(i++);
+      continue;
+    }
+    int j = i + 1;
+    while (j < n && j - i < WAVE && rp[j + 1] - rp[i] <= ADAPT_MAXNNZ) ++j;
+    blocks.push_back(make_int2(i, j));
+    i = j;
+  }
+  plan.adaptive = true;
+  plan.nblocks = static_cast<int>(blocks.size());
+  plan.nlong = static_cast<int>(longs.size());
+  plan.nblk_short = std::max(1, std::min((plan.nblocks + 3) / 4, 2048));
+  if (plan.nblocks) {
+    e = hipMalloc(&plan.blocks, sizeof(int2) * blocks.size());
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(plan.blocks, blocks.data(), sizeof(int2) * blocks.size(),
+                         hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess && plan.nlong) {
+    e = hipMalloc(&plan.long_rows, sizeof(int) * longs.size());
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(plan.long_rows, longs.data(), sizeof(int) * longs.size(),
+                         hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
 hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hipStream_t s) {
   plan.n = n;
   int nnz = 0;
@@ -414,6 +537,9 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
   plan.lanes = lanes > 0 ? lanes : pick_lanes(n ? double(nnz) / n : 1.0);
   plan.kmax = 0;
   plan.tile_rows = WAVE;
+  plan.adaptive = false;
+  plan.nblocks = 0;
+  plan.blocks = nullptr;
   plan.nblk_short = short_blocks(std::max(n, 1), false);
   plan.nlong = 0;
   plan.long_rows = nullptr;
@@ -449,6 +575,7 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
       plan.nblk_short = short_blocks(n, true, plan.tile_rows);
       return hipSuccess;  // the stream kernel covers long rows too
     }
+    return adaptive_plan(plan, n, rowptr_dev, s);
   }
   std::vector<int> rows;
   for (int i = 0; i < n; ++i)
@@ -466,8 +593,11 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
 
 void spmv_plan_free(SpmvPlan& plan) {
   if (plan.long_rows) (void)hipFree(plan.long_rows);
+  if (plan.blocks) (void)hipFree(plan.blocks);
   plan.long_rows = nullptr;
+  plan.blocks = nullptr;
   plan.nlong = 0;
+  plan.nblocks = 0;
 }
 
 int spmv_partial_blocks(const SpmvPlan& plan) {

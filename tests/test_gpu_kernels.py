@@ -42,7 +42,8 @@ MATS = {
 def _stream_rows(A):
     """Tile height the SpMV plan picks with lanes=0: the tallest of 64, 32,
     16, 8 rows whose fullest tile holds at most 512 entries, else 0 (the
-    row-split and long-row kernels)."""
+    CSR-Adaptive blocks plus the workgroup-per-row kernel for rows of more
+    than 512 entries)."""
     rp = A.rowptr
     for rows in (64, 32, 16, 8):
         if max(int(rp[min(r + rows, A.n)] - rp[r]) for r in range(0, A.n, rows)) <= 512:
@@ -55,6 +56,8 @@ def test_spmv_cases_cover_every_kernel():
     assert picked["lap3d"] == 64 and picked["fem3d_A"] == 16
     assert picked["powerlaw_flat"] == 32 and picked["powerlaw_dense"] == 8
     assert picked["powerlaw_hubs"] == 0
+    lens = np.diff(MATS["powerlaw_hubs"]().rowptr)
+    assert (lens > 512).any() and (lens <= 512).any()
 
 
 @pytest.mark.parametrize("name", list(MATS))
