@@ -107,12 +107,15 @@ def train_factor(T, name, args, log):
     solvers, X0s = [], []
     for i in range(args.train_count):
         P = make_workload(name, size, seed=12 + i)
-        solvers.append(T.Solver(P.A, P.B, p=min(P.p, P.k), m=P.m, k=P.k, l=1, tol=1e-6,
-                                precond="jacobi", max_cycles=300))
-        X0s.append(start_block(P.A.n, P.k, 12 + i))
+        # pairs (u, A u) from the stored basis of three solves of the instance:
+        # to convergence (smooth, nearly converged vectors) and stopped after 1
+        # and 3 cycles (rough early Krylov vectors); without the early ones the
+        # rows the converged vectors barely touch (graph hubs) are unconstrained
+        for cycles in (300, 1, 3):
+            solvers.append(T.Solver(P.A, P.B, p=min(P.p, P.k), m=P.m, k=P.k, l=1, tol=1e-6,
+                                    precond="jacobi", max_cycles=cycles))
+            X0s.append(start_block(P.A.n, P.k, 12 + i))
     t0 = time.time()
-    # pairs: every stored basis column (the kept Ritz vectors and the last
-    # cycle's Krylov vectors), so the loss sees the whole spectrum
     params, hist = T.train(solvers, X0s, epochs=args.epochs, lr=1e-3, S=min(64, W["m"]))
     for s in solvers:
         s.close()

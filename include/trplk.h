@@ -164,7 +164,10 @@ int trplk_get_eigpairs(trplk_ctx* ctx, double* evals, double* evecs, double* res
 /* ------------------------------------------------------------------------
  * Learned factor.  A two-layer MLP (float32) maps features of each
  * lower-triangular nonzero (i, j) of A to a scalar o_ij; the factor is
- * G(i,i) = exp(o_ii)/sqrt(a_ii), G(i,j) = o_ij/sqrt(a_jj) (j < i), so M =
+ * G(i,i) = exp(o_ii)/sqrt(a_ii), G(i,j) = -o_ij a_ij/(cbar a_jj sqrt(a_ii))
+ * (j < i; cbar = mean |a_ij|/sqrt(a_ii a_jj) over the strictly lower
+ * entries: up to cbar the scale of the first-order symmetric Gauss-Seidel
+ * factor, 1/sqrt(a_jj) for a constant-coefficient stencil), so M =
  * G^T G is SPD by construction and a zero output layer reproduces Jacobi.
  * Inputs: [f_i (8), f_j (8), |a_ij|/sqrt(a_ii a_jj)], f = z-scored row
  * features (degree, a_ii, sum / mean / min / max / std of |a_ij|, j != i,

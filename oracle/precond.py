@@ -17,9 +17,17 @@ set G[i, P_i] = y / sqrt(y_i).  Then (G A)_{ij} = 0 for j in P_i \ {i} and
 
 Learned factor: a two-layer MLP maps features of each lower-triangular
 nonzero (i, j) to a scalar o_ij.  G[i, i] = exp(o_ii) / sqrt(a_ii) and
-G[i, j] = o_ij / sqrt(a_jj) for j < i, so G has a positive diagonal (M is SPD
-by construction) and a zero output layer gives G = D^{-1/2}, i.e. M equals
-the Jacobi preconditioner.  The loss over pairs (r_s, e_s) = (A u_s, u_s)
+G[i, j] = -o_ij a_ij / (cbar a_jj sqrt(a_ii)) for j < i, with cbar the
+mean normalised coupling |a_ij| / sqrt(a_ii a_jj) over the strictly lower
+entries.  G has a positive diagonal (M is SPD by construction) and a zero
+output layer gives G = D^{-1/2}, i.e. M equals the Jacobi preconditioner.
+Up to cbar the off-diagonal scale is that of a first-order factor: o = cbar
+off the diagonal and 0 on it gives D^{-1/2}(I - L D^{-1}) (L the strict
+lower triangle of A), the first-order expansion of D^{1/2}(D + L)^{-1},
+whose G^T G is the symmetric Gauss-Seidel approximation of A^{-1}; for a
+constant-coefficient stencil the scale is 1 / sqrt(a_jj).  So a column
+shared by many rows (a graph hub) enters G^T with weights that fall as
+1/a_jj and the network only has to learn an O(1) factor.  The loss over pairs (r_s, e_s) = (A u_s, u_s)
 from the solver's basis is the mean squared sine of the angle between the
 preconditioned residual M r_s and e_s,
 L = (1/S) sum_s [1 - <M r_s, e_s>^2 / (||M r_s||^2 ||e_s||^2)],
@@ -174,11 +182,31 @@ def mlp_backward(params, cache, do):
     return {"W1": gW1, "b1": gb1, "w2": gw2, "b2": np.asarray(gb2)}
 
 
+def coupling_scale(A):
+    """Mean of |a_ij| / sqrt(a_ii a_jj) over the strictly lower entries of A
+    (1 when there are none)."""
+    r, c, v, _ = tril_entries(A)
+    d = sp.csr_matrix(A).diagonal()
+    off = r != c
+    if not np.any(off):
+        return 1.0
+    cb = float(np.mean(np.abs(v[off]) / np.sqrt(d[r[off]] * d[c[off]])))
+    return cb if cb > 0.0 else 1.0
+
+
+def offdiag_scale(A):
+    """dG[i,j]/do_ij = -a_ij / (cbar a_jj sqrt(a_ii)) per lower nonzero (the
+    diagonal entries' values are unused)."""
+    r, c, v, _ = tril_entries(A)
+    d = sp.csr_matrix(A).diagonal()
+    return -v / (coupling_scale(A) * d[c] * np.sqrt(d[r]))
+
+
 def assemble_G(A, o):
     """G on the lower pattern of A from MLP outputs o (one per tril nonzero)."""
     r, c, v, L = tril_entries(A)
     d = sp.csr_matrix(A).diagonal()
-    g = np.where(r == c, np.exp(o), o) / np.sqrt(d[c])
+    g = np.where(r == c, np.exp(o) / np.sqrt(d[c]), o * offdiag_scale(A))
     return sp.csr_matrix((g, L.indices, L.indptr), shape=L.shape)
 
 
@@ -214,10 +242,9 @@ def loss_and_grad_params(params, A, R, E, x=None):
     G = assemble_G(A, o)
     L, gG = loss_and_grad_G(G, R, E)
     r, c, v, _ = tril_entries(A)
-    # chain rule through G[i,i] = exp(o)/sqrt(a_ii), G[i,j] = o/sqrt(a_jj)
+    # chain rule through G[i,i] = exp(o)/sqrt(a_ii), G[i,j] = o * offdiag_scale
     gvals = G.data
-    d = sp.csr_matrix(A).diagonal()
-    do = np.where(r == c, gG * gvals, gG / np.sqrt(d[c]))
+    do = np.where(r == c, gG * gvals, gG * offdiag_scale(A))
     return L, mlp_backward(params, cache, do), G
 
 

@@ -360,7 +360,10 @@ def init_params(seed=0):
 def train(solvers, X0s, epochs, lr=1e-3, S=24, params=None, log=None):
     """Train the factor's MLP on the GPU: solve each instance once (Jacobi or
     whatever preconditioner its Solver holds) to harvest pairs (u, A u) from
-    its basis, then full-batch Adam over the instances for `epochs` epochs."""
+    its basis, then full-batch Adam over the instances for `epochs` epochs.
+    A Solver whose max_cycles stops it after a cycle or two contributes the
+    rough early Krylov vectors; pairing those with a converged solve of the
+    same instance constrains the rows that converged vectors barely touch."""
     P = init_params() if params is None else np.array(params, dtype=np.float32)
     m = np.zeros(MLP_NPARAM, dtype=np.float32)
     v = np.zeros(MLP_NPARAM, dtype=np.float32)

@@ -258,6 +258,7 @@ struct LearnArgs {
   const double* gvalT = nullptr;
   const float* Fz = nullptr;
   const double* dinv = nullptr;
+  const double* cbar = nullptr;  // mean normalised coupling (device scalar)
   const float* P = nullptr;   // parameters (device)
   const double* Rr = nullptr; // pairs, row-major n x S
   const double* Er = nullptr;
@@ -280,8 +281,12 @@ hipError_t tril_count(int n, const int* rowptr, const int* col, int* cnt, hipStr
 hipError_t tril_fill(int n, const int* rowptr, const int* col, const double* val, const int* lrow,
                      int* lcol, int* lr, double* lval, hipStream_t s);
 hipError_t mlp_forward(int64_t nnz, const int* lr, const int* lc, const double* lval,
-                       const float* Fz, const double* dinv, const float* P, double* gval,
-                       float* oval, hipStream_t s);
+                       const float* Fz, const double* dinv, const double* cbar, const float* P,
+                       double* gval, float* oval, hipStream_t s);
+// cbar = mean |a_ij| / sqrt(a_ii a_jj) over the strictly lower entries;
+// part holds 2 * 256 doubles
+hipError_t coupling_scale(int64_t nnz, const int* lr, const int* lc, const double* lval,
+                          const double* dinv, double* part, double* cbar, hipStream_t s);
 int learn_blocks();
 hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s);
 hipError_t learn_colnorms(int n, int S, const double* Er, double* part, double* en, hipStream_t s);

@@ -4,9 +4,17 @@
 // Network (per lower-triangular nonzero (i, j) of A, float32):
 //   x = [f_i (8), f_j (8), |a_ij| / sqrt(a_ii a_jj)]          (17 inputs)
 //   h = relu(W1 x + b1)  (64),   o = w2 . h + b2
-//   G(i,i) = exp(o) / sqrt(a_ii),   G(i,j) = o / sqrt(a_jj)  (j < i)
-// so G has a positive diagonal (M is SPD by construction) and a zero output
-// layer gives G = D^{-1/2}, i.e. the Jacobi preconditioner.
+//   G(i,i) = exp(o) / sqrt(a_ii),   G(i,j) = -o a_ij / (cbar a_jj sqrt(a_ii))  (j < i)
+// with cbar the mean normalised coupling |a_ij| / sqrt(a_ii a_jj) over the
+// strictly lower entries, so G has a positive diagonal (M is SPD by
+// construction) and a zero output layer gives G = D^{-1/2}, i.e. the Jacobi
+// preconditioner.  Up to the constant cbar the off-diagonal scale is that of
+// a first-order factor (o = cbar off the diagonal, 0 on it, gives
+// D^{-1/2}(I - L D^{-1}), L the strict lower triangle, the expansion of the
+// symmetric Gauss-Seidel factor D^{1/2}(D + L)^{-1}): a column j shared by
+// many rows (a graph hub) enters G^T with weights falling as 1/a_jj, so the
+// network learns an O(1) factor that carries over between sizes, and for a
+// constant-coefficient stencil the scale reduces to 1 / sqrt(a_jj).
 // Features f_i: degree, a_ii, sum / mean / min / max / std of |a_ij| (j != i)
 // and a_ii / sum, each z-scored over the rows of A.
 // Loss over pairs (r_s, e_s) = (A u_s, u_s) from the solver's basis: the
@@ -168,8 +176,8 @@ __device__ __forceinline__ void make_input(const float* Fz, const double* dinv, 
 
 __global__ __launch_bounds__(256) void k_mlp_forward(int64_t nnz, const int* lr, const int* lc,
                                                      const double* lval, const float* Fz,
-                                                     const double* dinv, const float* P,
-                                                     double* gval, float* oval) {
+                                                     const double* dinv, const double* cbar,
+                                                     const float* P, double* gval, float* oval) {
   __shared__ float sP[NP];
   load_params(P, sP);
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(int64_t nnz, const int* lr,
     }
     if (oval) oval[e] = o;
     const double od = static_cast<double>(o);
-    gval[e] = (i == j ? exp(od) : od) * sqrt(dinv[j]);
+    gval[e] = i == j ? exp(od) * sqrt(dinv[j]) : -od * lval[e] * dinv[j] * sqrt(dinv[i]) / *cbar;
   }
 }
 
@@ -294,9 +302,10 @@ __global__ void k_colnorms(int nblk, int S, const double* part, double* en) {
 }
 
 // dL/do_e: sampled products on the pattern, then the chain rule through
-// G = exp(o)/sqrt(a_ii) (diagonal) or o/sqrt(a_jj)
+// G = exp(o)/sqrt(a_ii) (diagonal) or -o a_ij / (cbar a_jj sqrt(a_ii))
 __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int S, const int* lr, const int* lc,
-                                               const double* gval, const double* dinv,
+                                               const double* lval, const double* gval,
+                                               const double* dinv, const double* cbar,
                                                const double* Y, const double* Z, const double* Uz,
                                                const double* R, float* dout) {
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int S, const int* lr
     const double* rj = R + static_cast<int64_t>(j) * S;
     double g = 0.0;
     for (int s = 0; s < S; ++s) g += yi[s] * zj[s] + ui[s] * rj[s];
-    const double dodg = (i == j) ? gval[e] : sqrt(dinv[j]);
+    const double dodg = (i == j) ? gval[e] : -lval[e] * dinv[j] * sqrt(dinv[i]) / *cbar;
     dout[e] = static_cast<float>(g * dodg);
   }
 }
@@ -460,10 +469,63 @@ hipError_t tril_fill(int n, const int* rowptr, const int* col, const double* val
 }
 
 hipError_t mlp_forward(int64_t nnz, const int* lr, const int* lc, const double* lval,
-                       const float* Fz, const double* dinv, const float* P, double* gval,
-                       float* oval, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_forward, dim3(g1(nnz)), dim3(256), 0, s, nnz, lr, lc, lval, Fz, dinv, P,
-                     gval, oval);
+                       const float* Fz, const double* dinv, const double* cbar, const float* P,
+                       double* gval, float* oval, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3(g1(nnz)), dim3(256), 0, s, nnz, lr, lc, lval, Fz, dinv,
+                     cbar, P, gval, oval);
+  return hipGetLastError();
+}
+
+// cbar: mean of |a_ij| sqrt(dinv_i dinv_j) over the strictly lower entries
+// (1 when there are none), two fixed-order stages
+constexpr int CB_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_coupling_part(int64_t nnz, const int* lr, const int* lc,
+                                                       const double* lval, const double* dinv,
+                                                       double* part) {
+  double sum = 0.0, cnt = 0.0;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = lr[e], j = lc[e];
+    if (i != j) {
+      sum += fabs(lval[e]) * sqrt(dinv[i] * dinv[j]);
+      cnt += 1.0;
+    }
+  }
+  __shared__ double red[2][256 / WAVE];
+  sum = wave_sum(sum);
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    red[0][threadIdx.x / WAVE] = sum;
+    red[1][threadIdx.x / WAVE] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void k_coupling_final(int nblk, const double* part, double* cbar) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  cbar[0] = (b > 0.0 && a > 0.0) ? a / b : 1.0;
+}
+
+hipError_t coupling_scale(int64_t nnz, const int* lr, const int* lc, const double* lval,
+                          const double* dinv, double* part, double* cbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_coupling_part, dim3(CB_BLOCKS), dim3(256), 0, s, nnz, lr, lc, lval, dinv,
+                     part);
+  hipLaunchKernelGGL(k_coupling_final, dim3(1), dim3(64), 0, s, CB_BLOCKS, part, cbar);
   return hipGetLastError();
 }
 
@@ -484,7 +546,8 @@ hipError_t learn_loss_grad(const LearnArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_make_z, dim3(g1(static_cast<int64_t>(a.n) * S)), bs, 0, s, a.n, S, a.coef,
                      a.Er, a.Q, a.Z);
   hipLaunchKernelGGL(k_spmm, gs, bs, 0, s, a.n, S, a.Lrow, a.lc, a.gval, a.Z, nullptr, a.Uz);
-  hipLaunchKernelGGL(k_sddmm, dim3(g1(a.nnz)), bs, 0, s, a.nnz, S, a.lr, a.lc, a.gval, a.dinv, a.Y,
+  hipLaunchKernelGGL(k_sddmm, dim3(g1(a.nnz)), bs, 0, s, a.nnz, S, a.lr, a.lc, a.lval, a.gval,
+                     a.dinv, a.cbar, a.Y,
                      a.Z, a.Uz, a.Rr, a.dout);
   hipLaunchKernelGGL(k_mlp_backward, dim3(nb), bs, 0, s, a.nnz, a.lr, a.lc, a.lval, a.Fz, a.dinv,
                      a.P, a.dout, a.part);

@@ -155,6 +155,7 @@ struct trplk_ctx {
     double* loss = nullptr;
     double* grad = nullptr;
     double* scratch = nullptr;
+    double* cbar = nullptr;
   } L;
 };
 
@@ -1006,6 +1007,8 @@ int learn_prepare(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &L.loss, 1));
   HIPCHK(c, dalloc(c, &L.grad, MLP_NPARAM));
   HIPCHK(c, dalloc(c, &L.part, static_cast<int64_t>(learn_blocks()) * MLP_NPARAM));
+  HIPCHK(c, dalloc(c, &L.cbar, 1));
+  HIPCHK(c, coupling_scale(L.nnz, L.lr, L.Lcol, L.lval, L.dinv, L.part, L.cbar, s));
   HIPCHK(c, hipStreamSynchronize(s));
   L.ready = true;
   return TRPLK_OK;
@@ -1030,7 +1033,8 @@ int learn_alloc_pairs(trplk_ctx* c) {
 int learn_forward(trplk_ctx* c, const float* params_host) {
   auto& L = c->L;
   HIPCHK(c, hipMemcpyAsync(L.P, params_host, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->s));
-  HIPCHK(c, mlp_forward(L.nnz, L.lr, L.Lcol, L.lval, L.Fz, L.dinv, L.P, L.gval, nullptr, c->s));
+  HIPCHK(c, mlp_forward(L.nnz, L.lr, L.Lcol, L.lval, L.Fz, L.dinv, L.cbar, L.P, L.gval, nullptr,
+                        c->s));
   HIPCHK(c, gather_values(L.nnz, L.gval, L.permd, L.gvalT, c->s));
   return TRPLK_OK;
 }
@@ -1040,7 +1044,7 @@ int learn_loss_grad_run(trplk_ctx* c) {
   LearnArgs a;
   a.n = c->n; a.nnz = L.nnz; a.S = L.S; a.Lrow = L.Lrow; a.lc = L.Lcol; a.lr = L.lr;
   a.lval = L.lval; a.Trow = L.Trow; a.Tcol = L.Tcol; a.gval = L.gval; a.gvalT = L.gvalT;
-  a.Fz = L.Fz; a.dinv = L.dinv; a.P = L.P; a.Rr = L.Rr; a.Er = L.Er; a.en = L.w; a.Y = L.Y;
+  a.Fz = L.Fz; a.dinv = L.dinv; a.cbar = L.cbar; a.P = L.P; a.Rr = L.Rr; a.Er = L.Er; a.en = L.w; a.Y = L.Y;
   a.Q = L.D; a.Z = L.Z; a.Uz = L.Uu; a.coef = L.coef; a.dout = L.dout; a.part = L.part;
   a.loss = L.loss; a.grad = L.grad;
   HIPCHK(c, learn_loss_grad(a, c->s));

@@ -187,3 +187,27 @@ def test_adam_training_lowers_loss():
         PC.adam_step(params, g, st, lr=1e-3)
     L1 = PC.loss_and_grad_params(params, A, R, E, x)[0]
     assert L1 < 0.9 * L0
+
+
+def test_learned_offdiagonal_scale_by_hand():
+    """G[i,j] = -o a_ij / (cbar a_jj sqrt(a_ii)), cbar the mean of
+    |a_ij| / sqrt(a_ii a_jj) over the strictly lower entries.  Checked on a
+    1-D Laplacian (every coupling 1/2, so the scale is 1/sqrt(a_jj) = 1/sqrt 2)
+    and on a 3 x 3 matrix with unequal couplings, worked out by hand."""
+    import scipy.sparse as sp
+    T1 = sp.diags([-np.ones(4), 2 * np.ones(5), -np.ones(4)], [-1, 0, 1], format="csr")
+    assert PC.coupling_scale(T1) == 0.5
+    o = np.full(9, 0.3)                      # 5 diagonal + 4 lower entries
+    G = PC.assemble_G(T1, o).toarray()
+    assert np.isclose(G[1, 0], 0.3 / np.sqrt(2.0), rtol=1e-15)
+    assert np.isclose(G[3, 3], np.exp(0.3) / np.sqrt(2.0), rtol=1e-15)
+    # a_00 = 9, a_11 = 4, a_22 = 1; a_10 = -3 (coupling 3/6 = 1/2), a_20 = -1
+    # (coupling 1/3), a_21 = 0.5 (coupling 1/4): cbar = (1/2 + 1/3 + 1/4)/3 = 13/36
+    A = sp.csr_matrix(np.array([[9.0, -3.0, -1.0], [-3.0, 4.0, 0.5], [-1.0, 0.5, 1.0]]))
+    assert np.isclose(PC.coupling_scale(A), 13.0 / 36.0, rtol=1e-15)
+    G = PC.assemble_G(A, np.array([0.0, 2.0, 0.0, 2.0, 2.0, 0.0])).toarray()
+    cb = 13.0 / 36.0
+    assert np.isclose(G[1, 0], 2.0 * 3.0 / (cb * 9.0 * 2.0), rtol=1e-15)
+    assert np.isclose(G[2, 0], 2.0 * 1.0 / (cb * 9.0 * 1.0), rtol=1e-15)
+    assert np.isclose(G[2, 1], 2.0 * -0.5 / (cb * 4.0 * 1.0), rtol=1e-15)
+    assert np.isclose(G[0, 0], 1.0 / 3.0, rtol=1e-15)
