@@ -82,6 +82,11 @@ def parse():
     ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--profile-only", action="store_true", help="one profiled solve (for rocprofv3 runs)")
+    ap.add_argument("--sweep", default="", choices=["", "m", "l"],
+                    help="ablation instead of the timed solve: vary the basis size m (paper "
+                         "Fig. 2) or the number l of previous Ritz vectors (+K, Fig. 3; l = 0 is "
+                         "thick-restart Lanczos) and print one JSON line with every setting")
+    ap.add_argument("--sweep-values", default="", help="comma-separated values (default per sweep)")
     ap.add_argument("--max-cycles", type=int, default=5000,
                     help="cap the restart cycles (a capped run reports per-cycle time)")
     return ap.parse_args()
@@ -125,6 +130,38 @@ def train_factor(T, name, args, log):
                     "epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1]}
 
 
+def run_sweep(args, T, P, Ad, Bd, Xd, precond, precision, log):
+    """Ablation of the paper's Sec. 5 (Figs. 2 and 3) on a synthetic operator:
+    one warm and one timed solve per setting, everything else fixed."""
+    import torch
+    if args.sweep == "m":
+        vals = [int(v) for v in args.sweep_values.split(",")] if args.sweep_values else \
+            [v for v in (P.k + 4, P.k + 8, P.k + 12, 2 * P.k, P.k + 28, 64) if P.k + 2 <= v <= 64]
+    else:
+        vals = [int(v) for v in args.sweep_values.split(",")] if args.sweep_values else \
+            [0, 1, 2, 3, 4, 5]
+    rows = []
+    for v in vals:
+        m, l = (v, 1) if args.sweep == "m" else (P.m, v)
+        S = T.Solver(Ad, Bd, p=P.p, m=m, k=P.k, l=l, tol=P.tol, precond=precond,
+                     precision=precision, max_cycles=args.max_cycles)
+        S.solve(Xd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.solve(Xd)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ev, _, res, conv = S.eigpairs(vectors=False)
+        S.close()
+        rows.append({"m": m, "l": l, "s": round(dt, 4), "cycles": st["cycles"],
+                     "matvecs": st["matvecs"], "converged": bool(conv.all()),
+                     "max_resid_rel": float(np.max(res) / st["normA"])})
+        log(f"# sweep {args.sweep}={v}: {st['cycles']} cycles, {st['matvecs']} MV, {dt:.3f} s")
+    print(json.dumps({"sweep": args.sweep, "workload": args.workload, "n": P.A.n,
+                      "p": P.p, "k": P.k, "precond": precond, "precision": precision,
+                      "tol": P.tol, "results": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,6 +188,10 @@ def main():
     Bd = T.DeviceCSR(P.B) if P.B is not None else None
     Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
     torch.cuda.synchronize()
+
+    if args.sweep:
+        return run_sweep(args, T, P, Ad, Bd, Xd, "fsai" if precond == "learned" else precond,
+                         precision, log)
 
     learned = None
     learn_info = None
