@@ -232,7 +232,10 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_short(const SpmvArgs a) {
 // entries s0+i, s0+i+64, ... and stages the products in LDS; then
 // G = 64 / ROWS lanes sum each row's segment (lane rl + ROWS*g takes the
 // entries g, g+G, ... of row rl, combined by a fixed shuffle tree) and lane
-// rl < ROWS runs the epilogue of row r0 + rl.
+// rl < ROWS runs the epilogue of row r0 + rl.  The loop is software
+// pipelined over the wavefront's tiles: the values and indices of the next
+// tile and the row pointers of the one after are loaded while the current
+// tile gathers x and sums its rows.
 template <int KMAX, int ROWS, typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) {
   EpiCtx e{1.0, 0.0, 0};
@@ -255,16 +258,18 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
   const int g = lane / ROWS;
   const int n = a.n;
   const int ntile = (n + ROWS - 1) / ROWS;
+  const int stride = gridDim.x * WPB;
   double acc = 0.0;
-  for (int tile = blockIdx.x * WPB + wv; tile < ntile; tile += gridDim.x * WPB) {
-    const int r0 = tile * ROWS;
-    const int row = r0 + rl;
-    const int rb = rowptr[min(row, n)];
-    const int rt = rowptr[min(r0 + ROWS, n)];
+  // row pointers of tile t (clamped to the last tile past the end)
+  auto ptrs = [&](int t, int& rb, int& rt) {
+    const int tc = min(t, ntile - 1);
+    rb = rowptr[min(tc * ROWS + rl, n)];
+    rt = rowptr[min(tc * ROWS + ROWS, n)];
+  };
+  // values and indices of a tile whose row pointers are rb, rt (none if !live)
+  auto entries = [&](bool live, int rb, int rt, VT* v, int* c) {
     const int s0 = __shfl(rb, 0, WAVE);
-    const int cnt = rt - s0;
-    VT v[KMAX];
-    int c[KMAX];
+    const int cnt = live ? rt - s0 : 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       const bool ok = lane + WAVE * k < cnt;
@@ -272,19 +277,54 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
       v[k] = ok ? val[idx] : VT(0);
       c[k] = ok ? col[idx] : 0;
     }
+  };
+  int tile = blockIdx.x * WPB + wv;
+  if (tile < ntile) {
+    int rb, rt, rbn, rtn;
+    VT v[KMAX];
+    int c[KMAX];
+    ptrs(tile, rb, rt);
+    entries(true, rb, rt, v, c);
+    int tn = tile + stride;
+    ptrs(tn, rbn, rtn);
+    while (true) {
+      AT pr[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      prod[wv][lane + WAVE * k] = static_cast<AT>(v[k]) * static_cast<AT>(x[c[k]]);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    // lanes rl + 1 < ROWS hold the next row's start
-    const int nx = __shfl(rb, (rl + 1) & (WAVE - 1), WAVE);
-    const int end = (rl == ROWS - 1 || row + 1 > n) ? rt : nx;
-    AT sum = 0;
-    for (int j = rb - s0 + g; j < end - s0; j += G) sum += prod[wv][j];
+      for (int k = 0; k < KMAX; ++k) pr[k] = static_cast<AT>(v[k]) * static_cast<AT>(x[c[k]]);
+      const bool more = tn < ntile;
+      VT vn[KMAX];
+      int cn[KMAX];
+      entries(more, rbn, rtn, vn, cn);
+      const int t2 = tn + stride;
+      int rb2, rt2;
+      ptrs(t2, rb2, rt2);
 #pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o * ROWS, WAVE);
-    if (g == 0 && row < n) epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int k = 0; k < KMAX; ++k) prod[wv][lane + WAVE * k] = pr[k];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int s0 = __shfl(rb, 0, WAVE);
+      // lanes rl + 1 < ROWS hold the next row's start
+      const int nx = __shfl(rb, (rl + 1) & (WAVE - 1), WAVE);
+      const int row = tile * ROWS + rl;
+      const int end = (rl == ROWS - 1 || row + 1 > n) ? rt : nx;
+      AT sum = 0;
+      for (int j = rb - s0 + g; j < end - s0; j += G) sum += prod[wv][j];
+#pragma unroll
+      for (int o = G / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o * ROWS, WAVE);
+      if (g == 0 && row < n) epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      if (!more) break;
+      tile = tn;
+      rb = rbn;
+      rt = rtn;
+      tn = t2;
+      rbn = rb2;
+      rtn = rt2;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        v[k] = vn[k];
+        c[k] = cn[k];
+      }
+    }
   }
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
@@ -403,14 +443,14 @@ __global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen, i
   for (int q = 0; q < 4; ++q) atomicMax(maxtile + q, mt[q]);
 }
 
-// Grid of the tile kernels: one 64-row tile per wavefront up to a cap.
-// The CSR-stream kernel is latency-bound and runs best with every block
-// resident at once (8 blocks of 4 wavefronts per compute unit, measured on
-// MI355X for n = 2.1M); the row-split kernels with a deeper grid.
+// Grid of the tile kernels: one tile per wavefront up to a cap.  The
+// software-pipelined CSR-stream kernel runs best with two rounds of resident
+// blocks (16 blocks of 4 wavefronts per compute unit, measured on MI355X for
+// the 27-point and 7-point matrices); the row-split kernels with a deeper grid.
 int short_blocks(int n, bool stream, int rows = WAVE) {
   const int tiles = (n + rows - 1) / rows;
   const int want = (tiles + SPMV_THREADS / WAVE - 1) / (SPMV_THREADS / WAVE);
-  return std::max(1, std::min(want, stream ? 2048 : 8192));
+  return std::max(1, std::min(want, stream ? 4096 : 8192));
 }
 
 template <typename VT, typename XT, typename AT, typename OT>
