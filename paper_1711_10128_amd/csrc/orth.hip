@@ -341,33 +341,49 @@ hipError_t launch_width(int mode, const OrthArgs& a, int need, int nblk, hipStre
 }
 
 // ------------------------------------------------------------- finish --
-// One workgroup of 16 wavefronts sums the per-block partials: lane j of
-// wavefront w adds blocks w, w+16, ... of output j (coalesced across lanes),
-// then the 16 partial sums are added in a fixed order.
+// One workgroup of 16 wavefronts sums the per-block partials.  Output column
+// j of a sum is owned by lane j % 64: wavefront w adds blocks w, w+16, ...
+// (coalesced across lanes) with FIN_UNR independent loads in flight per lane
+// (summed in a fixed order), then the 16 wavefront sums are added in a fixed
+// order.  fin_sum2 reduces two column ranges of up to 64 columns in the same
+// pass (the T column and the first Gram-Schmidt coefficients).
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_WAVES = FIN_THREADS / WAVE;
+constexpr int FIN_UNR = 16;
+
+// Sum over the blocks of partial[b * stride + src + idx] for one lane; 0 if
+// the lane has no column.
+__device__ __forceinline__ double fin_lane(const FinishArgs& f, int src, int idx, bool on) {
+  const int lane_w = threadIdx.x / WAVE;
+  const double* p = f.partial + src + idx;
+  const int64_t st = f.stride;
+  double t[FIN_UNR];
+#pragma unroll
+  for (int u = 0; u < FIN_UNR; ++u) t[u] = 0.0;
+  if (on) {
+    int b = lane_w;
+    for (; b + (FIN_UNR - 1) * FIN_WAVES < f.nblk; b += FIN_UNR * FIN_WAVES) {
+#pragma unroll
+      for (int u = 0; u < FIN_UNR; ++u) t[u] += p[(b + u * FIN_WAVES) * st];
+    }
+#pragma unroll
+    for (int u = 0; u < FIN_UNR; ++u)
+      if (b + u * FIN_WAVES < f.nblk) t[u] += p[(b + u * FIN_WAVES) * st];
+  }
+  // fixed pairwise order
+#pragma unroll
+  for (int w = FIN_UNR / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) t[u] += t[u + w];
+  return t[0];
+}
 
 __device__ void fin_sum(const FinishArgs& f, int src, int cnt, double* dst, double (*red)[WAVE]) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   for (int c0 = 0; c0 < cnt; c0 += WAVE) {
     const int idx = c0 + lane;
-    double t = 0.0;
-    if (idx < cnt) {
-      // four independent loads in flight per step (fixed summation order)
-      const double* p = f.partial + src + idx;
-      const int64_t st = f.stride;
-      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-      int b = wv;
-      for (; b + 3 * FIN_WAVES < f.nblk; b += 4 * FIN_WAVES) {
-        t0 += p[b * st];
-        t1 += p[(b + FIN_WAVES) * st];
-        t2 += p[(b + 2 * FIN_WAVES) * st];
-        t3 += p[(b + 3 * FIN_WAVES) * st];
-      }
-      for (; b < f.nblk; b += FIN_WAVES) t0 += p[b * st];
-      t = (t0 + t1) + (t2 + t3);
-    }
+    const double t = fin_lane(f, src, idx, idx < cnt);
     red[wv][lane] = t;
     __syncthreads();
     if (wv == 0 && idx < cnt) {
@@ -377,6 +393,69 @@ __device__ void fin_sum(const FinishArgs& f, int src, int cnt, double* dst, doub
     }
     __syncthreads();
   }
+}
+
+// Two ranges at once (each at most 64 columns): waves 0..7 take range A,
+// waves 8..15 range B, each half summing every 8th block.
+__device__ void fin_sum2(const FinishArgs& f, int srcA, int cntA, double* dstA, int srcB, int cntB,
+                         double* dstB, double (*red)[WAVE]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  constexpr int HALF = FIN_WAVES / 2;
+  const bool isA = wv < HALF;
+  const int src = isA ? srcA : srcB;
+  const int cnt = isA ? cntA : cntB;
+  const double* p = f.partial + src + lane;
+  const int64_t st = f.stride;
+  double t[FIN_UNR];
+#pragma unroll
+  for (int u = 0; u < FIN_UNR; ++u) t[u] = 0.0;
+  if (lane < cnt) {
+    int b = wv % HALF;
+    for (; b + (FIN_UNR - 1) * HALF < f.nblk; b += FIN_UNR * HALF) {
+#pragma unroll
+      for (int u = 0; u < FIN_UNR; ++u) t[u] += p[(b + u * HALF) * st];
+    }
+#pragma unroll
+    for (int u = 0; u < FIN_UNR; ++u)
+      if (b + u * HALF < f.nblk) t[u] += p[(b + u * HALF) * st];
+  }
+#pragma unroll
+  for (int w = FIN_UNR / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) t[u] += t[u + w];
+  red[wv][lane] = t[0];
+  __syncthreads();
+  if ((wv == 0 || wv == HALF) && lane < cnt) {
+    double u = 0.0;
+    for (int q = 0; q < HALF; ++q) u += red[wv + q][lane];
+    (isA ? dstA : dstB)[lane] = u;
+  }
+  __syncthreads();
+}
+
+// sum of v[c]^2, c < cnt (<= 2 * 64), by the first wavefront: lane j takes
+// c = j and j + 64, then a fixed shuffle tree
+__device__ __forceinline__ double sumsq_wave(const double* v, int cnt) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double t = 0.0;
+  for (int c = lane; c < cnt; c += WAVE) t += v[c] * v[c];
+  return wave_sum(t);
+}
+
+// One column summed over the blocks by all 1024 threads.
+__device__ double fin_one(const FinishArgs& f, int src, double (*red)[WAVE]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < f.nblk; b += FIN_THREADS) t += f.partial[b * static_cast<int64_t>(f.stride) + src];
+  t = wave_sum(t);
+  if (lane == 0) red[0][wv] = t;
+  __syncthreads();
+  double u = 0.0;
+  for (int q = 0; q < FIN_WAVES; ++q) u += red[0][q];
+  __syncthreads();
+  return u;
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
@@ -393,19 +472,22 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       // new column j = nb of T; the dots cover U columns 0..nb (after the
       // ncol_fixed locked columns)
       const int j = nb;
-      fin_sum(f, f.ncol_fixed, j + 1, v0, red);
       const int nc = f.ncol_fixed + nb + 1;
-      if (f.mode == FIN_TH) fin_sum(f, ORTH_MAXCOL, nc, v1, red);
+      if (f.mode == FIN_TH && j + 1 <= WAVE && nc <= WAVE) {
+        fin_sum2(f, f.ncol_fixed, j + 1, v0, ORTH_MAXCOL, nc, v1, red);
+      } else {
+        fin_sum(f, f.ncol_fixed, j + 1, v0, red);
+        if (f.mode == FIN_TH) fin_sum(f, ORTH_MAXCOL, nc, v1, red);
+      }
       for (int r = tid; r <= j; r += blockDim.x) {
         f.T[r + static_cast<int64_t>(j) * f.ldT] = v0[r];
         f.T[j + static_cast<int64_t>(r) * f.ldT] = v0[r];
       }
       if (f.mode == FIN_TH) {
         for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v1[c];
-        if (tid == 0) {
-          double t = 0.0;
-          for (int c = 0; c < nc; ++c) t += v1[c] * v1[c];
-          st->h1norm2 = t;
+        if (tid < WAVE) {
+          const double t = sumsq_wave(v1, nc);
+          if (tid == 0) st->h1norm2 = t;
         }
       }
       __syncthreads();
@@ -438,17 +520,16 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       const int nc = f.ncol_fixed + nb + f.extra;
       fin_sum(f, 0, nc, v0, red);
       for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v0[c];
-      if (f.mode == FIN_H && tid == 0) {
-        double t = 0.0;
-        for (int c = 0; c < nc; ++c) t += v0[c] * v0[c];
-        st->h1norm2 = t;
+      if (f.mode == FIN_H && tid < WAVE) {
+        const double t = sumsq_wave(v0, nc);
+        if (tid == 0) st->h1norm2 = t;
       }
       break;
     }
     case FIN_NORM: {
-      fin_sum(f, 0, 1, v0, red);
+      const double b2s = fin_one(f, 0, red);
       if (tid == 0) {
-        const double b2 = v0[0];
+        const double b2 = b2s;
         st->beta2 = b2;
         st->cnt_norm += 1;
         const bool finite = (b2 == b2) && (b2 < 1.0e308);
