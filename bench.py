@@ -77,11 +77,14 @@ def parse():
     ap.add_argument("--precond", default="", help="timed form's preconditioner (default per workload)")
     ap.add_argument("--precision", default="", choices=["", "fp64", "mixed"])
     ap.add_argument("--variants", type=int, default=1, help="also time the other forms once")
-    ap.add_argument("--cpu-cycles", type=int, default=1, help="oracle cycles in the CPU sample (0 = skip)")
+    ap.add_argument("--cpu-cycles", type=int, default=3, help="oracle cycles in the CPU sample (0 = skip)")
     ap.add_argument("--train-count", type=int, default=6, help="learned factor: training instances")
     ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--profile-only", action="store_true", help="one profiled solve (for rocprofv3 runs)")
+    ap.add_argument("--method", default="trplk", choices=["trplk", "pl1", "pl1_practical"],
+                    help="outer method of the timed solve: TRPL+K (Alg. 1) or PL+1 (Alg. 2, "
+                         "the smallest pair; p = k = l = 1, the other methods as variants)")
     ap.add_argument("--sweep", default="", choices=["", "m", "l"],
                     help="ablation instead of the timed solve: vary the basis size m (paper "
                          "Fig. 2) or the number l of previous Ritz vectors (+K, Fig. 3; l = 0 is "
@@ -182,6 +185,9 @@ def main():
     precision = args.precision or W["form"][1]
     t0 = time.time()
     P = make_workload(args.workload, args.size)
+    if args.method != "trplk":
+        import dataclasses
+        P = dataclasses.replace(P, p=1, k=1, l=1)
     X0 = start_block(P.A.n, P.k, P.seed)
     log(f"# workload {args.workload} n={P.A.n} nnz={P.A.nnz} generated in {time.time() - t0:.1f}s")
     Ad = T.DeviceCSR(P.A)
@@ -200,10 +206,11 @@ def main():
     if need_learned:
         learned, learn_info = train_factor(T, args.workload, args, log)
 
-    def make_solver(pc, pr, profile=False):
+    def make_solver(pc, pr, profile=False, method=None):
         base = "jacobi" if pc == "learned" else pc
         s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
-                     precision=pr, profile=profile, max_cycles=args.max_cycles)
+                     precision=pr, profile=profile, max_cycles=args.max_cycles,
+                     method=method or args.method)
         if pc == "learned":
             s.learned_factor(learned)
         return s
@@ -297,13 +304,18 @@ def main():
     # ---- other forms (one warm solve each, outside the timed region) ----
     variants = {}
     if args.variants:
-        forms = [("jacobi", "fp64"), ("fsai", "fp64"), ("fsai", "mixed"), ("jacobi", "mixed")]
+        forms = [("jacobi", "fp64", None), ("fsai", "fp64", None), ("fsai", "mixed", None),
+                 ("jacobi", "mixed", None)]
         if learned is not None:
-            forms += [("learned", "fp64"), ("learned", "mixed")]
-        for pc, pr in forms:
-            if (pc, pr) == (precond, precision):
+            forms += [("learned", "fp64", None), ("learned", "mixed", None)]
+        if args.method != "trplk":
+            # PL+1: the other outer methods with the timed form's preconditioner
+            forms = [(precond, precision, mm) for mm in ("trplk", "pl1", "pl1_practical")
+                     if mm != args.method]
+        for pc, pr, mm in forms:
+            if mm is None and (pc, pr) == (precond, precision):
                 continue
-            V = make_solver(pc, pr)
+            V = make_solver(pc, pr, method=mm)
             V.solve(Xd)
             torch.cuda.synchronize()
             a = time.perf_counter()
@@ -312,8 +324,9 @@ def main():
             b = time.perf_counter()
             evv, _, rv, cv = V.eigpairs(vectors=False)
             V.close()
-            log(f"# variant {pc}-{pr}: {sv['cycles']} cycles, {b - a:.3f} s")
-            variants[f"{pc}-{pr}"] = {
+            label = f"{pc}-{pr}" if mm is None else f"{mm}-{pc}-{pr}"
+            log(f"# variant {label}: {sv['cycles']} cycles, {b - a:.3f} s")
+            variants[label] = {
                 "s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
                 "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
                 "max_resid_rel": float(np.max(rv) / normA),
@@ -352,8 +365,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l=1 tol=1e-8, "
-                               f"{precond} {precision}",
+        "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l={P.l} tol=1e-8, "
+                               f"{precond} {precision}"
+                               + ("" if args.method == "trplk" else f", {args.method}"),
                    "name": args.workload, "n": P.A.n, "nnz": P.A.nnz,
                    "generalized": P.B is not None},
         "converged": converged,

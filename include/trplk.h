@@ -64,6 +64,16 @@ enum {
                      restart rotation always float64 */
 };
 enum { TRPLK_LOCK_AUTO = 0, TRPLK_LOCK_SOFT = 1, TRPLK_LOCK_HARD = 2 };
+/* outer method */
+enum {
+  TRPLK_METHOD_TRPLK = 0,        /* TRPL+K, Alg. 1 */
+  TRPLK_METHOD_PL1 = 1,          /* PL+1, Alg. 2 (Sec. 4.2): the smallest pair (p = 1); the
+                                    Krylov block is B-orthonormal within itself, the search
+                                    direction is made conjugate to the previous one with
+                                    respect to A - rho(x_{k-1}) B (step 7) */
+  TRPLK_METHOD_PL1_PRACTICAL = 2 /* PL+1 with p_k = g_k + p_{k-1} w(m+2), the combination the
+                                    Ritz vector uses (end of Sec. 4.2) */
+};
 enum { TRPLK_NORM_INF = 0, TRPLK_NORM_FRO = 1 };
 
 typedef struct trplk_csr {
@@ -97,6 +107,9 @@ typedef struct trplk_opts {
   int32_t fallback_window; /* FSAI / FACTOR: when the target residual has not halved for this
                               many cycles, continue with Jacobi (M may change between cycles,
                               Sec. 3); 0 selects 50, negative disables */
+  int32_t method;     /* TRPLK_METHOD_*.  PL+1 needs p = 1 and FP64; its projection space
+                         [x_k, G_k, p_{k-1}] has at most m columns (Krylov block m - 2); the
+                         start vector is the first column of x0; cycles = outer steps */
 } trplk_opts;
 
 typedef struct trplk_stats {
@@ -126,7 +139,7 @@ typedef struct trplk_stats {
 typedef struct trplk_ctx trplk_ctx;
 
 /* Fill *o with defaults: p=1 m=18 k=8 l=1 tol=1e-8 norm=INF max_cycles=5000
- * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0. */
+ * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0 method=TRPLK. */
 void trplk_default_opts(trplk_opts* o);
 
 /* Create a solver context for the pencil (A, B) (paper eq. (1.1)).

@@ -16,6 +16,9 @@ import numpy as np
 from ._build import LIB
 
 MEM_HOST, MEM_DEVICE = 0, 1
+# outer method: TRPL+K (Alg. 1), PL+1 with the conjugate search direction of
+# Alg. 2 step 7, PL+1 with the practical direction g_k + p_{k-1} w(m+2)
+METHOD = {"trplk": 0, "pl1": 1, "pl1_practical": 2}
 PREC = {"none": 0, "jacobi": 1, "fsai": 2, "factor": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 LOCKING = {"auto": 0, "soft": 1, "hard": 2}
@@ -41,7 +44,8 @@ class _Opts(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("locking", ctypes.c_int32),
                 ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32)]
+                ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -180,7 +184,7 @@ class Solver:
 
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
-                 profile=False, mixed_switch=0.0, fallback_window=0):
+                 profile=False, mixed_switch=0.0, fallback_window=0, method="trplk"):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -189,6 +193,7 @@ class Solver:
         o.precond, o.precision, o.locking = PREC[precond], PRECISION[precision], LOCKING[locking]
         o.fsai_cap, o.profile, o.mixed_switch = fsai_cap, int(bool(profile)), mixed_switch
         o.fallback_window = fallback_window
+        o.method = METHOD[method]
         self.opts = o
         self.n = int(A.n)
         self.p = p

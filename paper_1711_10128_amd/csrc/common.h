@@ -197,6 +197,8 @@ struct FinishArgs {
   double* out = nullptr;
   int cnt = 0;
   int nvec = 1;
+  int skip_first = 0;   // FIN_TH / FIN_H / FIN_H2: zero the coefficient of the first active
+                        // column (a basis orthogonalised among its own columns only)
 };
 hipError_t finish(const FinishArgs& f, hipStream_t s);
 

@@ -484,6 +484,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
         f.T[j + static_cast<int64_t>(r) * f.ldT] = v0[r];
       }
       if (f.mode == FIN_TH) {
+        if (f.skip_first) {
+          if (tid == 0) v1[f.ncol_fixed] = 0.0;
+          __syncthreads();
+        }
         for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v1[c];
         if (tid < WAVE) {
           const double t = sumsq_wave(v1, nc);
@@ -519,6 +523,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
     case FIN_H2: {
       const int nc = f.ncol_fixed + nb + f.extra;
       fin_sum(f, 0, nc, v0, red);
+      if (f.skip_first) {
+        if (tid == 0) v0[f.ncol_fixed] = 0.0;
+        __syncthreads();
+      }
       for (int c = tid; c < nc; c += blockDim.x) f.h[c] = v0[c];
       if (f.mode == FIN_H && tid < WAVE) {
         const double t = sumsq_wave(v0, nc);

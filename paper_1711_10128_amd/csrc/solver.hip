@@ -94,6 +94,9 @@ struct trplk_ctx {
   float* y32 = nullptr;
   float* wtmp32 = nullptr;
   double* Xprev = nullptr;
+  double* pl1_Ap = nullptr;  // PL+1: A p and B p of the search direction (p itself in Xprev)
+  double* pl1_Bp = nullptr;
+  double* pl1_s = nullptr;   // PL+1: border of Q^T B Q (2 * ORTH_MAXCOL)
   double* T = nullptr;
   double* theta = nullptr;
   double* Y = nullptr;
@@ -362,6 +365,7 @@ struct Solver {
   hipStream_t s;
   int nbh = 0;  // host-side expected basis size
   bool keepT = false;  // the next cycle keeps T(0:kact,0:kact) (recomputed X^T A X)
+  int skip0 = 0;  // PL+1: inner vectors are not orthogonalised against the first column
 
   double* Ucol(int j) const { return c->W + (c->u0 + j) * ld; }
   double* AUcol(int j) const { return c->AW + (c->u0 + j) * ld; }
@@ -408,7 +412,7 @@ struct Solver {
       S.check(orth(ORTH_DOT, a), "orth h1");
       FinishArgs f;
       f.mode = FIN_H; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
-      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
+      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf; f.skip_first = skip0;
       S.check(fin(f), "fin h1");
     }
     {
@@ -418,7 +422,7 @@ struct Solver {
       S.check(orth(ORTH_UPD_DOT, a), "orth upd-dot");
       FinishArgs f;
       f.mode = FIN_H2; f.partial = c->partial; f.nblk = nblk(ORTH_UPD_DOT); f.stride = orth_stride();
-      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
+      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf; f.skip_first = skip0;
       S.check(fin(f), "fin h2");
     }
     {
@@ -510,7 +514,7 @@ struct Solver {
     FinishArgs f;
     f.mode = with_h1 ? FIN_TH : FIN_T; f.partial = c->partial; f.nblk = nblk(ORTH_DOT);
     f.stride = orth_stride(); f.state = c->st; f.ncol_fixed = c->u0; f.T = c->T; f.ldT = SYEV_MAXB;
-    f.h = c->hbuf;
+    f.h = c->hbuf; f.skip_first = skip0;
     S.check(fin(f), "fin tcol");
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
@@ -598,7 +602,117 @@ struct Solver {
   }
 
   int run(const double* x0, int32_t mem, trplk_stats* out);
+  int run_pl1(const double* x0, int32_t mem, trplk_stats* out);
+  void collect_profile();
 };
+
+// ---------------------------------------------------------- PL+1 helpers --
+// Small dense symmetric algebra on the host for the (<= 64) projected pencil.
+
+// Cholesky T = L L^T of an n x n row-major matrix; false if not positive
+// definite (a pivot <= eps_rel * the largest diagonal).
+bool host_cholesky(const std::vector<double>& T, int n, std::vector<double>& L) {
+  L.assign(static_cast<size_t>(n) * n, 0.0);
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(T[i * n + i]));
+  for (int j = 0; j < n; ++j) {
+    double d = T[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 1e-12 * dmax)) return false;
+    const double ljj = std::sqrt(d);
+    L[j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double v = T[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / ljj;
+    }
+  }
+  return true;
+}
+
+// Cyclic Jacobi eigenvalue iteration (row-major, symmetric); on return the
+// eigenvalues are in `lam` and the eigenvectors in the columns of V.
+void host_jacobi_eig(std::vector<double> C, int n, std::vector<double>& lam,
+                     std::vector<double>& V) {
+  V.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, fro = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        fro += C[i * n + j] * C[i * n + j];
+        if (i != j) off += C[i * n + j] * C[i * n + j];
+      }
+    if (off <= 1e-30 * fro) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = C[p * n + q];
+        if (apq == 0.0) continue;
+        const double tau = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double ckp = C[k * n + p], ckq = C[k * n + q];
+          C[k * n + p] = cs * ckp - sn * ckq;
+          C[k * n + q] = sn * ckp + cs * ckq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double cpk = C[p * n + k], cqk = C[q * n + k];
+          C[p * n + k] = cs * cpk - sn * cqk;
+          C[q * n + k] = sn * cpk + cs * cqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = cs * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = C[i * n + i];
+}
+
+// Lowest eigenpair of the pencil (TA, TB), TB = L L^T: w = L^{-T} y with
+// (L^{-1} TA L^{-T}) y = lambda y.  Row-major n x n inputs.
+void host_lowest_pair(const std::vector<double>& TA, const std::vector<double>& L, int n,
+                      double& lambda, std::vector<double>& w) {
+  // X = L^{-1} TA (forward substitution per column), C = X L^{-T}
+  std::vector<double> X(static_cast<size_t>(n) * n), C(static_cast<size_t>(n) * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      double v = TA[i * n + j];
+      for (int k = 0; k < i; ++k) v -= L[i * n + k] * X[k * n + j];
+      X[i * n + j] = v / L[i * n + i];
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = X[i * n + j];
+      for (int k = 0; k < j; ++k) v -= C[i * n + k] * L[j * n + k];
+      C[i * n + j] = v / L[j * n + j];
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) C[i * n + j] = C[j * n + i] = 0.5 * (C[i * n + j] + C[j * n + i]);
+  std::vector<double> lam, V;
+  host_jacobi_eig(C, n, lam, V);
+  int imin = 0;
+  for (int i = 1; i < n; ++i)
+    if (lam[i] < lam[imin]) imin = i;
+  lambda = lam[imin];
+  w.assign(n, 0.0);
+  for (int i = n - 1; i >= 0; --i) {  // L^T w = y
+    double v = V[i * n + imin];
+    for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * w[k];
+    w[i] = v / L[i * n + i];
+  }
+}
+
+double quad(const std::vector<double>& M, int n, const std::vector<double>& a,
+            const std::vector<double>& b) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) s += a[i] * M[i * n + j] * b[j];
+  return s;
+}
 
 int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   const trplk_opts& o = c->o;
@@ -818,6 +932,14 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   stt.solve_ms = ms;
   stt.nconv = nconv;
   stt.status = done ? TRPLK_OK : TRPLK_ENOCONV;
+  collect_profile();
+  c->solved = true;
+  if (out) *out = stt;
+  return stt.status;
+}
+
+void Solver::collect_profile() {
+  trplk_stats& stt = c->stats;
   if (c->o.profile) {
     for (const Prof& pr : c->prof) {
       float e = 0.f;
@@ -838,6 +960,223 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       }
     }
   }
+}
+
+// PL+1 (Alg. 2, Sec. 4.2) for the smallest pair.  Per outer step: the
+// preconditioned Krylov block G_k, B-orthonormal within itself (the first
+// column x_k takes part in the T columns but not in the Gram-Schmidt
+// coefficients), the previous search direction p_{k-1} appended with its
+// stored products, the border of S = Q^T B Q from one dot pass, the lowest
+// pair of the projected pencil (T, S) on the host, and one rotation of
+// [Q, A Q, B Q] to [x_{k+1}, p_k].
+int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
+  const trplk_opts& o = c->o;
+  const int m = o.m;
+  const int mk = m - 2;
+  const bool conj = o.method == TRPLK_METHOD_PL1;
+  const double normA = (o.norm == TRPLK_NORM_FRO) ? c->normA_fro : c->normA_inf;
+  const double thr = o.tol * normA;
+  trplk_stats& stt = c->stats;
+  stt = trplk_stats{};
+  stt.normA = normA;
+  c->prof.clear();
+  c->evused = 0;
+  c->u0 = 0;
+  c->solved = false;
+  c->fp32_phase = false;
+  int r;
+  if (!c->pl1_Ap) HIPCHK(c, dalloc(c, &c->pl1_Ap, c->ld));
+  if (c->hasB && !c->pl1_Bp) HIPCHK(c, dalloc(c, &c->pl1_Bp, c->ld));
+  if (!c->pl1_s) HIPCHK(c, dalloc(c, &c->pl1_s, 2 * ORTH_MAXCOL));
+  HIPCHK(c, hipEventRecord(c->ev0, s));
+  HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
+  HIPCHK(c, hipMemsetAsync(c->T, 0, sizeof(double) * SYEV_MAXB * SYEV_MAXB, s));
+  // ---- x_0: B-normalised, A x_0, rho_0 = x_0^T A x_0, r_0 ----
+  skip0 = 0;
+  nbh = 0;
+  if ((r = load_w(x0, mem))) return r;
+  if ((r = add_vector(BREAKDOWN_TOL))) return r;
+  if ((r = rayleigh_ritz(1, 1))) return r;
+  if (c->rep_h->nb != 1) return set_err(c, TRPLK_EINVAL, "start vector is zero");
+  long long prev_app = c->rep_h->cnt_append;
+  stt.matvecs = prev_app;
+  double rho = c->rep_h->theta[0], res = c->rep_h->res[0], rho_prev = 0.0;
+  bool have_p = false;
+  bool done = res <= thr;
+  std::vector<double> Th(static_cast<size_t>(SYEV_MAXB) * SYEV_MAXB), Sh(2 * ORTH_MAXCOL);
+  std::vector<double> Yh(static_cast<size_t>(SYEV_MAXB) * 2), th2(2);
+  int cycle = 0;
+  skip0 = 1;
+  while (!done && cycle < o.max_cycles) {
+    ++cycle;
+    HIPCHK(c, set_state(c->st, SET_RHO, rho, 0, s));
+    HIPCHK(c, set_state(c->st, SET_NB, 0.0, 1, s));
+    HIPCHK(c, reset_T(c->T, SYEV_MAXB, SYEV_MAXB, 1, c->theta, 0, s));
+    nbh = 1;
+    {  // u_1 = M r_k
+      const bool fac = c->prec >= TRPLK_PREC_FSAI;
+      const int next = c->prec == TRPLK_PREC_JACOBI ? NEXT_JACOBI
+                       : c->prec == TRPLK_PREC_NONE ? NEXT_IDENT : NEXT_STORE_V;
+      HIPCHK(c, restart_residual(n, AUcol(0), BUcol(0), c->theta, 0, next, c->dinv, c->w,
+                                 fac ? c->vtmp : nullptr, nullptr, s));
+      if (fac) HIPCHK(c, apply_factor());
+      stt.precs += 1;
+    }
+    // ---- G_k: the preconditioned Krylov block (step 4) ----
+    if ((r = stage_reset(BREAKDOWN_TOL))) return r;
+    for (int j = 0; j < mk; ++j) {
+      if ((r = project(j == 0))) return r;
+      const bool more = j < mk - 1;
+      if ((r = append(more ? 1 : 0))) return r;
+      if ((r = tcol(more))) return r;
+      ++nbh;
+      if (more) stt.precs += 1;
+    }
+    HIPCHK(c, set_state(c->st, SET_SKIP, 0.0, 0, s));
+    HIPCHK(c, hipMemcpyAsync(c->rep_h, c->st, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    int nq = c->rep_h->nb;  // 1 + columns of G_k kept
+    // ---- Q_k = [x_k, G_k, p_{k-1}] (step 5) ----
+    if (have_p) {
+      Status S;
+      S.check(copy_cols(n, c->Xprev, ld, Ucol(nq), ld, 1, s), "p");
+      S.check(copy_cols(n, c->pl1_Ap, ld, AUcol(nq), ld, 1, s), "Ap");
+      if (c->hasB) S.check(copy_cols(n, c->pl1_Bp, ld, BUcol(nq), ld, 1, s), "Bp");
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = nq + 1; a.ncol_max = nq + 1; a.Md0 = Ucol(0);
+      a.vec0 = AUcol(nq); a.nvec = 1; a.partial = c->partial;
+      S.check(orth(ORTH_DOT, a), "T p");
+      FinishArgs f;
+      f.mode = FIN_TCOL; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
+      f.T = c->T; f.ldT = SYEV_MAXB; f.cnt = nq;
+      S.check(fin(f), "fin T p");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where);
+      ++nq;
+    }
+    {  // border of S = Q^T B Q: rows of B x_k and B p_{k-1}
+      Status S;
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = nq; a.ncol_max = nq; a.Md0 = Ucol(0); a.Md1 = Ucol(0);
+      a.vec0 = BUcol(0); a.vec1 = BUcol(nq - 1); a.nvec = 2; a.partial = c->partial;
+      S.check(orth(ORTH_DOT, a), "S border");
+      FinishArgs f;
+      f.mode = FIN_SUM; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
+      f.out = c->pl1_s; f.cnt = ORTH_MAXCOL + nq;
+      S.check(fin(f), "fin S border");
+      S.check(hipMemcpyAsync(Th.data(), c->T, sizeof(double) * Th.size(), hipMemcpyDeviceToHost, s), "T d2h");
+      S.check(hipMemcpyAsync(Sh.data(), c->pl1_s, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, s), "S d2h");
+      S.check(hipStreamSynchronize(s), "sync");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where);
+    }
+    // ---- lowest pair of Q^T A Q w = rho Q^T B Q w (steps 5-6) ----
+    bool use_p = have_p;
+    int nqq = nq;
+    std::vector<double> TA, TB, L;
+    auto build = [&](int q) {
+      TA.assign(static_cast<size_t>(q) * q, 0.0);
+      TB.assign(static_cast<size_t>(q) * q, 0.0);
+      for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) TA[i * q + j] = 0.5 * (Th[i + j * SYEV_MAXB] + Th[j + i * SYEV_MAXB]);
+      for (int i = 0; i < q; ++i) TB[i * q + i] = 1.0;  // G_k is B-orthonormal
+      for (int j = 0; j < q; ++j) TB[j] = TB[j * q] = Sh[j];
+      if (use_p) {
+        const int e = q - 1;
+        for (int j = 0; j < q; ++j) TB[e * q + j] = TB[j * q + e] = Sh[ORTH_MAXCOL + j];
+        TB[0 * q + e] = TB[e * q + 0] = 0.5 * (Sh[e] + Sh[ORTH_MAXCOL]);
+      }
+    };
+    build(nqq);
+    if (!host_cholesky(TB, nqq, L)) {
+      if (!use_p) return set_err(c, TRPLK_ENOTSPD, "PL+1: projected B not positive definite");
+      use_p = false;  // p_{k-1} numerically inside span{x_k, G_k}
+      --nqq;
+      build(nqq);
+      if (!host_cholesky(TB, nqq, L)) return set_err(c, TRPLK_ENOTSPD, "PL+1: projected B not positive definite");
+    }
+    double lambda;
+    std::vector<double> wv;
+    host_lowest_pair(TA, L, nqq, lambda, wv);
+    if (!std::isfinite(lambda)) return set_err(c, TRPLK_ENUMERIC, "non-finite Ritz value");
+    // g_k coordinates, then the search direction p_k (step 7 or the practical one)
+    std::vector<double> zg(wv), zp;
+    zg[0] = 0.0;
+    if (use_p) zg[nqq - 1] = 0.0;
+    zp = zg;
+    if (use_p) {
+      const int e = nqq - 1;
+      if (conj) {
+        std::vector<double> K(TA);
+        for (size_t i = 0; i < K.size(); ++i) K[i] -= rho_prev * TB[i];
+        std::vector<double> ee(nqq, 0.0);
+        ee[e] = 1.0;
+        const double cc = quad(K, nqq, ee, zg) / quad(K, nqq, ee, ee);
+        zp[e] = -cc;
+      } else {
+        zp[e] = wv[e];
+      }
+    }
+    const double nw = std::sqrt(quad(TB, nqq, wv, wv)), np = std::sqrt(quad(TB, nqq, zp, zp));
+    if (!(np > 0.0) || !(nw > 0.0)) return set_err(c, TRPLK_ENUMERIC, "PL+1: zero direction");
+    std::fill(Yh.begin(), Yh.end(), 0.0);
+    for (int i = 0; i < nqq; ++i) {
+      Yh[i] = wv[i] / nw;
+      Yh[SYEV_MAXB + i] = zp[i] / np;
+    }
+    th2[0] = lambda;
+    th2[1] = 0.0;
+    {
+      Status S;
+      S.check(hipMemcpyAsync(c->Y, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice, s), "Y h2d");
+      S.check(hipMemcpyAsync(c->theta, th2.data(), sizeof(double) * 2, hipMemcpyHostToDevice, s), "theta h2d");
+      S.check(set_state(c->st, SET_NB, 0.0, nqq, s), "nb");
+      RotArgs ra;
+      ra.n = n; ra.kout = 2; ra.state = c->st; ra.Y = c->Y; ra.ldY = SYEV_MAXB; ra.b_max = m;
+      ra.U = Ucol(0); ra.AU = AUcol(0); ra.BU = c->hasB ? BUcol(0) : nullptr; ra.ld = ld;
+      ra.theta = c->theta; ra.partial = c->partial;
+      {
+        const int64_t mats = c->hasB ? 3 : 2;
+        ProfScope ps(c, PC_ROT, 8LL * n * (nqq + 2) * mats);
+        S.check(rotate(ra, c->rot_nblk, s), "rotate");
+      }
+      FinishArgs f;
+      f.mode = FIN_RES; f.partial = c->partial; f.nblk = c->rot_nblk; f.stride = 128;
+      f.out = c->resout; f.cnt = 1;
+      S.check(fin(f), "fin res");
+      // p_k and its products for the next step
+      S.check(copy_cols(n, Ucol(1), ld, c->Xprev, ld, 1, s), "save p");
+      S.check(copy_cols(n, AUcol(1), ld, c->pl1_Ap, ld, 1, s), "save Ap");
+      if (c->hasB) S.check(copy_cols(n, BUcol(1), ld, c->pl1_Bp, ld, 1, s), "save Bp");
+      hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, c->st, c->theta, c->resout, 1, 1,
+                         c->rep_d);
+      S.check(hipGetLastError(), "report");
+      S.check(hipMemcpyAsync(c->rep_h, c->rep_d, sizeof(Report), hipMemcpyDeviceToHost, s), "d2h");
+      S.check(hipStreamSynchronize(s), "sync");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+    }
+    if (c->rep_h->bad) return set_err(c, TRPLK_ENOTSPD, "B-norm squared not positive or not finite");
+    stt.matvecs += c->rep_h->cnt_append - prev_app;
+    prev_app = c->rep_h->cnt_append;
+    have_p = true;
+    rho_prev = rho;
+    rho = lambda;
+    res = c->rep_h->res[0];
+    done = res <= thr;
+  }
+  skip0 = 0;
+  stt.cycles = cycle;
+  stt.bmatvecs = c->hasB ? c->rep_h->cnt_norm : 0;
+  c->theta_out.assign(1, rho);
+  c->res_out.assign(1, res);
+  c->nout = 1;
+  c->conv_out.assign(1, res <= thr ? 1 : 0);
+  HIPCHK(c, hipEventRecord(c->ev1, s));
+  HIPCHK(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  stt.solve_ms = ms;
+  stt.nconv = done ? 1 : 0;
+  stt.status = done ? TRPLK_OK : TRPLK_ENOCONV;
+  collect_profile();
   c->solved = true;
   if (out) *out = stt;
   return stt.status;
@@ -1183,9 +1522,25 @@ void trplk_default_opts(trplk_opts* o) {
   o->fsai_cap = 0;
   o->profile = 0;
   o->mixed_switch = 0.0;
+  o->method = TRPLK_METHOD_TRPLK;
 }
 
 static int check_opts(const trplk_opts* o, int n, std::string& why) {
+  if (o->method < TRPLK_METHOD_TRPLK || o->method > TRPLK_METHOD_PL1_PRACTICAL) {
+    why = "bad method";
+    return TRPLK_EINVAL;
+  }
+  if (o->method != TRPLK_METHOD_TRPLK) {
+    if (o->p != 1) { why = "PL+1 computes one pair: p must be 1"; return TRPLK_EINVAL; }
+    if (o->precision != TRPLK_FP64) { why = "PL+1 runs in float64"; return TRPLK_EINVAL; }
+    if (!(3 <= o->m && o->m <= SYEV_MAXB && o->m <= n)) { why = "PL+1 needs 3 <= m <= min(n, 64)"; return TRPLK_EINVAL; }
+    if (o->k < 1 || o->l < 0) { why = "k must be >= 1 and l >= 0"; return TRPLK_EINVAL; }
+    if (!(o->tol > 0.0)) { why = "tol must be > 0"; return TRPLK_EINVAL; }
+    if (o->max_cycles < 1) { why = "max_cycles must be >= 1"; return TRPLK_EINVAL; }
+    if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
+    if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
+    return TRPLK_OK;
+  }
   if (o->p < 1) { why = "p must be >= 1"; return TRPLK_EINVAL; }
   if (o->k < 1) { why = "k must be >= 1"; return TRPLK_EINVAL; }
   if (o->l < 0) { why = "l must be >= 0"; return TRPLK_EINVAL; }
@@ -1275,7 +1630,8 @@ int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   if (!x0) return set_err(c, TRPLK_EINVAL, "x0 is NULL");
   if (c->prec >= TRPLK_PREC_FSAI && !c->G.val) return set_err(c, TRPLK_EINVAL, "no factor installed");
   if (mem == TRPLK_MEM_HOST) {
-    for (int64_t i = 0; i < static_cast<int64_t>(c->n) * c->o.k; ++i)
+    const int64_t ncols = c->o.method == TRPLK_METHOD_TRPLK ? c->o.k : 1;
+    for (int64_t i = 0; i < static_cast<int64_t>(c->n) * ncols; ++i)
       if (!std::isfinite(x0[i])) return set_err(c, TRPLK_ENUMERIC, "non-finite start block");
   }
   int r = ensure_workspace(c);
@@ -1285,7 +1641,7 @@ int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   c->stats.setup_ms = c->stats.setup_ms;
   const double setup = c->stats.setup_ms;
   const int prec0 = c->prec;
-  r = S.run(x0, mem, st);
+  r = c->o.method == TRPLK_METHOD_TRPLK ? S.run(x0, mem, st) : S.run_pl1(x0, mem, st);
   c->prec = prec0;  // a fallback inside the solve does not outlive it
   c->stats.setup_ms = setup;
   if (st) st->setup_ms = setup;

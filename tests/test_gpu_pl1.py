@@ -1,0 +1,79 @@
+"""PL+1 (Sec. 4.2, Algorithm 2) on the GPU against the FP64 oracle, through
+the C ABI: both search directions, standard and generalized problems, the
+outer step count, the Ritz value of every step and the final pair."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pl1 as PL  # noqa: E402
+from oracle import trplk as O  # noqa: E402
+from workloads import fem3d, lap2d, powerlaw  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_1711_10128_amd as T
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    T.lib()
+    return T
+
+
+def _x0(n, seed=12):
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+
+
+CASES = {
+    "lap2d_conj": (lambda: (lap2d(30).to_scipy(), None), 6, "pl1"),
+    "lap2d_practical": (lambda: (lap2d(30).to_scipy(), None), 6, "pl1_practical"),
+    "powerlaw_conj": (lambda: (powerlaw(2000, seed=13).to_scipy(), None), 4, "pl1"),
+    "fem_generalized_conj": (lambda: tuple(M.to_scipy() for M in fem3d(7, 0.5, 12)), 5, "pl1"),
+    "fem_generalized_practical": (lambda: tuple(M.to_scipy() for M in fem3d(7, 0.5, 12)), 5,
+                                  "pl1_practical"),
+}
+
+
+class _Csr:
+    def __init__(self, M):
+        M = M.tocsr()
+        M.sort_indices()
+        self.n = M.shape[0]
+        self.rowptr = M.indptr.astype(np.int32)
+        self.col = M.indices.astype(np.int32)
+        self.val = M.data.astype(np.float64)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pl1_matches_oracle(T, name):
+    make, mk, method = CASES[name]
+    A, B = make()
+    n = A.shape[0]
+    print(f"pl1 {name} n={n} m={mk + 2} {method}", flush=True)
+    x0 = _x0(n)
+    variant = "conjugate" if method == "pl1" else "practical"
+    ref = PL.solve(A, B, mk, 1e-10, x0, apply_M=O.jacobi(A), variant=variant, keep_history=True)
+    assert ref.converged
+    S = T.Solver(_Csr(A), None if B is None else _Csr(B), p=1, m=mk + 2, k=1, l=1, tol=1e-10,
+                 method=method)
+    st = S.solve(x0[:, None])
+    ev, X, res, conv = S.eigpairs()
+    S.close()
+    print(f"  gpu {st['cycles']} steps {st['matvecs']} MV theta {ev[0]:.15e}; oracle "
+          f"{ref.cycles} steps {ref.matvecs} MV theta {ref.theta:.15e}", flush=True)
+    assert conv[0] and res[0] <= 1e-10 * ref.normA
+    # the same iteration: one outer step more or less at the tolerance edge
+    assert abs(st["cycles"] - ref.cycles) <= 1
+    assert abs(st["matvecs"] - ref.matvecs) <= mk
+    assert abs(ev[0] - ref.theta) <= max(1e-10 * abs(ref.theta), 16 * 2.2e-16 * ref.normA)
+    x = X[:, 0]
+    Bx = x if B is None else B @ x
+    assert abs(x @ Bx - 1.0) <= 1e-10
+
+
+def test_pl1_rejects_p_above_one(T):
+    A = lap2d(10).to_scipy()
+    with pytest.raises(Exception):
+        T.Solver(_Csr(A), None, p=2, m=8, k=2, l=1, method="pl1")
