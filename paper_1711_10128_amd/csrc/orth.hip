@@ -13,7 +13,7 @@
 // j, j+64, ... of the slab.  Dot products accumulate in registers across
 // all slabs of the workgroup and are reduced once at the end.  The fused
 // pass w <- w - U h, h2 = U^T w needs the sum over all columns of a row,
-// which the 8 wavefronts combine through a double-buffered LDS array (one
+// which the wavefronts combine through a double-buffered LDS array (one
 // barrier per slab), so it reads U once.
 // Reductions are deterministic: fixed per-lane order, fixed shuffle tree,
 // and a fixed-order sum over blocks in the finishing kernel.
@@ -28,8 +28,6 @@ namespace trplk {
 
 namespace {
 
-constexpr int OT_THREADS = 512;
-constexpr int NWV = OT_THREADS / WAVE;  // 8
 constexpr int STRIDE = 2 * ORTH_MAXCOL; // partial doubles per block
 constexpr int ORTH_RP = 1;              // row pairs per lane per slab: dot passes
 constexpr int UPD_RP = 4;               // update-only pass
@@ -89,13 +87,15 @@ using Part = std::integral_constant<bool, false>;
 
 // MODE ORTH_DOT: acc[i][v] = (column c of Md_v) . vec_v over the block's
 // slabs.  MODE ORTH_UPD_DOT: w <- w - Mu h, then acc[i][0] = Md1(:,c) . w.
-template <int CPW, int MODE, int NV, bool SAME, int RP, bool NT>
-__global__ __launch_bounds__(OT_THREADS) void k_orth(const OrthArgs a) {
+// NWV wavefronts per workgroup, wavefront w owning columns w + NWV * i.
+template <int CPW, int MODE, int NV, bool SAME, int RP, bool NT, int NWV>
+__global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
   constexpr int SLABP = WAVE * RP;  // row pairs per slab
   if (a.state && a.state->skip) return;
   const int ncol = a.ncol_fixed + (a.state ? a.state->nb : 0) + a.ncol_extra;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wv = threadIdx.x / WAVE;
+  // wave-uniform: column indices, coefficients and column tests stay scalar
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t ld = a.ld;
   const int n = a.n;
 
@@ -305,39 +305,41 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
   }
 }
 
-template <int CPW, int RP, bool NT>
+template <int CPW, int RP, bool NT, int NWV>
 hipError_t launch_rp(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
-  const dim3 g(nblk), b(OT_THREADS);
+  const dim3 g(nblk), b(NWV * WAVE);
   const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
   if (mode == ORTH_DOT) {
     if (a.nvec == 1) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RP, NT>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RP, NT, NWV>), g, b, 0, s, a);
     } else if (same) {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RP, NT>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RP, NT, NWV>), g, b, 0, s, a);
     } else {
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false, RP, NT>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, false, RP, NT, NWV>), g, b, 0, s, a);
     }
   } else {
-    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true, RP, NT>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false, RP, NT>), g, b, 0, s, a);
+    if (same) hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, true, RP, NT, NWV>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_orth<CPW, ORTH_UPD_DOT, 1, false, RP, NT, NWV>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
-template <int CPW, bool NT>
+template <int CPW, bool NT, int NWV>
 hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
-  return launch_rp<CPW, ORTH_RP, NT>(mode, a, nblk, s);
+  return launch_rp<CPW, ORTH_RP, NT, NWV>(mode, a, nblk, s);
 }
 
 template <bool NT>
 hipError_t launch_width(int mode, const OrthArgs& a, int need, int nblk, hipStream_t s) {
-  // columns a wavefront may own: ceil(max columns / 8)
-  const int cpw = (std::max(need, 1) + NWV - 1) / NWV;
-  if (cpw <= 1) return launch_cpw<1, NT>(mode, a, nblk, s);
-  if (cpw <= 2) return launch_cpw<2, NT>(mode, a, nblk, s);
-  if (cpw <= 4) return launch_cpw<4, NT>(mode, a, nblk, s);
-  if (cpw <= 8) return launch_cpw<8, NT>(mode, a, nblk, s);
-  return launch_cpw<16, NT>(mode, a, nblk, s);
+  // 8 wavefronts owning ceil(need / 8) columns each (16 wavefronts of 8
+  // columns for wide bases measured slower on MI355X: the per-slab LDS
+  // exchange and barrier over 16 wavefronts cost more than the occupancy gains)
+  const int cpw = (std::max(need, 1) + 7) / 8;
+  if (cpw > 8) return launch_cpw<16, NT, 8>(mode, a, nblk, s);
+  if (cpw <= 1) return launch_cpw<1, NT, 8>(mode, a, nblk, s);
+  if (cpw <= 2) return launch_cpw<2, NT, 8>(mode, a, nblk, s);
+  if (cpw <= 4) return launch_cpw<4, NT, 8>(mode, a, nblk, s);
+  return launch_cpw<8, NT, 8>(mode, a, nblk, s);
 }
 
 // ------------------------------------------------------------- finish --
