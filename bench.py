@@ -37,7 +37,10 @@ WORKLOADS = {
     "fem3d": dict(gen=dict(Ne=97, sigma=0.5), p=16, m=48, k=24, form=("fsai", "mixed"),
                   desc="Q1 FEM pencil 97^3 elements, lognormal sigma=0.5, consistent mass"),
     "powerlaw": dict(gen=dict(n=1_000_000), p=20, m=48, k=24, form=("learned", "fp64"),
-                     desc="shifted Laplacian of a Chung-Lu power-law graph, n=1e6"),
+                     desc="shifted Laplacian of a Chung-Lu power-law graph, n=1e6",
+                     # gather-bound SpMV and well-separated wanted eigenvalues: a long
+                     # float32 phase pays here (measured), unlike on the grids
+                     mixed_switch=1e-5),
     "aniso3d": dict(gen=dict(N=256, sigma=1.0), p=50, m=64, k=32, form=("learned", "mixed"),
                     desc="anisotropic 7-point diffusion 256^3, lognormal sigma=1"),
 }
@@ -210,7 +213,7 @@ def main():
         base = "jacobi" if pc == "learned" else pc
         s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
                      precision=pr, profile=profile, max_cycles=args.max_cycles,
-                     method=method or args.method)
+                     method=method or args.method, mixed_switch=W.get("mixed_switch", 0.0))
         if pc == "learned":
             s.learned_factor(learned)
         return s
