@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import precond as PC  # noqa: E402
 from oracle import trplk as O  # noqa: E402
-from workloads import make, start_block  # noqa: E402
+from workloads import island_block, lap2d_island, make, start_block  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -73,6 +73,8 @@ CASES = [
     ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "fsai", {}),
     ("powerlaw", dict(n=3000, p=8, m=24, k=12), "jacobi", {}),
     ("aniso3d", dict(N=10, sigma=1.0, p=12, m=16, k=8, tol=1e-9), "jacobi", {}),  # hard locking
+    ("lap3d", dict(N=12, vmax=0.05, p=8, m=64, k=24), "jacobi", {}),   # largest basis m = 64
+    ("lap2d", dict(N=6, p=3, m=36, k=6), "jacobi", {}),                # m = n = 36: one cycle
 ]
 
 
@@ -171,3 +173,40 @@ def test_max_cycles_partial_results(T):
     assert st["status"] == 1 and st["cycles"] == 3
     ev, X, res, conv = s.eigpairs()
     assert not conv.all() and np.all(np.isfinite(ev))
+
+
+def test_hard_locking_at_the_column_limit(T):
+    """p = m = 64: the locked set plus the basis fill the 128 columns the
+    projection passes take; 64 locked pairs and a final 64 x 64
+    Rayleigh-Ritz on them."""
+    P = make("lap3d", "small", N=12, vmax=0.05, p=64, m=64, k=24)
+    print(f"solve lap3d N=12 p=64 m=64 k=24 n={P.A.n}", flush=True)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, "jacobi", X0)
+    st, ev, X, res, conv = _gpu(T, P, "jacobi", X0)
+    _compare(P, st, ev, X, res, conv, ref, cycle_slack=3)
+
+
+@pytest.mark.parametrize("s,k,m,prec", [(6, 4, 12, "jacobi"), (9, 3, 16, "none")])
+def test_breakdown_in_an_invariant_subspace(T, s, k, m, prec):
+    """A start block inside the s-dimensional invariant subspace of a
+    disconnected path: the device detects the breakdown after s - k Krylov
+    vectors, skips the rest of the cycle, and returns the exact pairs of the
+    path block after one cycle with s products, as the oracle does."""
+    A = lap2d_island(20, s)
+    n = A.n
+    print(f"breakdown island s={s} k={k} m={m} prec={prec} n={n}", flush=True)
+    X0 = island_block(n, s, k, 7)
+    As = A.to_scipy()
+    ref = O.solve(As, None, 2, m, k, 1, 1e-10, X0, apply_M=O.jacobi(As) if prec == "jacobi" else None)
+    assert ref.cycles == 1 and ref.matvecs == s
+    sv = T.Solver(A, None, p=2, m=m, k=k, l=1, tol=1e-10, precond=prec)
+    st = sv.solve(X0)
+    ev, X, res, conv = sv.eigpairs()
+    sv.close()
+    print(f"  gpu cycles={st['cycles']} mv={st['matvecs']} ev={ev} ref={ref.theta}", flush=True)
+    assert conv.all()
+    assert st["cycles"] == 1 and st["matvecs"] == s
+    assert np.all(np.abs(ev - ref.theta) <= 16 * 2.2e-16 * ref.normA)
+    assert np.all(X[:n - s] == 0.0)
+    assert np.max(np.abs(X.T @ X - np.eye(2))) < 1e-12

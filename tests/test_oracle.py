@@ -14,7 +14,8 @@ import scipy.linalg as sl
 import scipy.sparse as sp
 
 from oracle import trplk as O
-from workloads import make, start_block, lap2d, lap3d, fem3d, aniso3d, powerlaw
+from workloads import (make, start_block, lap2d, lap3d, fem3d, aniso3d, powerlaw,
+                       lap2d_island, island_block)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -281,6 +282,38 @@ def test_optimal_step_lemma():
     # and no other step along p does better
     for a2 in (0.5 * alpha, 2 * alpha, -alpha):
         assert rho(x + a2 * p) > th
+
+
+@pytest.mark.parametrize("s,k,m,prec", [(6, 4, 12, "jacobi"), (9, 3, 16, None)])
+def test_breakdown_in_an_invariant_subspace(s, k, m, prec):
+    """A start block inside an s-dimensional invariant subspace (a
+    disconnected path of s nodes): the Krylov block is exhausted after s - k
+    vectors, the next one is zero up to rounding, the inner loop stops
+    (breakdown, R7), and the Rayleigh-Ritz pairs on the s-dimensional basis
+    are exact eigenpairs of the path block after one cycle."""
+    A = lap2d_island(20, s).to_scipy()
+    n = A.shape[0]
+    ev = np.linalg.eigvalsh(A.toarray()[n - s:, n - s:])
+    seen = []
+    r = O.solve(A, None, 2, m, k, 1, 1e-10, island_block(n, s, k, 7),
+                apply_M=O.jacobi(A) if prec else None,
+                trace=lambda c, U, AU, BU, T, ka, Q, info: seen.append((U.shape[1], info["nk"])))
+    assert seen == [(s, s - k)]
+    assert r.cycles == 1 and r.matvecs == s
+    assert np.all(np.abs(r.theta - ev[:2]) <= 1e-14 * r.normA)
+    assert np.all(r.true_res <= 1e-14 * r.normA)
+    assert np.all(r.X[:n - s] == 0.0)
+
+
+def test_basis_filling_the_whole_space():
+    """m = n: the first cycle's basis spans R^n (no breakdown on a 6 x 6 grid),
+    so its Rayleigh-Ritz pairs are the exact eigenpairs (closed form)."""
+    A = lap2d(6).to_scipy()
+    seen = []
+    r = O.solve(A, None, 3, 36, 6, 1, 1e-10, start_block(36, 6, 12), apply_M=O.jacobi(A),
+                trace=lambda c, U, AU, BU, T, ka, Q, info: seen.append(U.shape[1]))
+    assert seen == [36] and r.cycles == 1 and r.matvecs == 36
+    assert np.all(np.abs(r.theta - lap2d_closed(6, 3)) <= 1e-13 * r.normA)
 
 
 def test_input_validation():

@@ -304,6 +304,23 @@ def start_block(n: int, k: int, seed: int = 12) -> np.ndarray:
     return np.asfortranarray(X)
 
 
+def lap2d_island(N: int, s: int, diag: float = 2.5) -> CSR:
+    """lap2d(N) with a disconnected path of s extra nodes appended: the
+    block-diagonal matrix diag(lap2d(N), tridiag(-1, diag, -1) of order s).
+    Coordinates N^2 .. N^2 + s - 1 span an invariant subspace of dimension s."""
+    import scipy.sparse as sp
+    P = sp.diags([-np.ones(s - 1), np.full(s, diag), -np.ones(s - 1)], [-1, 0, 1])
+    return CSR.from_scipy(sp.block_diag([lap2d(N).to_scipy(), P], format="csr"))
+
+
+def island_block(n: int, s: int, k: int, seed: int = 12) -> np.ndarray:
+    """n x k start block that is zero outside the last s coordinates, where it
+    is uniform[-1, 1].  Fortran (column-major) order."""
+    X = np.zeros((n, k), order="F")
+    X[n - s:, :] = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(k, s)).T
+    return X
+
+
 # ---------------------------------------------------------------------------
 # the five workloads (full size) and their small variants for tests
 # ---------------------------------------------------------------------------
