@@ -75,6 +75,20 @@ enum {
                                     Ritz vector uses (end of Sec. 4.2) */
 };
 enum { TRPLK_NORM_INF = 0, TRPLK_NORM_FRO = 1 };
+/* orthogonalisation of the inner (Krylov) vectors of TRPL+K.  Both make each
+ * new basis vector orthogonal to the basis to working accuracy with classical
+ * Gram-Schmidt applied twice; they differ in when the second pass runs. */
+enum {
+  TRPLK_ORTH_AUTO = 0,    /* DELAYED where it applies (standard problem, soft locking,
+                             TRPL+K), CGS2 otherwise */
+  TRPLK_ORTH_CGS2 = 1,    /* both passes before the vector is appended: three passes over
+                             the basis per inner step */
+  TRPLK_ORTH_DELAYED = 2  /* the second pass of vector j is merged with the first pass of
+                             vector j + 1 (one dot pass and one update pass per inner step);
+                             the T column and the stored products A U are corrected exactly
+                             from small matrices.  B = NULL and soft locking only (EINVAL
+                             otherwise) */
+};
 
 typedef struct trplk_csr {
   int32_t n;              /* rows = columns */
@@ -110,6 +124,7 @@ typedef struct trplk_opts {
   int32_t method;     /* TRPLK_METHOD_*.  PL+1 needs p = 1 and FP64; its projection space
                          [x_k, G_k, p_{k-1}] has at most m columns (Krylov block m - 2); the
                          start vector is the first column of x0; cycles = outer steps */
+  int32_t orth;       /* TRPLK_ORTH_* (TRPL+K only; PL+1 always uses CGS2) */
 } trplk_opts;
 
 typedef struct trplk_stats {
@@ -121,7 +136,7 @@ typedef struct trplk_stats {
   int32_t fp32_cycles; /* cycles that used the float32 SpMV (MIXED) */
   int32_t status;      /* TRPLK_OK or TRPLK_ENOCONV */
   int32_t fallback_cycle; /* cycle at which the preconditioner fell back to Jacobi, 0 = never */
-  int32_t pad_;
+  int32_t orth_delayed; /* 1 when the inner vectors used TRPLK_ORTH_DELAYED */
   double normA;        /* the ||A|| used in the stopping test */
   double solve_ms;     /* device time of trplk_solve (HIP events on the context stream) */
   double setup_ms;     /* device time of trplk_create's preconditioner setup */
@@ -132,14 +147,16 @@ typedef struct trplk_stats {
   double rot_ms;       int64_t rot_launches;      int64_t rot_bytes;
   double rr_ms;        int64_t rr_launches;
   /* the orthogonalisation split by pass: [0] dots (T column + first
-     coefficients), [1] fused update + dots, [2] update + norm */
+     coefficients; with DELAYED also the correction dots), [1] fused update +
+     dots (CGS2 only), [2] update + norm (with DELAYED: correction + update) */
   double pass_ms[3];   int64_t pass_launches[3];  int64_t pass_bytes[3];
 } trplk_stats;
 
 typedef struct trplk_ctx trplk_ctx;
 
 /* Fill *o with defaults: p=1 m=18 k=8 l=1 tol=1e-8 norm=INF max_cycles=5000
- * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0 method=TRPLK. */
+ * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0 method=TRPLK
+ * orth=AUTO. */
 void trplk_default_opts(trplk_opts* o);
 
 /* Create a solver context for the pencil (A, B) (paper eq. (1.1)).

@@ -19,6 +19,10 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # outer method: TRPL+K (Alg. 1), PL+1 with the conjugate search direction of
 # Alg. 2 step 7, PL+1 with the practical direction g_k + p_{k-1} w(m+2)
 METHOD = {"trplk": 0, "pl1": 1, "pl1_practical": 2}
+# inner-vector orthogonalisation: auto (delayed where it applies), classical
+# Gram-Schmidt twice per vector, or the delayed form (second pass merged with
+# the next vector's first pass)
+ORTH = {"auto": 0, "cgs2": 1, "delayed": 2}
 PREC = {"none": 0, "jacobi": 1, "fsai": 2, "factor": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 LOCKING = {"auto": 0, "soft": 1, "hard": 2}
@@ -45,7 +49,7 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("locking", ctypes.c_int32),
                 ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("orth", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -53,7 +57,7 @@ class _Stats(ctypes.Structure):
                 ("matvecs", ctypes.c_int64), ("bmatvecs", ctypes.c_int64),
                 ("precs", ctypes.c_int64), ("fp32_cycles", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("fallback_cycle", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("normA", ctypes.c_double),
+                ("orth_delayed", ctypes.c_int32), ("normA", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
                 ("spmv_bytes", ctypes.c_int64),
@@ -184,7 +188,8 @@ class Solver:
 
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
-                 profile=False, mixed_switch=0.0, fallback_window=0, method="trplk"):
+                 profile=False, mixed_switch=0.0, fallback_window=0, method="trplk",
+                 orth="auto"):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -194,6 +199,7 @@ class Solver:
         o.fsai_cap, o.profile, o.mixed_switch = fsai_cap, int(bool(profile)), mixed_switch
         o.fallback_window = fallback_window
         o.method = METHOD[method]
+        o.orth = ORTH[orth]
         self.opts = o
         self.n = int(A.n)
         self.p = p

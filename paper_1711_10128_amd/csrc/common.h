@@ -26,7 +26,7 @@ struct DevState {
   double tol2;     // breakdown tolerance squared of the current stage
   long long cnt_append;  // vectors appended to the basis (one A product each)
   long long cnt_norm;    // B-norm evaluations (one B product each when B != I)
-  double pad[1];
+  double inv_gamma;      // delayed correction: 1 / ||u' - U c|| of the column being corrected
 };
 
 // Launch-error helper: records the first failing call.
@@ -137,7 +137,9 @@ hipError_t spmv_f32(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s);
 enum OrthMode : int {
   ORTH_DOT = 0,      // h_v = M_v^T vec_v for NV vectors (v0 with Md0, v1 with Md1)
   ORTH_UPD_DOT = 1,  // w <- w - Mu h ; h2 = Md1^T w
-  ORTH_UPD = 2       // wout <- w - Mu h ; optional ||wout||^2 partial; optional f32 copy
+  ORTH_UPD = 2,      // wout <- w - Mu h ; optional ||wout||^2 partial; optional f32 copy
+  ORTH_UPD2 = 3      // delayed step: u <- (u' - U c) inv_gamma in place, then
+                     // wout <- w - U h - u h_last (+ ||wout||^2, f32 copy); see k_upd2
 };
 
 struct OrthArgs {
@@ -156,13 +158,16 @@ struct OrthArgs {
   // column just appended, located on the device)
   const double* vec0_base = nullptr;
   int vec0_col0 = 0;
+  const double* vec1_base = nullptr;  // the same for vec1
+  const double* vec2 = nullptr;       // ORTH_DOT with nvec = 3 (all against Md0)
   const double* h = nullptr;    // update coefficients (device)
   double* w = nullptr;          // vector updated in place (ORTH_UPD_DOT) / input (ORTH_UPD)
   double* wout = nullptr;       // ORTH_UPD output
   float* wout32 = nullptr;      // ORTH_UPD optional float32 copy
   bool norm = false;            // ORTH_UPD: partial of ||wout||^2
   double* partial = nullptr;    // [nblk][stride]
-  int nvec = 1;                 // ORTH_DOT: 1 or 2
+  int nvec = 1;                 // ORTH_DOT: 1, 2 or 3
+  const double* c = nullptr;    // ORTH_UPD2: correction coefficients of the pending column
 };
 
 constexpr int ORTH_MAXCOL = 128;
@@ -180,7 +185,9 @@ enum FinishMode : int {
   FIN_NORM = 4,  // beta^2: breakdown test, inv_beta, skip flag
   FIN_SUM = 5,   // plain sums into out[0..cnt)
   FIN_TCOL = 6,  // T column j = cnt from vec0 dots over columns 0..j, no state
-  FIN_RES = 7    // residual report: out[i] = sqrt(r2_i / x2_i), i < cnt (rotation partials)
+  FIN_RES = 7,   // residual report: out[i] = sqrt(r2_i / x2_i), i < cnt (rotation partials)
+  FIN_DC = 8     // delayed step: correction c, 1/gamma, corrected T column, h of the new
+                 // direction (when nvec = 3), column of L; nb += 1
 };
 
 struct FinishArgs {
@@ -199,6 +206,8 @@ struct FinishArgs {
   int nvec = 1;
   int skip_first = 0;   // FIN_TH / FIN_H / FIN_H2: zero the coefficient of the first active
                         // column (a basis orthogonalised among its own columns only)
+  double* cbuf = nullptr;  // FIN_DC: correction coefficients out (ORTH_MAXCOL)
+  double* L = nullptr;     // FIN_DC: AU_true = AU_stored L (upper triangular, ldT)
 };
 hipError_t finish(const FinishArgs& f, hipStream_t s);
 
@@ -210,6 +219,11 @@ enum SetWhich : int {
 hipError_t set_rho_from(DevState* st, const double* theta, int idx, hipStream_t s);
 // T <- 0 except T(i,i) = theta[off + i] for i < kact
 hipError_t reset_T(double* T, int ldT, int m, int kact, const double* theta, int off, hipStream_t s);
+// YA = L Y for b = state->nb columns of the upper triangular L (both ld)
+hipError_t ly_product(const double* L, const double* Y, double* YA, int ld, const DevState* st,
+                      hipStream_t s);
+// L <- I (m x m, leading dimension ld)
+hipError_t set_identity(double* L, int ld, int m, hipStream_t s);
 
 // r = AX(:,t) - theta_t BX(:,t) followed by the Jacobi / identity scale, or
 // stored for the factor preconditioner (v, float32 or float64).
@@ -314,6 +328,7 @@ struct RotArgs {
   int b_max = 0;               // upper bound of the basis columns (sizes the K loop)
   const DevState* state = nullptr;
   const double* Y = nullptr;   // ldY
+  const double* YA = nullptr;  // optional coefficients for AU (ldY); Y when null
   int ldY = 0;
   double* U = nullptr;         // rotated in place
   double* AU = nullptr;        // optional

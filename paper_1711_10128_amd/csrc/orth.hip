@@ -28,7 +28,7 @@ namespace trplk {
 
 namespace {
 
-constexpr int STRIDE = 2 * ORTH_MAXCOL; // partial doubles per block
+constexpr int STRIDE = 3 * ORTH_MAXCOL; // partial doubles per block (up to three vectors)
 constexpr int ORTH_RP = 1;              // row pairs per lane per slab: dot passes
 constexpr int UPD_RP = 4;               // update-only pass
 int64_t g_orth_nt_bytes = int64_t(128) << 20;  // non-temporal from this basis size
@@ -116,6 +116,8 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
 
   const double* vec0 = a.vec0;
   if (a.vec0_base) vec0 = a.vec0_base + static_cast<int64_t>(a.vec0_col0 + a.state->nb) * ld;
+  const double* vec1 = a.vec1;
+  if (a.vec1_base) vec1 = a.vec1_base + static_cast<int64_t>(a.vec0_col0 + a.state->nb) * ld;
 
   auto slab = [&](int sl, auto full) {
     constexpr bool F = decltype(full)::value;
@@ -125,7 +127,8 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
 #pragma unroll
       for (int r = 0; r < RP; ++r) {
         vv[0][r] = ld_pair<F, false>(vec0, base + WAVE * r, n);
-        if constexpr (NV == 2) vv[1][r] = ld_pair<F, false>(a.vec1, base + WAVE * r, n);
+        if constexpr (NV >= 2) vv[1][r] = ld_pair<F, false>(vec1, base + WAVE * r, n);
+        if constexpr (NV == 3) vv[2][r] = ld_pair<F, false>(a.vec2, base + WAVE * r, n);
       }
       // every load of the slab is issued before the first product
       constexpr int NU = (NV == 2 && !SAME) ? 2 : 1;
@@ -147,9 +150,13 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
         for (int r = 0; r < RP; ++r) {
           acc[i][0] += u[0][i][r].x * vv[0][r].x;
           acc[i][0] += u[0][i][r].y * vv[0][r].y;
-          if constexpr (NV == 2) {
+          if constexpr (NV >= 2) {
             acc[i][1] += u[NU - 1][i][r].x * vv[1][r].x;
             acc[i][1] += u[NU - 1][i][r].y * vv[1][r].y;
+          }
+          if constexpr (NV == 3) {
+            acc[i][2] += u[0][i][r].x * vv[2][r].x;
+            acc[i][2] += u[0][i][r].y * vv[2][r].y;
           }
         }
       }
@@ -305,6 +312,111 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
   }
 }
 
+// Delayed step (one basis pass for two vectors).  The column j = nb - 1
+// holds u', a vector orthogonalised once and scaled to unit norm; c =
+// U(:, 0:j)^T u' and inv_gamma come from the previous dot pass.  Per row:
+//   u    = (u' - U(:, 0:j) c) inv_gamma      (written back to column j)
+//   wout = w - U(:, 0:j) h(0:j) - u h(j)     (when w is given, + ||wout||^2)
+// Columns 0..j-1 are read once for both sums; every lane reads the rows of
+// column j it writes, so the in-place update is safe.
+template <bool NT>
+__global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
+  if (a.state->skip) return;
+  const int j = a.ncol_fixed + a.state->nb - 1;
+  __shared__ double hs[ORTH_MAXCOL];
+  __shared__ double cs[ORTH_MAXCOL];
+  __shared__ double red[UPD_THREADS / WAVE];
+  const bool withw = a.w != nullptr;
+  for (int c = threadIdx.x; c < j; c += UPD_THREADS) {
+    cs[c] = a.c[c];
+    hs[c] = withw ? a.h[c] : 0.0;
+  }
+  __syncthreads();
+  const double ig = a.state->inv_gamma;
+  const double hl = withw ? a.h[j] : 0.0;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int64_t ld = a.ld;
+  const int n = a.n;
+  double* ucol = const_cast<double*>(a.Mu) + static_cast<int64_t>(j) * ld;
+  constexpr int TILEP = WAVE * UPD_RP;
+  const int npair = (n + 1) / 2;
+  const int ntile = (npair + TILEP - 1) / TILEP;
+  const int nfull = n / (2 * TILEP);
+  double nacc = 0.0;
+  auto tile_body = [&](int tile, auto full) {
+    constexpr bool F = decltype(full)::value;
+    const int base = tile * TILEP + lane;
+    d2 pu[UPD_RP], pw[UPD_RP];
+#pragma unroll
+    for (int r = 0; r < UPD_RP; ++r) {
+      pu[r] = d2{0.0, 0.0};
+      pw[r] = d2{0.0, 0.0};
+    }
+    int c = 0;
+    for (; c + 4 <= j; c += 4) {
+      d2 u[4][UPD_RP];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < UPD_RP; ++r)
+          u[q][r] = ld_pair<F, NT>(a.Mu + (c + q) * ld, base + WAVE * r, n);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < UPD_RP; ++r) {
+          pu[r].x += u[q][r].x * cs[c + q];
+          pu[r].y += u[q][r].y * cs[c + q];
+          pw[r].x += u[q][r].x * hs[c + q];
+          pw[r].y += u[q][r].y * hs[c + q];
+        }
+    }
+    for (; c < j; ++c) {
+#pragma unroll
+      for (int r = 0; r < UPD_RP; ++r) {
+        const d2 u = ld_pair<F, NT>(a.Mu + c * ld, base + WAVE * r, n);
+        pu[r].x += u.x * cs[c];
+        pu[r].y += u.y * cs[c];
+        pw[r].x += u.x * hs[c];
+        pw[r].y += u.y * hs[c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < UPD_RP; ++r) {
+      const int p = base + WAVE * r;
+      const d2 up = ld_pair<F, false>(ucol, p, n);
+      d2 un;
+      un.x = (up.x - pu[r].x) * ig;
+      un.y = (up.y - pu[r].y) * ig;
+      st_pair<F>(ucol, p, n, un);
+      if (withw) {
+        const d2 w = ld_pair<F, false>(a.w, p, n);
+        d2 wn;
+        wn.x = w.x - pw[r].x - un.x * hl;
+        wn.y = w.y - pw[r].y - un.y * hl;
+        st_pair<F>(a.wout, p, n, wn);
+        if (a.wout32) st_pair32<F>(a.wout32, p, n, wn);
+        nacc += pair_sq<F>(p, n, wn);
+      }
+    }
+  };
+  for (int tile = blockIdx.x * (UPD_THREADS / WAVE) + wv; tile < ntile;
+       tile += gridDim.x * (UPD_THREADS / WAVE)) {
+    if (tile < nfull) tile_body(tile, Full{});
+    else tile_body(tile, Part{});
+  }
+  if (a.norm) {
+    nacc = wave_sum(nacc);
+    if (lane == 0) red[wv] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < UPD_THREADS / WAVE; ++q) t += red[q];
+      a.partial[static_cast<int64_t>(blockIdx.x) * STRIDE] = t;
+    }
+  }
+}
+
 template <int CPW, int RP, bool NT, int NWV>
 hipError_t launch_rp(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   const dim3 g(nblk), b(NWV * WAVE);
@@ -312,6 +424,9 @@ hipError_t launch_rp(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   if (mode == ORTH_DOT) {
     if (a.nvec == 1) {
       hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RP, NT, NWV>), g, b, 0, s, a);
+    } else if (a.nvec == 3) {
+      // all three vectors against Md0
+      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 3, true, RP, NT, NWV>), g, b, 0, s, a);
     } else if (same) {
       hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RP, NT, NWV>), g, b, 0, s, a);
     } else {
@@ -536,6 +651,89 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       }
       break;
     }
+    case FIN_DC: {
+      // Delayed step for the pending column j = nb (u' at U(:, j), z' = A u'
+      // at AU(:, j)); the dot pass gave a = U(:, 0:j+1)^T u', t = U^T z' and,
+      // with nvec = 3, b = U^T w.  With c = a(0:j) and
+      // gamma^2 = a_j - |c|^2 the corrected column is u = (u' - U c) / gamma;
+      // A u = (z' - A U c) / gamma gives, with T = U^T A U and A symmetric,
+      //   T(i, j) = (t_i - (T c)_i) / gamma                 (i < j)
+      //   T(j, j) = (t_j - 2 c.t + c.(T c)) / gamma^2
+      // and the new direction's coefficients h(0:j) = b(0:j),
+      // h(j) = (b_j - c.b) / gamma.  A U(:, j) is kept as the stored z': the
+      // true products are AU_stored L with L(:, j) = (e_j - L c) / gamma.
+      const int j = nb;
+      const bool withw = f.nvec == 3;
+      double* a_ = v0;
+      double* t_ = v0 + ORTH_MAXCOL;
+      fin_sum(f, 0, j + 1, a_, red);
+      fin_sum(f, ORTH_MAXCOL, j + 1, t_, red);
+      if (withw) fin_sum(f, 2 * ORTH_MAXCOL, j + 1, v1, red);
+      __shared__ double ys[ORTH_MAXCOL];
+      __shared__ double ls[ORTH_MAXCOL];
+      __shared__ double sc[4];
+      for (int i = tid; i < j; i += blockDim.x) {
+        double y = 0.0, l = 0.0;
+        for (int k = 0; k < j; ++k) y += f.T[i + static_cast<int64_t>(k) * f.ldT] * a_[k];
+        for (int k = i; k < j; ++k) l += f.L[i + static_cast<int64_t>(k) * f.ldT] * a_[k];
+        ys[i] = y;
+        ls[i] = l;
+      }
+      __syncthreads();
+      if (tid < WAVE) {
+        double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
+        for (int k = tid; k < j; k += WAVE) {
+          cc += a_[k] * a_[k];
+          ct += a_[k] * t_[k];
+          cy += a_[k] * ys[k];
+          if (withw) cb += a_[k] * v1[k];
+        }
+        cc = wave_sum(cc);
+        ct = wave_sum(ct);
+        cy = wave_sum(cy);
+        cb = wave_sum(cb);
+        if (tid == 0) {
+          const double g2 = a_[j] - cc;
+          const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
+          const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
+          if (!ok) {
+            st->bad = 1;
+            st->skip = 1;
+          }
+          st->inv_gamma = ig;
+          sc[0] = ig;
+          sc[1] = (t_[j] - 2.0 * ct + cy) * ig * ig;
+          sc[2] = withw ? (v1[j] - cb) * ig : 0.0;
+        }
+      }
+      __syncthreads();
+      const double ig = sc[0];
+      for (int i = tid; i < j; i += blockDim.x) {
+        const double tij = (t_[i] - ys[i]) * ig;
+        f.T[i + static_cast<int64_t>(j) * f.ldT] = tij;
+        f.T[j + static_cast<int64_t>(i) * f.ldT] = tij;
+        f.L[i + static_cast<int64_t>(j) * f.ldT] = -ls[i] * ig;
+        f.cbuf[i] = a_[i];
+        if (withw) f.h[i] = v1[i];
+      }
+      if (tid == 0) {
+        f.T[j + static_cast<int64_t>(j) * f.ldT] = sc[1];
+        f.L[j + static_cast<int64_t>(j) * f.ldT] = ig;
+        if (withw) f.h[j] = sc[2];
+      }
+      if (withw && tid < WAVE) {
+        double hh = 0.0;
+        for (int k = tid; k < j; k += WAVE) hh += v1[k] * v1[k];
+        hh = wave_sum(hh);
+        if (tid == 0) st->h1norm2 = hh + sc[2] * sc[2];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        st->nb = nb + 1;
+        st->cnt_append += 1;
+      }
+      break;
+    }
     case FIN_NORM: {
       const double b2s = fin_one(f, 0, red);
       if (tid == 0) {
@@ -583,6 +781,26 @@ __global__ void k_reset_T(double* T, int ldT, int m, int kact, const double* the
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m * m; t += gridDim.x * blockDim.x) {
     const int i = t % m, j = t / m;
     T[i + static_cast<int64_t>(j) * ldT] = (i == j && i < kact) ? theta[off + i] : 0.0;
+  }
+}
+
+// YA = L Y over the b = st->nb basis columns (L upper triangular); every
+// column of Y is transformed (the rotation reads the first kout).
+__global__ __launch_bounds__(256) void k_ly(const double* L, const double* Y, double* YA, int ld,
+                                            const DevState* st) {
+  const int b = st->nb;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int i = e % b, c = e / b;
+    double v = 0.0;
+    for (int k = i; k < b; ++k) v += L[i + static_cast<int64_t>(k) * ld] * Y[k + static_cast<int64_t>(c) * ld];
+    YA[i + static_cast<int64_t>(c) * ld] = v;
+  }
+}
+
+__global__ void k_eye(double* L, int ld, int m) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m * m; t += gridDim.x * blockDim.x) {
+    const int i = t % m, j = t / m;
+    L[i + static_cast<int64_t>(j) * ld] = i == j ? 1.0 : 0.0;
   }
 }
 
@@ -673,7 +891,7 @@ int g_orth_maxblk = 0;  // 0: by pass
 
 int orth_blocks(int n, int mode) {
   const int npair = (std::max(n, 1) + 1) / 2;
-  if (mode == ORTH_UPD) {
+  if (mode == ORTH_UPD || mode == ORTH_UPD2) {
     const int tiles = (npair + WAVE * UPD_RP - 1) / (WAVE * UPD_RP);
     const int want = (tiles + UPD_THREADS / WAVE - 1) / (UPD_THREADS / WAVE);
     return std::max(1, std::min(want, g_orth_maxblk > 0 ? g_orth_maxblk : 1024));
@@ -698,6 +916,12 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
     else hipLaunchKernelGGL(k_upd<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
     return hipGetLastError();
   }
+  if (mode == ORTH_UPD2) {
+    if (!a.state || !a.c || !a.Mu || (a.w && (!a.h || !a.wout))) return hipErrorInvalidValue;
+    if (nt) hipLaunchKernelGGL(k_upd2<true>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    else hipLaunchKernelGGL(k_upd2<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
   return nt ? launch_width<true>(mode, a, need, nblk, s) : launch_width<false>(mode, a, need, nblk, s);
 }
 
@@ -718,6 +942,17 @@ hipError_t set_rho_from(DevState* st, const double* theta, int idx, hipStream_t 
 
 hipError_t reset_T(double* T, int ldT, int m, int kact, const double* theta, int off, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_T, dim3(16), dim3(256), 0, s, T, ldT, m, kact, theta, off);
+  return hipGetLastError();
+}
+
+hipError_t ly_product(const double* L, const double* Y, double* YA, int ld, const DevState* st,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_ly, dim3(1), dim3(256), 0, s, L, Y, YA, ld, st);
+  return hipGetLastError();
+}
+
+hipError_t set_identity(double* L, int ld, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_eye, dim3(16), dim3(256), 0, s, L, ld, m);
   return hipGetLastError();
 }
 

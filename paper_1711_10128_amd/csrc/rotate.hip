@@ -26,7 +26,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int RT = 256;  // threads per block (4 wavefronts)
 
-template <int NTILE, int KS>
+template <int NTILE, int KS, bool TWOY>
 __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   const int b = a.state ? a.state->nb : a.b_fixed;
   const int kk = min(a.kout, b);
@@ -48,6 +48,16 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   constexpr bool YLDS = KS >= 16;
   __shared__ double Ys[YLDS ? 4 * KS : 1][YLDS ? 16 * NTILE + 1 : 1];
   double yf[NTILE][YLDS ? 1 : KS];
+  // TWOY: A U takes its own coefficients YA (delayed re-orthogonalisation
+  // keeps uncorrected products; the true ones are AU L), always from LDS
+  __shared__ double Ya[TWOY ? 4 * KS : 1][TWOY ? 16 * NTILE + 1 : 1];
+  if constexpr (TWOY) {
+    for (int e = threadIdx.x; e < 4 * KS * 16 * NTILE; e += RT) {
+      const int kin = e % (4 * KS), kout = e / (4 * KS);
+      Ya[kin][kout] = (kin < b && kout < kk) ? a.YA[kin + static_cast<int64_t>(kout) * a.ldY] : 0.0;
+    }
+    if constexpr (!YLDS) __syncthreads();
+  }
   if constexpr (YLDS) {
     for (int e = threadIdx.x; e < 4 * KS * 16 * NTILE; e += RT) {
       const int kin = e % (4 * KS), kout = e / (4 * KS);
@@ -104,7 +114,9 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
 #pragma unroll
           for (int t = 0; t < NTILE; ++t)
             D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                YLDS ? Ys[4 * ks + lg][16 * t + li] : yf[t][YLDS ? 0 : ks], bv[ks], D[t], 0, 0, 0);
+                (TWOY && mi == 0) ? Ya[TWOY ? 4 * ks + lg : 0][TWOY ? 16 * t + li : 0]
+                : YLDS ? Ys[4 * ks + lg][16 * t + li] : yf[t][YLDS ? 0 : ks],
+                bv[ks], D[t], 0, 0, 0);
         }
       }
       // lane holds X(row = rb*16 + li, col = 16 t + lg + 4 r): the F64 16x16x4
@@ -175,16 +187,22 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   }
 }
 
-template <int NTILE>
-hipError_t launch_nt(const RotArgs& a, int nblk, hipStream_t s) {
+template <int NTILE, bool TWOY>
+hipError_t launch_nt2(const RotArgs& a, int nblk, hipStream_t s) {
   const int bmax = a.b_max > 0 ? a.b_max : (a.state ? SYEV_MAXB : a.b_fixed);
   const int ks = (bmax + 3) / 4;
   const dim3 g(nblk), b(RT);
-  if (ks <= 4) hipLaunchKernelGGL((k_rotate<NTILE, 4>), g, b, 0, s, a);
-  else if (ks <= 8) hipLaunchKernelGGL((k_rotate<NTILE, 8>), g, b, 0, s, a);
-  else if (ks <= 12) hipLaunchKernelGGL((k_rotate<NTILE, 12>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_rotate<NTILE, 16>), g, b, 0, s, a);
+  if (ks <= 4) hipLaunchKernelGGL((k_rotate<NTILE, 4, TWOY>), g, b, 0, s, a);
+  else if (ks <= 8) hipLaunchKernelGGL((k_rotate<NTILE, 8, TWOY>), g, b, 0, s, a);
+  else if (ks <= 12) hipLaunchKernelGGL((k_rotate<NTILE, 12, TWOY>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_rotate<NTILE, 16, TWOY>), g, b, 0, s, a);
   return hipGetLastError();
+}
+
+template <int NTILE>
+hipError_t launch_nt(const RotArgs& a, int nblk, hipStream_t s) {
+  if (a.YA && a.AU) return launch_nt2<NTILE, true>(a, nblk, s);
+  return launch_nt2<NTILE, false>(a, nblk, s);
 }
 
 }  // namespace

@@ -101,6 +101,9 @@ struct trplk_ctx {
   double* theta = nullptr;
   double* Y = nullptr;
   double* hbuf = nullptr;
+  double* cbuf = nullptr;   // delayed form: correction coefficients of the pending column
+  double* Lm = nullptr;     // delayed form: AU_true = AU_stored Lm (SYEV_MAXB^2)
+  double* YA = nullptr;     // delayed form: Lm Y, the rotation coefficients of AU
   double* partial = nullptr;
   double* resout = nullptr;
   DevState* st = nullptr;
@@ -321,6 +324,9 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &c->theta, SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->Y, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->hbuf, ORTH_MAXCOL));
+  HIPCHK(c, dalloc(c, &c->cbuf, ORTH_MAXCOL));
+  HIPCHK(c, dalloc(c, &c->Lm, SYEV_MAXB * SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->YA, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
   c->orth_nblk = orth_blocks_max(n);
   c->rot_nblk = rot_blocks(n);
@@ -366,6 +372,7 @@ struct Solver {
   int nbh = 0;  // host-side expected basis size
   bool keepT = false;  // the next cycle keeps T(0:kact,0:kact) (recomputed X^T A X)
   int skip0 = 0;  // PL+1: inner vectors are not orthogonalised against the first column
+  bool dc = false;  // delayed re-orthogonalisation of the inner vectors
 
   double* Ucol(int j) const { return c->W + (c->u0 + j) * ld; }
   double* AUcol(int j) const { return c->AW + (c->u0 + j) * ld; }
@@ -384,6 +391,7 @@ struct Solver {
     const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
     if (mode == ORTH_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 8LL * n * a.nvec;
     else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
+    else if (mode == ORTH_UPD2) bytes = 8 * (cols - 1) * n + (a.w ? 32LL : 16LL) * n;
     else bytes = 8 * cols * n + 16LL * n;
     ProfScope ps(c, mode == ORTH_DOT ? PC_DOT : mode == ORTH_UPD_DOT ? PC_UPDDOT : PC_UPD, bytes);
     return orth_pass(mode, a, orth_blocks(n, mode), s);
@@ -519,6 +527,79 @@ struct Solver {
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
+  // Delayed form, first inner vector: one Gram-Schmidt pass of w against
+  // [Q | U] into wtmp with its norm; the second pass is merged into the
+  // next dc_step.
+  int project_once() {
+    Status S;
+    const int ncf = c->u0;
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
+      a.Md0 = Wq(); a.vec0 = c->w; a.nvec = 1; a.partial = c->partial;
+      S.check(orth(ORTH_DOT, a), "orth h");
+      FinishArgs f;
+      f.mode = FIN_H; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
+      f.state = c->st; f.ncol_fixed = ncf; f.h = c->hbuf;
+      S.check(fin(f), "fin h");
+    }
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
+      a.Mu = Wq(); a.h = c->hbuf; a.w = c->w; a.wout = c->wtmp;
+      a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
+      a.norm = true; a.partial = c->partial;
+      S.check(orth(ORTH_UPD, a), "orth upd");
+    }
+    FinishArgs f;
+    f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
+    f.nblk = nblk(ORTH_UPD); f.stride = orth_stride();
+    S.check(fin(f), "fin norm");
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
+  // Delayed form, after the append of u' (column nb, once orthogonalised)
+  // with z' = A u' and, when `more`, the next direction w = M(z' - rho u'):
+  // one dot pass gives U^T [u', z', w]; the finish kernel turns them into
+  // the correction c, the exact T column of the corrected vector and the
+  // coefficients of w; one update pass writes u = (u' - U c) / gamma in
+  // place and the once-orthogonalised w into wtmp with its norm.
+  int dc_step(bool more) {
+    Status S;
+    const int ncf = c->u0;
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.ncol_extra = 1; a.state = c->st;
+      a.ncol_max = maxcols();
+      a.Md0 = Wq(); a.Md1 = Wq(); a.vec0_base = c->W; a.vec1_base = c->AW; a.vec0_col0 = ncf;
+      a.nvec = more ? 3 : 2; a.vec2 = more ? c->w : nullptr; a.partial = c->partial;
+      S.check(orth(ORTH_DOT, a), "orth dc dot");
+      FinishArgs f;
+      f.mode = FIN_DC; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
+      f.state = c->st; f.ncol_fixed = ncf; f.T = c->T; f.ldT = SYEV_MAXB; f.h = c->hbuf;
+      f.nvec = more ? 3 : 2; f.cbuf = c->cbuf; f.L = c->Lm;
+      S.check(fin(f), "fin dc");
+    }
+    {
+      OrthArgs a;
+      a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.ncol_extra = 1; a.state = c->st;
+      a.ncol_max = maxcols();
+      a.Mu = Wq(); a.c = c->cbuf; a.h = c->hbuf; a.partial = c->partial;
+      if (more) {
+        a.w = c->w; a.wout = c->wtmp; a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
+        a.norm = true;
+      }
+      S.check(orth(ORTH_UPD2, a), "orth dc upd");
+    }
+    if (more) {
+      FinishArgs f;
+      f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
+      f.nblk = nblk(ORTH_UPD2); f.stride = orth_stride();
+      S.check(fin(f), "fin dc norm");
+    }
+    return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+  }
+
   int stage_reset(double tol) {
     HIPCHK(c, set_state(c->st, SET_RESET_STAGE, tol * tol, 0, s));
     return TRPLK_OK;
@@ -544,14 +625,17 @@ struct Solver {
 
   // Rayleigh-Ritz on T(0:nb,0:nb), rotation of U, AU, BU to kout columns
   // and residuals of the first `nres` Ritz pairs; fills the host report.
-  int rayleigh_ritz(int kout, int nres) {
+  int rayleigh_ritz(int kout, int nres, bool useL = false) {
     Status S;
     {
       ProfScope ps(c, PC_RR, 0);
       S.check(syev(c->T, SYEV_MAXB, 0, &c->st->nb, 0, c->theta, c->Y, SYEV_MAXB, s), "syev");
+      // delayed form: the stored A U columns are z' = A u'; AU_true Y = AU (L Y)
+      if (useL) S.check(ly_product(c->Lm, c->Y, c->YA, SYEV_MAXB, c->st, s), "L Y");
     }
     RotArgs r;
     r.n = n; r.kout = kout; r.state = c->st; r.Y = c->Y; r.ldY = SYEV_MAXB; r.b_max = c->m;
+    r.YA = useL ? c->YA : nullptr;
     r.U = Ucol(0); r.AU = AUcol(0); r.BU = c->hasB ? BUcol(0) : nullptr; r.ld = ld;
     r.theta = c->theta; r.partial = c->partial;
     {
@@ -731,6 +815,8 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   c->u0 = 0;
   c->solved = false;
   c->fp32_phase = (o.precision == TRPLK_MIXED);
+  dc = o.orth != TRPLK_ORTH_CGS2 && !c->hasB && !hard;
+  stt.orth_delayed = dc ? 1 : 0;
   int r;
   HIPCHK(c, hipEventRecord(c->ev0, s));
   HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
@@ -779,11 +865,20 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
     // ---- inner preconditioned Krylov loop, eq. (3.1) ----
     const int m_in = m - kact - nprev;
     if ((r = stage_reset(BREAKDOWN_TOL))) return r;
+    if (dc) HIPCHK(c, set_identity(c->Lm, SYEV_MAXB, SYEV_MAXB, s));
     for (int j = 0; j < m_in; ++j) {
-      if ((r = project(j == 0))) return r;
       const bool more = j < m_in - 1;
-      if ((r = append(more ? 1 : 0))) return r;
-      if ((r = tcol(more))) return r;
+      if (dc) {
+        // one Gram-Schmidt pass per vector before its product with A; the
+        // second pass is the correction at the next step (or the last one)
+        if (j == 0 && (r = project_once())) return r;
+        if ((r = append(more ? 1 : 0))) return r;
+        if ((r = dc_step(more))) return r;
+      } else {
+        if ((r = project(j == 0))) return r;
+        if ((r = append(more ? 1 : 0))) return r;
+        if ((r = tcol(more))) return r;
+      }
       ++nbh;
       if (more) stt.precs += 1;
     }
@@ -799,7 +894,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
     HIPCHK(c, copy_cols(n, Ucol(t), ld, c->Xprev, ld, lcnt, s));
     // ---- Rayleigh-Ritz and thick restart ----
     const int kout = std::min(k, SYEV_MAXB);
-    if ((r = rayleigh_ritz(kout, kout))) return r;
+    if ((r = rayleigh_ritz(kout, kout, dc))) return r;
     const Report& R = *c->rep_h;
     stt.matvecs += R.cnt_append - prev_app;
     prev_app = R.cnt_append;
@@ -1525,6 +1620,7 @@ void trplk_default_opts(trplk_opts* o) {
   o->profile = 0;
   o->mixed_switch = 0.0;
   o->method = TRPLK_METHOD_TRPLK;
+  o->orth = TRPLK_ORTH_AUTO;
 }
 
 static int check_opts(const trplk_opts* o, int n, std::string& why) {
@@ -1558,6 +1654,8 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
   if (o->max_cycles < 1) { why = "max_cycles must be >= 1"; return TRPLK_EINVAL; }
   if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
   if (o->precision != TRPLK_FP64 && o->precision != TRPLK_MIXED) { why = "bad precision"; return TRPLK_EINVAL; }
+  if (o->orth < TRPLK_ORTH_AUTO || o->orth > TRPLK_ORTH_DELAYED) { why = "bad orth"; return TRPLK_EINVAL; }
+  if (o->orth == TRPLK_ORTH_DELAYED && hard) { why = "delayed orthogonalisation needs soft locking"; return TRPLK_EINVAL; }
   if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
   return TRPLK_OK;
 }
@@ -1573,6 +1671,8 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
   std::string why;
   int r = check_opts(o, n, why);
   if (r) return set_err(nullptr, r, why);
+  if (B && o->method == TRPLK_METHOD_TRPLK && o->orth == TRPLK_ORTH_DELAYED)
+    return set_err(nullptr, TRPLK_EINVAL, "delayed orthogonalisation needs B = I");
   if (mem == TRPLK_MEM_HOST) {
     if ((r = validate_host_csr(A, n, why))) return set_err(nullptr, r, "A: " + why);
     if (B && (r = validate_host_csr(B, n, why))) return set_err(nullptr, r, "B: " + why);

@@ -52,3 +52,32 @@ def test_orth_entries_reject_misaligned_layouts_without_gpu():
     assert L.trplk_gemv_t(10, 2, good, 10, odd, good, None) == -1
     assert L.trplk_cgs_update_dot(10, 2, good, 11, good, good, good, None) == -1
     assert L.trplk_cgs_update_dot(10, 2, good, 10, good, odd, good, None) == -1
+
+
+def test_orth_option_validation_without_gpu():
+    # option checks run before anything touches the device
+    import numpy as np
+    import paper_1711_10128_amd as T
+    L = T.lib()
+    n = 40
+    rp = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    val = np.full(n, 2.0)
+    A = T._Csr(n, n, rp.ctypes.data_as(ctypes.c_void_p), col.ctypes.data_as(ctypes.c_void_p),
+               val.ctypes.data_as(ctypes.c_void_p))
+    o = T._Opts()
+    L.trplk_default_opts(ctypes.byref(o))
+    assert o.orth == T.ORTH["auto"]
+    ctx = ctypes.c_void_p()
+    o.orth = 3
+    assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), None, ctypes.byref(o), 0, None) == -1
+    assert b"orth" in L.trplk_last_error(None)
+    o.orth = T.ORTH["delayed"]
+    o.p, o.k, o.m = 6, 4, 16                       # p > k: hard locking
+    assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), None, ctypes.byref(o), 0, None) == -1
+    assert b"soft locking" in L.trplk_last_error(None)
+    o.p = 2
+    assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), 0,
+                          None) == -1
+    assert b"B = I" in L.trplk_last_error(None)
+    assert not ctx.value

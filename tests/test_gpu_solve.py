@@ -210,3 +210,51 @@ def test_breakdown_in_an_invariant_subspace(T, s, k, m, prec):
     assert np.all(np.abs(ev - ref.theta) <= 16 * 2.2e-16 * ref.normA)
     assert np.all(X[:n - s] == 0.0)
     assert np.max(np.abs(X.T @ X - np.eye(2))) < 1e-12
+
+
+@pytest.mark.parametrize("name,kw,prec", [
+    ("lap3d", dict(N=16, vmax=0.05, p=10, m=40, k=20), "jacobi"),
+    ("powerlaw", dict(n=3000, p=8, m=24, k=12), "jacobi"),
+    ("lap3d", dict(N=14, vmax=0.05, p=6, m=24, k=12), "fsai"),
+])
+def test_delayed_and_cgs2_orthogonalisation_agree(T, name, kw, prec):
+    """The inner vectors orthogonalised with both Gram-Schmidt passes before
+    the product (three basis passes per step) and with the second pass
+    delayed to the next step (two passes, T column and A U corrected from
+    small matrices) give the oracle's pairs with the same cycle and product
+    counts."""
+    P = make(name, "small", **kw)
+    print(f"orth {name} {kw} prec={prec} n={P.A.n}", flush=True)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, prec, X0)
+    out = {}
+    for orth in ("cgs2", "delayed"):
+        st, ev, X, res, conv = _gpu(T, P, prec, X0, orth=orth)
+        assert st["orth_delayed"] == (orth == "delayed")
+        _compare(P, st, ev, X, res, conv, ref)
+        out[orth] = (st, ev)
+    assert abs(out["cgs2"][0]["cycles"] - out["delayed"][0]["cycles"]) <= 1
+    assert np.all(np.abs(out["cgs2"][1] - out["delayed"][1]) <= 1e-10 * np.abs(ref.theta))
+
+
+def test_orth_option_rules(T):
+    """AUTO picks the delayed form only for B = I with soft locking;
+    an explicit DELAYED request elsewhere is rejected."""
+    P = make("fem3d", "small", Ne=6, sigma=0.5, p=4, m=16, k=8)
+    with pytest.raises(T.TrplkError) as e:
+        T.Solver(P.A, P.B, p=4, m=16, k=8, orth="delayed")
+    assert e.value.code == -1
+    Q = make("lap2d", "small", N=12)
+    with pytest.raises(T.TrplkError):
+        T.Solver(Q.A, None, p=6, m=16, k=4, orth="delayed")     # hard locking
+    X0 = start_block(P.A.n, 8, 12)
+    s = T.Solver(P.A, P.B, p=4, m=16, k=8)
+    assert s.solve(X0)["orth_delayed"] == 0                      # generalized: CGS2
+    s.close()
+    X0 = start_block(Q.A.n, 4, 12)
+    s = T.Solver(Q.A, None, p=6, m=16, k=4)
+    assert s.solve(X0)["orth_delayed"] == 0                      # hard locking: CGS2
+    s.close()
+    s = T.Solver(Q.A, None, p=2, m=16, k=4)
+    assert s.solve(X0)["orth_delayed"] == 1
+    s.close()
