@@ -49,6 +49,9 @@ WORKLOADS = {
 KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients)",
                 "orth_upd_dot": "k_orth<ORTH_UPD_DOT> (w -= U h1; h2 = U^T w)",
                 "orth_upd": "k_upd (w -= U h2; ||w||^2)",
+                "orth_dc_dot": "k_orth<ORTH_DOT, 3 vectors> (U^T [u', A u', w]: delayed correction, "
+                               "T column, coefficients of w)",
+                "orth_dc_upd": "k_upd2 (u = (u' - U c) / gamma; w -= U h; ||w||^2)",
                 "spmv": "k_spmv_stream / k_spmv_rows (SpMV + append epilogue)",
                 "prec": "k_spmv_stream / k_spmv_rows (factor apply G, G^T)",
                 "rot": "k_rotate (MFMA restart rotation)"}
@@ -281,7 +284,7 @@ def main():
             classes[cls] = {"ms": ms, "launches": sp[f"{cls}_launches"], "bytes": nbytes,
                             "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 and nbytes else None}
     # the orthogonalisation by pass (one kernel each)
-    for q, name in enumerate(("orth_dot", "orth_upd_dot", "orth_upd")):
+    for q, name in enumerate(("orth_dot", "orth_upd_dot", "orth_upd", "orth_dc_dot", "orth_dc_upd")):
         if sp["pass_launches"][q]:
             ms, nbytes = sp["pass_ms"][q], sp["pass_bytes"][q]
             classes[name] = {"ms": ms, "launches": sp["pass_launches"][q], "bytes": nbytes,

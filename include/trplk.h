@@ -147,9 +147,11 @@ typedef struct trplk_stats {
   double rot_ms;       int64_t rot_launches;      int64_t rot_bytes;
   double rr_ms;        int64_t rr_launches;
   /* the orthogonalisation split by pass: [0] dots (T column + first
-     coefficients; with DELAYED also the correction dots), [1] fused update +
-     dots (CGS2 only), [2] update + norm (with DELAYED: correction + update) */
-  double pass_ms[3];   int64_t pass_launches[3];  int64_t pass_bytes[3];
+     coefficients, and the last correction of a DELAYED inner block),
+     [1] fused update + dots, [2] update + norm, [3] DELAYED three-vector dots
+     (correction, T column, coefficients of the new direction), [4] DELAYED
+     correction + update */
+  double pass_ms[5];   int64_t pass_launches[5];  int64_t pass_bytes[5];
 } trplk_stats;
 
 typedef struct trplk_ctx trplk_ctx;

@@ -68,8 +68,8 @@ class _Stats(ctypes.Structure):
                 ("rot_ms", ctypes.c_double), ("rot_launches", ctypes.c_int64),
                 ("rot_bytes", ctypes.c_int64),
                 ("rr_ms", ctypes.c_double), ("rr_launches", ctypes.c_int64),
-                ("pass_ms", ctypes.c_double * 3), ("pass_launches", ctypes.c_int64 * 3),
-                ("pass_bytes", ctypes.c_int64 * 3)]
+                ("pass_ms", ctypes.c_double * 5), ("pass_launches", ctypes.c_int64 * 5),
+                ("pass_bytes", ctypes.c_int64 * 5)]
 
     def as_dict(self):
         d = {}

@@ -109,6 +109,10 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
     for (int v = 0; v < NV; ++v) acc[i][v] = 0.0;
   }
   __shared__ d2 red[2][NWV][SLABP];
+  // dot passes: the vectors' rows of a slab are read from memory once per
+  // workgroup into LDS (double-buffered, one barrier per slab) instead of once
+  // per wavefront
+  __shared__ d2 vs[MODE == ORTH_DOT ? 2 : 1][NV][MODE == ORTH_DOT ? SLABP : 1];
   int buf = 0;
   const int npair = (n + 1) / 2;
   const int nslab = (npair + SLABP - 1) / SLABP;
@@ -123,13 +127,6 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
     constexpr bool F = decltype(full)::value;
     const int base = sl * SLABP + lane;
     if constexpr (MODE == ORTH_DOT) {
-      d2 vv[NV][RP];
-#pragma unroll
-      for (int r = 0; r < RP; ++r) {
-        vv[0][r] = ld_pair<F, false>(vec0, base + WAVE * r, n);
-        if constexpr (NV >= 2) vv[1][r] = ld_pair<F, false>(vec1, base + WAVE * r, n);
-        if constexpr (NV == 3) vv[2][r] = ld_pair<F, false>(a.vec2, base + WAVE * r, n);
-      }
       // every load of the slab is issued before the first product
       constexpr int NU = (NV == 2 && !SAME) ? 2 : 1;
       d2 u[NU][CPW][RP];
@@ -144,6 +141,18 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
                 c < ncol ? ld_pair<F, NT>(a.Md1 + c * ld, base + WAVE * r, n) : d2{0.0, 0.0};
         }
       }
+      for (int e = threadIdx.x; e < NV * SLABP; e += NWV * WAVE) {
+        const int v = e / SLABP, q = e - v * SLABP;
+        const double* src = v == 0 ? vec0 : v == 1 ? vec1 : a.vec2;
+        vs[buf][v][q] = ld_pair<F, false>(src, sl * SLABP + q, n);
+      }
+      __syncthreads();
+      d2 vv[NV][RP];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) vv[v][r] = vs[buf][v][lane + WAVE * r];
+      buf ^= 1;
 #pragma unroll
       for (int i = 0; i < CPW; ++i) {
 #pragma unroll
@@ -551,6 +560,55 @@ __device__ void fin_sum2(const FinishArgs& f, int srcA, int cntA, double* dstA, 
   __syncthreads();
 }
 
+// Up to three ranges (r * ORTH_MAXCOL + column, r < nr) of at most 64
+// columns in one pass: lane c of every wavefront owns column c of each
+// range and wavefront w sums the blocks w, w + 16, ... with 8 loads per range
+// in flight; then the 16 wavefront sums are added in a fixed order.
+__device__ void fin_sum3(const FinishArgs& f, int nr, int cnt, double* dst0, double* dst1,
+                         double* dst2, double (*red3)[FIN_WAVES][WAVE]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  constexpr int U3 = 8;
+  double t[3][U3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int u = 0; u < U3; ++u) t[r][u] = 0.0;
+  if (lane < cnt) {
+    const double* p = f.partial + lane;
+    const int64_t st = f.stride;
+    int b = wv;
+    for (; b + (U3 - 1) * FIN_WAVES < f.nblk; b += U3 * FIN_WAVES) {
+#pragma unroll
+      for (int u = 0; u < U3; ++u)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          if (r < nr) t[r][u] += p[(b + u * FIN_WAVES) * st + r * ORTH_MAXCOL];
+    }
+#pragma unroll
+    for (int u = 0; u < U3; ++u)
+      if (b + u * FIN_WAVES < f.nblk)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          if (r < nr) t[r][u] += p[(b + u * FIN_WAVES) * st + r * ORTH_MAXCOL];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int w = U3 / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) t[r][u] += t[r][u + w];
+    red3[r][wv][lane] = t[r][0];
+  }
+  __syncthreads();
+  if (wv < nr && lane < cnt) {
+    double u = 0.0;
+    for (int q = 0; q < FIN_WAVES; ++q) u += red3[wv][q][lane];
+    (wv == 0 ? dst0 : wv == 1 ? dst1 : dst2)[lane] = u;
+  }
+  __syncthreads();
+}
+
 // sum of v[c]^2, c < cnt (<= 2 * 64), by the first wavefront: lane j takes
 // c = j and j + 64, then a fixed shuffle tree
 __device__ __forceinline__ double sumsq_wave(const double* v, int cnt) {
@@ -662,24 +720,36 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       // and the new direction's coefficients h(0:j) = b(0:j),
       // h(j) = (b_j - c.b) / gamma.  A U(:, j) is kept as the stored z': the
       // true products are AU_stored L with L(:, j) = (e_j - L c) / gamma.
+      // (the host runs this form with no locked columns and j + 1 <= 64)
       const int j = nb;
       const bool withw = f.nvec == 3;
       double* a_ = v0;
       double* t_ = v0 + ORTH_MAXCOL;
-      fin_sum(f, 0, j + 1, a_, red);
-      fin_sum(f, ORTH_MAXCOL, j + 1, t_, red);
-      if (withw) fin_sum(f, 2 * ORTH_MAXCOL, j + 1, v1, red);
-      __shared__ double ys[ORTH_MAXCOL];
-      __shared__ double ls[ORTH_MAXCOL];
+      __shared__ double red3[3][FIN_WAVES][WAVE];
+      __shared__ double ys[WAVE];
+      __shared__ double ls[WAVE];
       __shared__ double sc[4];
-      for (int i = tid; i < j; i += blockDim.x) {
+      fin_sum3(f, withw ? 3 : 2, j + 1, a_, t_, v1, red3);
+      // T c and L c: lane i owns row i, wavefront w the columns w, w + 16, ...
+      {
+        const int lane = tid & (WAVE - 1), wv = tid / WAVE;
         double y = 0.0, l = 0.0;
-        for (int k = 0; k < j; ++k) y += f.T[i + static_cast<int64_t>(k) * f.ldT] * a_[k];
-        for (int k = i; k < j; ++k) l += f.L[i + static_cast<int64_t>(k) * f.ldT] * a_[k];
-        ys[i] = y;
-        ls[i] = l;
+        if (lane < j) {
+          for (int k = wv; k < j; k += FIN_WAVES) {
+            y += f.T[lane + static_cast<int64_t>(k) * f.ldT] * a_[k];
+            l += f.L[lane + static_cast<int64_t>(k) * f.ldT] * a_[k];
+          }
+        }
+        red3[0][wv][lane] = y;
+        red3[1][wv][lane] = l;
+        __syncthreads();
+        if (wv < 2 && lane < j) {
+          double u = 0.0;
+          for (int q = 0; q < FIN_WAVES; ++q) u += red3[wv][q][lane];
+          (wv == 0 ? ys : ls)[lane] = u;
+        }
+        __syncthreads();
       }
-      __syncthreads();
       if (tid < WAVE) {
         double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
         for (int k = tid; k < j; k += WAVE) {
@@ -786,15 +856,20 @@ __global__ void k_reset_T(double* T, int ldT, int m, int kact, const double* the
 
 // YA = L Y over the b = st->nb basis columns (L upper triangular); every
 // column of Y is transformed (the rotation reads the first kout).
-__global__ __launch_bounds__(256) void k_ly(const double* L, const double* Y, double* YA, int ld,
-                                            const DevState* st) {
+__global__ __launch_bounds__(64) void k_ly(const double* L, const double* Y, double* YA, int ld,
+                                           const DevState* st) {
+  // block c computes column c; thread i row i (b <= 64)
   const int b = st->nb;
-  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-    const int i = e % b, c = e / b;
-    double v = 0.0;
-    for (int k = i; k < b; ++k) v += L[i + static_cast<int64_t>(k) * ld] * Y[k + static_cast<int64_t>(c) * ld];
-    YA[i + static_cast<int64_t>(c) * ld] = v;
-  }
+  const int c = blockIdx.x, i = threadIdx.x;
+  if (c >= b) return;
+  __shared__ double yc[64];
+  yc[i] = i < b ? Y[i + static_cast<int64_t>(c) * ld] : 0.0;
+  __syncthreads();
+  if (i >= b) return;
+  double v = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < b; ++k) v += L[i + static_cast<int64_t>(k) * ld] * yc[k];
+  YA[i + static_cast<int64_t>(c) * ld] = v;
 }
 
 __global__ void k_eye(double* L, int ld, int m) {
@@ -947,7 +1022,7 @@ hipError_t reset_T(double* T, int ldT, int m, int kact, const double* theta, int
 
 hipError_t ly_product(const double* L, const double* Y, double* YA, int ld, const DevState* st,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_ly, dim3(1), dim3(256), 0, s, L, Y, YA, ld, st);
+  hipLaunchKernelGGL(k_ly, dim3(64), dim3(64), 0, s, L, Y, YA, ld, st);
   return hipGetLastError();
 }
 

@@ -273,7 +273,7 @@ void free_csr(DevCsr& D) {
 
 // ------------------------------------------------------------ profiling --
 enum { PC_SPMV = 0, PC_ORTH = 1, PC_PREC = 2, PC_ROT = 3, PC_RR = 4, PC_DOT = 5, PC_UPDDOT = 6,
-       PC_UPD = 7 };
+       PC_UPD = 7, PC_DCDOT = 8, PC_DCUPD = 9 };
 
 struct ProfScope {
   trplk_ctx* c;
@@ -393,7 +393,9 @@ struct Solver {
     else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
     else if (mode == ORTH_UPD2) bytes = 8 * (cols - 1) * n + (a.w ? 32LL : 16LL) * n;
     else bytes = 8 * cols * n + 16LL * n;
-    ProfScope ps(c, mode == ORTH_DOT ? PC_DOT : mode == ORTH_UPD_DOT ? PC_UPDDOT : PC_UPD, bytes);
+    const int cls = mode == ORTH_DOT ? (a.nvec == 3 ? PC_DCDOT : PC_DOT)
+                    : mode == ORTH_UPD_DOT ? PC_UPDDOT : mode == ORTH_UPD2 ? PC_DCUPD : PC_UPD;
+    ProfScope ps(c, cls, bytes);
     return orth_pass(mode, a, orth_blocks(n, mode), s);
   }
   int nblk(int mode) const { return orth_blocks(n, mode); }
@@ -1045,7 +1047,9 @@ void Solver::collect_profile() {
         case PC_SPMV: stt.spmv_ms += e; stt.spmv_launches++; stt.spmv_bytes += pr.bytes; break;
         case PC_DOT:
         case PC_UPDDOT:
-        case PC_UPD: {
+        case PC_UPD:
+        case PC_DCDOT:
+        case PC_DCUPD: {
           stt.orth_ms += e; stt.orth_launches++; stt.orth_bytes += pr.bytes;
           const int q = pr.cls - PC_DOT;
           stt.pass_ms[q] += e; stt.pass_launches[q]++; stt.pass_bytes[q] += pr.bytes;
