@@ -729,15 +729,28 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       __shared__ double ys[WAVE];
       __shared__ double ls[WAVE];
       __shared__ double sc[4];
-      fin_sum3(f, withw ? 3 : 2, j + 1, a_, t_, v1, red3);
       // T c and L c: lane i owns row i, wavefront w the columns w, w + 16, ...
+      // (j <= 63: at most 4 each); the entries are loaded before the sums so
+      // that their latency overlaps
+      const int lane = tid & (WAVE - 1), wv = tid / WAVE;
+      constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
+      double tv[KQ], lv[KQ];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const int k = wv + FIN_WAVES * q;
+        const bool on = lane < j && k < j;
+        tv[q] = on ? f.T[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
+        lv[q] = on ? f.L[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
+      }
+      fin_sum3(f, withw ? 3 : 2, j + 1, a_, t_, v1, red3);
       {
-        const int lane = tid & (WAVE - 1), wv = tid / WAVE;
         double y = 0.0, l = 0.0;
-        if (lane < j) {
-          for (int k = wv; k < j; k += FIN_WAVES) {
-            y += f.T[lane + static_cast<int64_t>(k) * f.ldT] * a_[k];
-            l += f.L[lane + static_cast<int64_t>(k) * f.ldT] * a_[k];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+          const int k = wv + FIN_WAVES * q;
+          if (lane < j && k < j) {
+            y += tv[q] * a_[k];
+            l += lv[q] * a_[k];
           }
         }
         red3[0][wv][lane] = y;

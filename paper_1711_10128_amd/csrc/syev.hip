@@ -18,7 +18,7 @@ namespace trplk {
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;  // 16 wavefronts: every 2 x 2 block of a round has its own thread
 constexpr int MB = SYEV_MAXB;
 constexpr int LDA = MB + 1;  // padding against LDS bank conflicts
 
