@@ -173,6 +173,7 @@ struct OrthArgs {
 constexpr int ORTH_MAXCOL = 128;
 int orth_blocks(int n, int mode);   // grid of a pass (its partial count)
 int orth_blocks_max(int n);
+int orth_blocks_dot3(int n);        // grid of the three-vector dot pass (nvec = 3)
 int orth_stride();  // partial stride per block (doubles)
 hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s);
 

@@ -235,7 +235,8 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double s = wave_sum(acc[i][v]);
-      if (lane == 0 && c < ncol) out[v * ORTH_MAXCOL + c] = s;
+      // three vectors: compact [v][ncol] layout (read by the delayed finish)
+      if (lane == 0 && c < ncol) out[v * (NV == 3 ? ncol : ORTH_MAXCOL) + c] = s;
     }
   }
 }
@@ -433,9 +434,6 @@ hipError_t launch_rp(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   if (mode == ORTH_DOT) {
     if (a.nvec == 1) {
       hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 1, true, RP, NT, NWV>), g, b, 0, s, a);
-    } else if (a.nvec == 3) {
-      // all three vectors against Md0
-      hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 3, true, RP, NT, NWV>), g, b, 0, s, a);
     } else if (same) {
       hipLaunchKernelGGL((k_orth<CPW, ORTH_DOT, 2, true, RP, NT, NWV>), g, b, 0, s, a);
     } else {
@@ -560,55 +558,6 @@ __device__ void fin_sum2(const FinishArgs& f, int srcA, int cntA, double* dstA, 
   __syncthreads();
 }
 
-// Up to three ranges (r * ORTH_MAXCOL + column, r < nr) of at most 64
-// columns in one pass: lane c of every wavefront owns column c of each
-// range and wavefront w sums the blocks w, w + 16, ... with 8 loads per range
-// in flight; then the 16 wavefront sums are added in a fixed order.
-__device__ void fin_sum3(const FinishArgs& f, int nr, int cnt, double* dst0, double* dst1,
-                         double* dst2, double (*red3)[FIN_WAVES][WAVE]) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int wv = threadIdx.x / WAVE;
-  constexpr int U3 = 8;
-  double t[3][U3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int u = 0; u < U3; ++u) t[r][u] = 0.0;
-  if (lane < cnt) {
-    const double* p = f.partial + lane;
-    const int64_t st = f.stride;
-    int b = wv;
-    for (; b + (U3 - 1) * FIN_WAVES < f.nblk; b += U3 * FIN_WAVES) {
-#pragma unroll
-      for (int u = 0; u < U3; ++u)
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-          if (r < nr) t[r][u] += p[(b + u * FIN_WAVES) * st + r * ORTH_MAXCOL];
-    }
-#pragma unroll
-    for (int u = 0; u < U3; ++u)
-      if (b + u * FIN_WAVES < f.nblk)
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-          if (r < nr) t[r][u] += p[(b + u * FIN_WAVES) * st + r * ORTH_MAXCOL];
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int w = U3 / 2; w >= 1; w >>= 1)
-#pragma unroll
-      for (int u = 0; u < w; ++u) t[r][u] += t[r][u + w];
-    red3[r][wv][lane] = t[r][0];
-  }
-  __syncthreads();
-  if (wv < nr && lane < cnt) {
-    double u = 0.0;
-    for (int q = 0; q < FIN_WAVES; ++q) u += red3[wv][q][lane];
-    (wv == 0 ? dst0 : wv == 1 ? dst1 : dst2)[lane] = u;
-  }
-  __syncthreads();
-}
-
 // sum of v[c]^2, c < cnt (<= 2 * 64), by the first wavefront: lane j takes
 // c = j and j + 64, then a fixed shuffle tree
 __device__ __forceinline__ double sumsq_wave(const double* v, int cnt) {
@@ -709,114 +658,6 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       }
       break;
     }
-    case FIN_DC: {
-      // Delayed step for the pending column j = nb (u' at U(:, j), z' = A u'
-      // at AU(:, j)); the dot pass gave a = U(:, 0:j+1)^T u', t = U^T z' and,
-      // with nvec = 3, b = U^T w.  With c = a(0:j) and
-      // gamma^2 = a_j - |c|^2 the corrected column is u = (u' - U c) / gamma;
-      // A u = (z' - A U c) / gamma gives, with T = U^T A U and A symmetric,
-      //   T(i, j) = (t_i - (T c)_i) / gamma                 (i < j)
-      //   T(j, j) = (t_j - 2 c.t + c.(T c)) / gamma^2
-      // and the new direction's coefficients h(0:j) = b(0:j),
-      // h(j) = (b_j - c.b) / gamma.  A U(:, j) is kept as the stored z': the
-      // true products are AU_stored L with L(:, j) = (e_j - L c) / gamma.
-      // (the host runs this form with no locked columns and j + 1 <= 64)
-      const int j = nb;
-      const bool withw = f.nvec == 3;
-      double* a_ = v0;
-      double* t_ = v0 + ORTH_MAXCOL;
-      __shared__ double red3[3][FIN_WAVES][WAVE];
-      __shared__ double ys[WAVE];
-      __shared__ double ls[WAVE];
-      __shared__ double sc[4];
-      // T c and L c: lane i owns row i, wavefront w the columns w, w + 16, ...
-      // (j <= 63: at most 4 each); the entries are loaded before the sums so
-      // that their latency overlaps
-      const int lane = tid & (WAVE - 1), wv = tid / WAVE;
-      constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
-      double tv[KQ], lv[KQ];
-#pragma unroll
-      for (int q = 0; q < KQ; ++q) {
-        const int k = wv + FIN_WAVES * q;
-        const bool on = lane < j && k < j;
-        tv[q] = on ? f.T[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
-        lv[q] = on ? f.L[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
-      }
-      fin_sum3(f, withw ? 3 : 2, j + 1, a_, t_, v1, red3);
-      {
-        double y = 0.0, l = 0.0;
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-          const int k = wv + FIN_WAVES * q;
-          if (lane < j && k < j) {
-            y += tv[q] * a_[k];
-            l += lv[q] * a_[k];
-          }
-        }
-        red3[0][wv][lane] = y;
-        red3[1][wv][lane] = l;
-        __syncthreads();
-        if (wv < 2 && lane < j) {
-          double u = 0.0;
-          for (int q = 0; q < FIN_WAVES; ++q) u += red3[wv][q][lane];
-          (wv == 0 ? ys : ls)[lane] = u;
-        }
-        __syncthreads();
-      }
-      if (tid < WAVE) {
-        double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
-        for (int k = tid; k < j; k += WAVE) {
-          cc += a_[k] * a_[k];
-          ct += a_[k] * t_[k];
-          cy += a_[k] * ys[k];
-          if (withw) cb += a_[k] * v1[k];
-        }
-        cc = wave_sum(cc);
-        ct = wave_sum(ct);
-        cy = wave_sum(cy);
-        cb = wave_sum(cb);
-        if (tid == 0) {
-          const double g2 = a_[j] - cc;
-          const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
-          const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
-          if (!ok) {
-            st->bad = 1;
-            st->skip = 1;
-          }
-          st->inv_gamma = ig;
-          sc[0] = ig;
-          sc[1] = (t_[j] - 2.0 * ct + cy) * ig * ig;
-          sc[2] = withw ? (v1[j] - cb) * ig : 0.0;
-        }
-      }
-      __syncthreads();
-      const double ig = sc[0];
-      for (int i = tid; i < j; i += blockDim.x) {
-        const double tij = (t_[i] - ys[i]) * ig;
-        f.T[i + static_cast<int64_t>(j) * f.ldT] = tij;
-        f.T[j + static_cast<int64_t>(i) * f.ldT] = tij;
-        f.L[i + static_cast<int64_t>(j) * f.ldT] = -ls[i] * ig;
-        f.cbuf[i] = a_[i];
-        if (withw) f.h[i] = v1[i];
-      }
-      if (tid == 0) {
-        f.T[j + static_cast<int64_t>(j) * f.ldT] = sc[1];
-        f.L[j + static_cast<int64_t>(j) * f.ldT] = ig;
-        if (withw) f.h[j] = sc[2];
-      }
-      if (withw && tid < WAVE) {
-        double hh = 0.0;
-        for (int k = tid; k < j; k += WAVE) hh += v1[k] * v1[k];
-        hh = wave_sum(hh);
-        if (tid == 0) st->h1norm2 = hh + sc[2] * sc[2];
-      }
-      __syncthreads();
-      if (tid == 0) {
-        st->nb = nb + 1;
-        st->cnt_append += 1;
-      }
-      break;
-    }
     case FIN_NORM: {
       const double b2s = fin_one(f, 0, red);
       if (tid == 0) {
@@ -842,6 +683,176 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       }
       break;
     }
+  }
+}
+
+// Finish of the delayed step (FIN_DC).  The pending column is j = nb: u' at
+// U(:, j), z' = A u' at AU(:, j); the three-vector dot pass left, per block,
+// a = U(:, 0:j+1)^T u', t = U^T z' and b = U^T w packed as [a | t | b] (j + 1
+// entries each, j + 1 <= 64).  With c = a(0:j) and gamma^2 = a_j - |c|^2 the
+// corrected column is u = (u' - U c) / gamma; A u = (z' - A U c) / gamma
+// gives, with T = U^T A U and A symmetric,
+//   T(i, j) = (t_i - (T c)_i) / gamma                 (i < j)
+//   T(j, j) = (t_j - 2 c.t + c.(T c)) / gamma^2
+// and the new direction's coefficients h(0:j) = b(0:j),
+// h(j) = (b_j - c.b) / gamma (nvec = 3; nvec = 2 ignores b).  A U(:, j) keeps
+// the stored z': the true products are AU_stored L with
+// L(:, j) = (e_j - L c) / gamma.
+// The block sums: lane l of wavefront w loads entries 2l, 2l + 1 (and
+// 128 + 2l, 129 + 2l) of blocks w, w + 16, ... with 16-byte loads, so one
+// load covers a block's three sums when 3 (j + 1) <= 128.
+template <int SLOTS>
+__device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, double (*red)[3 * WAVE]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  constexpr int U = 16 / SLOTS;  // blocks in flight per lane
+  d2 t[SLOTS][U];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[q][u] = d2{0.0, 0.0};
+  const int64_t st = f.stride;
+  const bool on0 = 2 * lane < tot, on1 = 2 * lane + 2 * WAVE < tot;
+  int b = wv;
+  auto ld = [&](int blk, int q) -> d2 {
+    return *reinterpret_cast<const d2*>(f.partial + blk * st + 2 * lane + 2 * WAVE * q);
+  };
+  for (; b + (U - 1) * FIN_WAVES < f.nblk; b += U * FIN_WAVES) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (on0) t[0][u] += ld(b + u * FIN_WAVES, 0);
+      if (SLOTS == 2 && on1) t[SLOTS - 1][u] += ld(b + u * FIN_WAVES, 1);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (b + u * FIN_WAVES < f.nblk) {
+      if (on0) t[0][u] += ld(b + u * FIN_WAVES, 0);
+      if (SLOTS == 2 && on1) t[SLOTS - 1][u] += ld(b + u * FIN_WAVES, 1);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+    for (int w = U / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) t[q][u] += t[q][u + w];
+    const int e = 2 * lane + 2 * WAVE * q;
+    if (e < 3 * WAVE) {
+      red[wv][e] = t[q][0].x;
+      red[wv][e + 1] = t[q][0].y;
+    }
+  }
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
+  DevState* st = f.state;
+  if (st->skip) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int j = st->nb;
+  const int cnt = j + 1;
+  const int tot = 3 * cnt;
+  const bool withw = f.nvec == 3;
+  __shared__ double red[FIN_WAVES][3 * WAVE];
+  __shared__ double s3[3 * WAVE];
+  __shared__ double ys[WAVE];
+  __shared__ double ls[WAVE];
+  __shared__ double sc[4];
+  if (tot <= 2 * WAVE) dc_block_sums<1>(f, tot, red);
+  else dc_block_sums<2>(f, tot, red);
+  // T(0:j, 0:j) and L(0:j, 0:j) entries for T c and L c: lane i owns row i,
+  // wavefront w the columns w, w + 16, ...
+  constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
+  double tv[KQ], lv[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int k = wv + FIN_WAVES * q;
+    const bool on = lane < j && k < j;
+    tv[q] = on ? f.T[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
+    lv[q] = on ? f.L[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < tot; e += FIN_THREADS) {
+    double u = 0.0;
+    for (int q = 0; q < FIN_WAVES; ++q) u += red[q][e];
+    s3[e] = u;
+  }
+  __syncthreads();
+  const double* a_ = s3;
+  const double* t_ = s3 + cnt;
+  const double* b_ = s3 + 2 * cnt;
+  {
+    double y = 0.0, l = 0.0;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int k = wv + FIN_WAVES * q;
+      if (lane < j && k < j) {
+        y += tv[q] * a_[k];
+        l += lv[q] * a_[k];
+      }
+    }
+    red[wv][lane] = y;
+    red[wv][WAVE + lane] = l;
+    __syncthreads();
+    if (wv < 2 && lane < j) {
+      double u = 0.0;
+      for (int q = 0; q < FIN_WAVES; ++q) u += red[q][WAVE * wv + lane];
+      (wv == 0 ? ys : ls)[lane] = u;
+    }
+    __syncthreads();
+  }
+  if (tid < WAVE) {
+    double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
+    for (int k = tid; k < j; k += WAVE) {
+      cc += a_[k] * a_[k];
+      ct += a_[k] * t_[k];
+      cy += a_[k] * ys[k];
+      if (withw) cb += a_[k] * b_[k];
+    }
+    cc = wave_sum(cc);
+    ct = wave_sum(ct);
+    cy = wave_sum(cy);
+    cb = wave_sum(cb);
+    if (tid == 0) {
+      const double g2 = a_[j] - cc;
+      const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
+      const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
+      if (!ok) {
+        st->bad = 1;
+        st->skip = 1;
+      }
+      st->inv_gamma = ig;
+      sc[0] = ig;
+      sc[1] = (t_[j] - 2.0 * ct + cy) * ig * ig;
+      sc[2] = withw ? (b_[j] - cb) * ig : 0.0;
+    }
+  }
+  __syncthreads();
+  const double ig = sc[0];
+  for (int i = tid; i < j; i += FIN_THREADS) {
+    const double tij = (t_[i] - ys[i]) * ig;
+    f.T[i + static_cast<int64_t>(j) * f.ldT] = tij;
+    f.T[j + static_cast<int64_t>(i) * f.ldT] = tij;
+    f.L[i + static_cast<int64_t>(j) * f.ldT] = -ls[i] * ig;
+    f.cbuf[i] = a_[i];
+    if (withw) f.h[i] = b_[i];
+  }
+  if (tid == 0) {
+    f.T[j + static_cast<int64_t>(j) * f.ldT] = sc[1];
+    f.L[j + static_cast<int64_t>(j) * f.ldT] = ig;
+    if (withw) f.h[j] = sc[2];
+  }
+  if (withw && tid < WAVE) {
+    double hh = 0.0;
+    for (int k = tid; k < j; k += WAVE) hh += b_[k] * b_[k];
+    hh = wave_sum(hh);
+    if (tid == 0) st->h1norm2 = hh + sc[2] * sc[2];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->nb = j + 1;
+    st->cnt_append += 1;
   }
 }
 
@@ -991,6 +1002,14 @@ int orth_blocks(int n, int mode) {
 
 int orth_blocks_max(int n) { return std::max(orth_blocks(n, ORTH_DOT), orth_blocks(n, ORTH_UPD)); }
 
+// The three-vector dot pass runs 16 wavefronts per workgroup on half the
+// workgroups: the same residency, half the partial rows for its finish.
+int orth_blocks_dot3(int n) {
+  const int npair = (std::max(n, 1) + 1) / 2;
+  const int nslab = (npair + WAVE * ORTH_RP - 1) / (WAVE * ORTH_RP);
+  return std::max(1, std::min(nslab, 256));
+}
+
 int orth_stride() { return STRIDE; }
 
 hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
@@ -1010,10 +1029,26 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
     else hipLaunchKernelGGL(k_upd2<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
     return hipGetLastError();
   }
+  if (mode == ORTH_DOT && a.nvec == 3) {
+    const dim3 g(nblk), b(16 * WAVE);
+    if ((need + 15) / 16 <= 4) {
+      if (nt) hipLaunchKernelGGL((k_orth<4, ORTH_DOT, 3, true, ORTH_RP, true, 16>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_orth<4, ORTH_DOT, 3, true, ORTH_RP, false, 16>), g, b, 0, s, a);
+    } else {
+      if (nt) hipLaunchKernelGGL((k_orth<8, ORTH_DOT, 3, true, ORTH_RP, true, 16>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_orth<8, ORTH_DOT, 3, true, ORTH_RP, false, 16>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+  }
   return nt ? launch_width<true>(mode, a, need, nblk, s) : launch_width<false>(mode, a, need, nblk, s);
 }
 
 hipError_t finish(const FinishArgs& f, hipStream_t s) {
+  if (f.mode == FIN_DC) {
+    if (!f.state || !f.T || !f.L || !f.cbuf || (f.nvec == 3 && !f.h)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_finish_dc, dim3(1), dim3(FIN_THREADS), 0, s, f);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(FIN_THREADS), 0, s, f);
   return hipGetLastError();
 }

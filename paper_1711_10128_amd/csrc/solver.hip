@@ -396,7 +396,8 @@ struct Solver {
     const int cls = mode == ORTH_DOT ? (a.nvec == 3 ? PC_DCDOT : PC_DOT)
                     : mode == ORTH_UPD_DOT ? PC_UPDDOT : mode == ORTH_UPD2 ? PC_DCUPD : PC_UPD;
     ProfScope ps(c, cls, bytes);
-    return orth_pass(mode, a, orth_blocks(n, mode), s);
+    const int g = (mode == ORTH_DOT && a.nvec == 3) ? orth_blocks_dot3(n) : orth_blocks(n, mode);
+    return orth_pass(mode, a, g, s);
   }
   int nblk(int mode) const { return orth_blocks(n, mode); }
 
@@ -574,10 +575,12 @@ struct Solver {
       a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.ncol_extra = 1; a.state = c->st;
       a.ncol_max = maxcols();
       a.Md0 = Wq(); a.Md1 = Wq(); a.vec0_base = c->W; a.vec1_base = c->AW; a.vec0_col0 = ncf;
-      a.nvec = more ? 3 : 2; a.vec2 = more ? c->w : nullptr; a.partial = c->partial;
+      // three vectors also for the last column (the third, w, is then unused):
+      // the finish reads the packed three-vector layout
+      a.nvec = 3; a.vec2 = c->w; a.partial = c->partial;
       S.check(orth(ORTH_DOT, a), "orth dc dot");
       FinishArgs f;
-      f.mode = FIN_DC; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
+      f.mode = FIN_DC; f.partial = c->partial; f.nblk = orth_blocks_dot3(n); f.stride = orth_stride();
       f.state = c->st; f.ncol_fixed = ncf; f.T = c->T; f.ldT = SYEV_MAXB; f.h = c->hbuf;
       f.nvec = more ? 3 : 2; f.cbuf = c->cbuf; f.L = c->Lm;
       S.check(fin(f), "fin dc");
