@@ -453,9 +453,19 @@ hipError_t launch_cpw(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
 
 template <bool NT>
 hipError_t launch_width(int mode, const OrthArgs& a, int need, int nblk, hipStream_t s) {
-  // 8 wavefronts owning ceil(need / 8) columns each (16 wavefronts of 8
-  // columns for wide bases measured slower on MI355X: the per-slab LDS
-  // exchange and barrier over 16 wavefronts cost more than the occupancy gains)
+  if (mode == ORTH_DOT) {
+    // dot passes: 16 wavefronts per workgroup on half the workgroups (half
+    // the partial rows for the finishing reduction, the vectors staged once
+    // for 16 wavefronts)
+    const int cpw16 = (std::max(need, 1) + 15) / 16;
+    if (cpw16 <= 1) return launch_cpw<1, NT, 16>(mode, a, nblk, s);
+    if (cpw16 <= 2) return launch_cpw<2, NT, 16>(mode, a, nblk, s);
+    if (cpw16 <= 4) return launch_cpw<4, NT, 16>(mode, a, nblk, s);
+    return launch_cpw<8, NT, 16>(mode, a, nblk, s);
+  }
+  // fused update + dot: 8 wavefronts owning ceil(need / 8) columns each (16
+  // wavefronts measured slower on MI355X: the per-slab LDS exchange and
+  // barrier over 16 wavefronts cost more than the occupancy gains)
   const int cpw = (std::max(need, 1) + 7) / 8;
   if (cpw > 8) return launch_cpw<16, NT, 8>(mode, a, nblk, s);
   if (cpw <= 1) return launch_cpw<1, NT, 8>(mode, a, nblk, s);
@@ -996,19 +1006,17 @@ int orth_blocks(int n, int mode) {
     return std::max(1, std::min(want, g_orth_maxblk > 0 ? g_orth_maxblk : 1024));
   }
   const int nslab = (npair + WAVE * ORTH_RP - 1) / (WAVE * ORTH_RP);
-  const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : 512;
+  const int cap = g_orth_maxblk > 0 ? g_orth_maxblk : (mode == ORTH_DOT ? 256 : 512);
   return std::max(1, std::min(nslab, cap));
 }
 
-int orth_blocks_max(int n) { return std::max(orth_blocks(n, ORTH_DOT), orth_blocks(n, ORTH_UPD)); }
-
-// The three-vector dot pass runs 16 wavefronts per workgroup on half the
-// workgroups: the same residency, half the partial rows for its finish.
-int orth_blocks_dot3(int n) {
-  const int npair = (std::max(n, 1) + 1) / 2;
-  const int nslab = (npair + WAVE * ORTH_RP - 1) / (WAVE * ORTH_RP);
-  return std::max(1, std::min(nslab, 256));
+// largest grid of any pass: sizes the partial buffer
+int orth_blocks_max(int n) {
+  return std::max({orth_blocks(n, ORTH_DOT), orth_blocks(n, ORTH_UPD_DOT), orth_blocks(n, ORTH_UPD),
+                   orth_blocks(n, ORTH_UPD2), orth_blocks_dot3(n)});
 }
+
+int orth_blocks_dot3(int n) { return orth_blocks(n, ORTH_DOT); }
 
 int orth_stride() { return STRIDE; }
 

@@ -111,6 +111,7 @@ struct trplk_ctx {
   Report* rep_d = nullptr;
   int orth_nblk = 0, rot_nblk = 0;  // orth_nblk: largest pass grid (sizes partials)
   int64_t partial_bytes = 0;
+  int64_t partial_cap = 0;  // doubles in `partial`
   bool ws_ready = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> evpool;
@@ -336,6 +337,7 @@ int ensure_workspace(trplk_ctx* c) {
   if (c->hasB) pb = std::max<int64_t>(pb, spmv_partial_blocks(c->B.plan));
   pb = std::max<int64_t>(pb, 2 * static_cast<int64_t>(rownorm_blocks(n)));
   HIPCHK(c, dalloc(c, &c->partial, pb));
+  c->partial_cap = pb;
   HIPCHK(c, dalloc(c, &c->st, 1));
   HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), c->s));
   HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->rep_h), sizeof(Report)));
@@ -397,6 +399,8 @@ struct Solver {
                     : mode == ORTH_UPD_DOT ? PC_UPDDOT : mode == ORTH_UPD2 ? PC_DCUPD : PC_UPD;
     ProfScope ps(c, cls, bytes);
     const int g = (mode == ORTH_DOT && a.nvec == 3) ? orth_blocks_dot3(n) : orth_blocks(n, mode);
+    // every block writes one row of partials
+    if (static_cast<int64_t>(g) * orth_stride() > c->partial_cap) return hipErrorInvalidValue;
     return orth_pass(mode, a, g, s);
   }
   int nblk(int mode) const { return orth_blocks(n, mode); }
