@@ -18,7 +18,7 @@ struct DevState {
   int nb;          // columns of the active basis U (after the locked set)
   int skip;        // nonzero: step kernels of the current stage return at once
   int bad;         // nonzero: a B-norm squared <= 0 or a non-finite value was seen
-  int nappend;     // vectors appended in the current stage
+  int pending;     // delayed form: column nb holds a vector awaiting its correction
   double beta2;    // B-norm squared of the vector being appended
   double inv_beta; // 1 / sqrt(beta2)
   double h1norm2;  // squared norm of the first Gram-Schmidt coefficients
@@ -209,6 +209,8 @@ struct FinishArgs {
                         // column (a basis orthogonalised among its own columns only)
   double* cbuf = nullptr;  // FIN_DC: correction coefficients out (ORTH_MAXCOL)
   double* L = nullptr;     // FIN_DC: AU_true = AU_stored L (upper triangular, ldT)
+  int dc = 0;              // FIN_NORM: an accepted vector becomes pending (delayed form);
+                           // FIN_DC: correct column nb only if it is pending
 };
 hipError_t finish(const FinishArgs& f, hipStream_t s);
 

@@ -332,7 +332,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
 template <bool NT>
 __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
   if (a.state->skip) return;
-  const int j = a.ncol_fixed + a.state->nb - 1;
+  // inv_gamma == 0: no pending column (the finish found none); w is projected
+  // against the nb final columns only
+  const double ig = a.state->inv_gamma;
+  const bool corr = ig != 0.0;
+  const int j = a.ncol_fixed + a.state->nb - (corr ? 1 : 0);
   __shared__ double hs[ORTH_MAXCOL];
   __shared__ double cs[ORTH_MAXCOL];
   __shared__ double red[UPD_THREADS / WAVE];
@@ -342,8 +346,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
     hs[c] = withw ? a.h[c] : 0.0;
   }
   __syncthreads();
-  const double ig = a.state->inv_gamma;
-  const double hl = withw ? a.h[j] : 0.0;
+  const double hl = (withw && corr) ? a.h[j] : 0.0;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   const int64_t ld = a.ld;
@@ -394,11 +397,13 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
 #pragma unroll
     for (int r = 0; r < UPD_RP; ++r) {
       const int p = base + WAVE * r;
-      const d2 up = ld_pair<F, false>(ucol, p, n);
-      d2 un;
-      un.x = (up.x - pu[r].x) * ig;
-      un.y = (up.y - pu[r].y) * ig;
-      st_pair<F>(ucol, p, n, un);
+      d2 un{0.0, 0.0};
+      if (corr) {
+        const d2 up = ld_pair<F, false>(ucol, p, n);
+        un.x = (up.x - pu[r].x) * ig;
+        un.y = (up.y - pu[r].y) * ig;
+        st_pair<F>(ucol, p, n, un);
+      }
       if (withw) {
         const d2 w = ld_pair<F, false>(a.w, p, n);
         d2 wn;
@@ -680,6 +685,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
           st->skip = 1;  // breakdown / dropped vector: nothing is appended
         } else {
           st->inv_beta = 1.0 / sqrt(b2);
+          if (f.dc) st->pending = 1;
         }
       }
       break;
@@ -764,6 +770,9 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   const int cnt = j + 1;
   const int tot = 3 * cnt;
   const bool withw = f.nvec == 3;
+  // f.dc: column j is corrected only when it is pending (after a breakdown
+  // nothing is: then only w is projected, against the j final columns)
+  const bool corr = !f.dc || st->pending;
   __shared__ double red[FIN_WAVES][3 * WAVE];
   __shared__ double s3[3 * WAVE];
   __shared__ double ys[WAVE];
@@ -771,6 +780,26 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   __shared__ double sc[4];
   if (tot <= 2 * WAVE) dc_block_sums<1>(f, tot, red);
   else dc_block_sums<2>(f, tot, red);
+  if (!corr) {
+    __syncthreads();
+    for (int e = tid; e < j; e += FIN_THREADS) {
+      double u = 0.0;
+      for (int q = 0; q < FIN_WAVES; ++q) u += red[q][2 * cnt + e];
+      s3[e] = u;
+      if (withw) f.h[e] = u;
+    }
+    __syncthreads();
+    if (tid < WAVE) {
+      double hh = 0.0;
+      for (int k = tid; k < j; k += WAVE) hh += s3[k] * s3[k];
+      hh = wave_sum(hh);
+      if (tid == 0) {
+        st->h1norm2 = hh;
+        st->inv_gamma = 0.0;  // tells the update pass: no column to correct
+      }
+    }
+    return;
+  }
   // T(0:j, 0:j) and L(0:j, 0:j) entries for T c and L c: lane i owns row i,
   // wavefront w the columns w, w + 16, ...
   constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
@@ -863,6 +892,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   if (tid == 0) {
     st->nb = j + 1;
     st->cnt_append += 1;
+    st->pending = 0;
   }
 }
 

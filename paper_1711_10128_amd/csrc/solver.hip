@@ -560,7 +560,7 @@ struct Solver {
     }
     FinishArgs f;
     f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
-    f.nblk = nblk(ORTH_UPD); f.stride = orth_stride();
+    f.nblk = nblk(ORTH_UPD); f.stride = orth_stride(); f.dc = 1;
     S.check(fin(f), "fin norm");
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
@@ -571,7 +571,9 @@ struct Solver {
   // the correction c, the exact T column of the corrected vector and the
   // coefficients of w; one update pass writes u = (u' - U c) / gamma in
   // place and the once-orthogonalised w into wtmp with its norm.
-  int dc_step(bool more) {
+  // plusk: the vector in c->w is a +K vector; the column at nb is corrected
+  // only if it is pending (not after a breakdown of the Krylov block)
+  int dc_step(bool more, bool plusk = false) {
     Status S;
     const int ncf = c->u0;
     {
@@ -586,7 +588,7 @@ struct Solver {
       FinishArgs f;
       f.mode = FIN_DC; f.partial = c->partial; f.nblk = orth_blocks_dot3(n); f.stride = orth_stride();
       f.state = c->st; f.ncol_fixed = ncf; f.T = c->T; f.ldT = SYEV_MAXB; f.h = c->hbuf;
-      f.nvec = more ? 3 : 2; f.cbuf = c->cbuf; f.L = c->Lm;
+      f.nvec = more ? 3 : 2; f.cbuf = c->cbuf; f.L = c->Lm; f.dc = plusk ? 1 : 0;
       S.check(fin(f), "fin dc");
     }
     {
@@ -603,7 +605,7 @@ struct Solver {
     if (more) {
       FinishArgs f;
       f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
-      f.nblk = nblk(ORTH_UPD2); f.stride = orth_stride();
+      f.nblk = nblk(ORTH_UPD2); f.stride = orth_stride(); f.dc = 1;
       S.check(fin(f), "fin dc norm");
     }
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
@@ -879,10 +881,11 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       const bool more = j < m_in - 1;
       if (dc) {
         // one Gram-Schmidt pass per vector before its product with A; the
-        // second pass is the correction at the next step (or the last one)
+        // second pass is the correction at the next step (the last vector's
+        // is merged into the first +K vector's pass)
         if (j == 0 && (r = project_once())) return r;
         if ((r = append(more ? 1 : 0))) return r;
-        if ((r = dc_step(more))) return r;
+        if ((more || nprev == 0) && (r = dc_step(more))) return r;
       } else {
         if ((r = project(j == 0))) return r;
         if ((r = append(more ? 1 : 0))) return r;
@@ -892,9 +895,22 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       if (more) stt.precs += 1;
     }
     // ---- +K: previous Ritz vectors after the Krylov block ----
-    for (int j = 0; j < nprev; ++j) {
-      if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
-      if ((r = add_vector(PLUSK_DROP_TOL))) return r;
+    if (dc && nprev > 0) {
+      // each +K vector's single pass also corrects the pending column; the
+      // last appended vector is corrected at the end
+      for (int j = 0; j < nprev; ++j) {
+        if ((r = stage_reset(PLUSK_DROP_TOL))) return r;
+        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
+        if ((r = dc_step(true, true))) return r;
+        if ((r = append(0))) return r;
+      }
+      if ((r = dc_step(false, true))) return r;
+      nbh += nprev;
+    } else {
+      for (int j = 0; j < nprev; ++j) {
+        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
+        if ((r = add_vector(PLUSK_DROP_TOL))) return r;
+      }
     }
     HIPCHK(c, set_state(c->st, SET_SKIP, 0.0, 0, s));
     // previous vectors are taken from X before the Rayleigh-Ritz
