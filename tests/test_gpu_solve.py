@@ -258,3 +258,28 @@ def test_orth_option_rules(T):
     s = T.Solver(Q.A, None, p=2, m=16, k=4)
     assert s.solve(X0)["orth_delayed"] == 1
     s.close()
+
+
+@pytest.mark.parametrize("l,m,k", [(0, 24, 12), (2, 24, 12), (3, 28, 12), (1, 6, 4)])
+def test_delayed_form_plus_k_counts(T, l, m, k):
+    """The delayed form with no, one or several +K vectors, and with a single
+    Krylov vector per cycle (m = k + l + 1: the first inner vector is
+    corrected by the +K vector's pass): cycles, products and pairs match the
+    oracle."""
+    P = make("lap3d", "small", N=12, vmax=0.05, p=min(4, k), m=m, k=k, l=l)
+    print(f"delayed +K l={l} m={m} k={k} n={P.A.n}", flush=True)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, "jacobi", X0)
+    st, ev, X, res, conv = _gpu(T, P, "jacobi", X0)
+    assert st["orth_delayed"] == 1
+    _compare(P, st, ev, X, res, conv, ref)
+
+
+def test_delayed_form_mixed_precision(T):
+    """Float32 products in the delayed form: the float64 oracle's pairs."""
+    P = make("powerlaw", "small", n=3000, p=8, m=24, k=12)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, "jacobi", X0)
+    st, ev, X, res, conv = _gpu(T, P, "jacobi", X0, precision="mixed")
+    assert st["orth_delayed"] == 1 and st["fp32_cycles"] >= 1
+    _compare(P, st, ev, X, res, conv, ref, cycle_slack=10)
