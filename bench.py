@@ -174,7 +174,7 @@ def run_sweep(args, T, P, Ad, Bd, Xd, precond, precision, log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not "
+        print(json.dumps({"error": "this implementation runs on exactly one GPU; multi-GPU runs are not "
                                    "part of it (--gpus must be 1)"}))
         sys.exit(2)
     import torch

@@ -966,7 +966,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       if (kact <= 0) return set_err(c, TRPLK_EINVAL, "restart size exhausted by locking");
     }
     // a factor preconditioner that stops making progress hands over to
-    // Jacobi; the residuals (float64, true A and B) judge convergence
+    // Jacobi; the residuals (float64, true A and B) decide convergence
     if (window > 0 && c->prec >= TRPLK_PREC_FSAI) {
       const int target = hard ? c->u0 : t;
       const double rt = res.empty() ? 0.0 : res[hard ? 0 : std::min<int>(t, res.size() - 1)];
