@@ -79,15 +79,15 @@ enum { TRPLK_NORM_INF = 0, TRPLK_NORM_FRO = 1 };
  * new basis vector orthogonal to the basis to working accuracy with classical
  * Gram-Schmidt applied twice; they differ in when the second pass runs. */
 enum {
-  TRPLK_ORTH_AUTO = 0,    /* DELAYED where it applies (standard problem, soft locking,
-                             TRPL+K), CGS2 otherwise */
+  TRPLK_ORTH_AUTO = 0,    /* DELAYED where it applies (soft locking, TRPL+K), CGS2
+                             otherwise */
   TRPLK_ORTH_CGS2 = 1,    /* both passes before the vector is appended: three passes over
                              the basis per inner step */
   TRPLK_ORTH_DELAYED = 2  /* the second pass of vector j is merged with the first pass of
                              vector j + 1 (one dot pass and one update pass per inner step);
                              the T column and the stored products A U are corrected exactly
-                             from small matrices.  B = NULL and soft locking only (EINVAL
-                             otherwise) */
+                             from small matrices, B U in the update pass.  Soft locking only
+                             (EINVAL otherwise) */
 };
 
 typedef struct trplk_csr {

@@ -127,8 +127,11 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
     constexpr bool F = decltype(full)::value;
     const int base = sl * SLABP + lane;
     if constexpr (MODE == ORTH_DOT) {
-      // every load of the slab is issued before the first product
-      constexpr int NU = (NV == 2 && !SAME) ? 2 : 1;
+      // every load of the slab is issued before the first product.  Matrix of
+      // each vector: vec0 -> Md0; two vectors: vec1 -> Md1; three vectors:
+      // vec1 -> Md0, vec2 -> Md1
+      constexpr int NU = (NV >= 2 && !SAME) ? 2 : 1;
+      constexpr int M1 = NV == 3 ? 0 : NU - 1;
       d2 u[NU][CPW][RP];
 #pragma unroll
       for (int i = 0; i < CPW; ++i) {
@@ -160,12 +163,12 @@ __global__ __launch_bounds__(NWV * WAVE) void k_orth(const OrthArgs a) {
           acc[i][0] += u[0][i][r].x * vv[0][r].x;
           acc[i][0] += u[0][i][r].y * vv[0][r].y;
           if constexpr (NV >= 2) {
-            acc[i][1] += u[NU - 1][i][r].x * vv[1][r].x;
-            acc[i][1] += u[NU - 1][i][r].y * vv[1][r].y;
+            acc[i][1] += u[M1][i][r].x * vv[1][r].x;
+            acc[i][1] += u[M1][i][r].y * vv[1][r].y;
           }
           if constexpr (NV == 3) {
-            acc[i][2] += u[0][i][r].x * vv[2][r].x;
-            acc[i][2] += u[0][i][r].y * vv[2][r].y;
+            acc[i][2] += u[NU - 1][i][r].x * vv[2][r].x;
+            acc[i][2] += u[NU - 1][i][r].y * vv[2][r].y;
           }
         }
       }
@@ -323,17 +326,20 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
 }
 
 // Delayed step (one basis pass for two vectors).  The column j = nb - 1
-// holds u', a vector orthogonalised once and scaled to unit norm; c =
-// U(:, 0:j)^T u' and inv_gamma come from the previous dot pass.  Per row:
+// holds u', a vector orthogonalised once and scaled to unit (B-)norm; c =
+// U(:, 0:j)^T B u' and inv_gamma come from the previous dot pass.  Per row:
 //   u    = (u' - U(:, 0:j) c) inv_gamma      (written back to column j)
-//   wout = w - U(:, 0:j) h(0:j) - u h(j)     (when w is given, + ||wout||^2)
-// Columns 0..j-1 are read once for both sums; every lane reads the rows of
-// column j it writes, so the in-place update is safe.
-template <bool NT>
+//   B u  = (B u' - BU(:, 0:j) c) inv_gamma   (GEN: B != I, Md1 = B U)
+//   wout = w - U(:, 0:j) h(0:j) - u h(j)     (when w is given, + ||wout||^2
+//                                             for B = I)
+// Columns 0..j-1 are read once for all sums; every lane reads the rows of
+// column j it writes, so the in-place update is safe.  inv_gamma == 0 means
+// no column is pending (the finish found none): then j = nb and only w is
+// projected.
+template <bool NT, bool GEN>
 __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
   if (a.state->skip) return;
-  // inv_gamma == 0: no pending column (the finish found none); w is projected
-  // against the nb final columns only
+  constexpr int RPU = GEN ? 2 : UPD_RP;  // row pairs per lane (two matrices: fewer)
   const double ig = a.state->inv_gamma;
   const bool corr = ig != 0.0;
   const int j = a.ncol_fixed + a.state->nb - (corr ? 1 : 0);
@@ -352,7 +358,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
   const int64_t ld = a.ld;
   const int n = a.n;
   double* ucol = const_cast<double*>(a.Mu) + static_cast<int64_t>(j) * ld;
-  constexpr int TILEP = WAVE * UPD_RP;
+  double* bcol = GEN ? const_cast<double*>(a.Md1) + static_cast<int64_t>(j) * ld : nullptr;
+  constexpr int TILEP = WAVE * RPU;
   const int npair = (n + 1) / 2;
   const int ntile = (npair + TILEP - 1) / TILEP;
   const int nfull = n / (2 * TILEP);
@@ -360,42 +367,54 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
   auto tile_body = [&](int tile, auto full) {
     constexpr bool F = decltype(full)::value;
     const int base = tile * TILEP + lane;
-    d2 pu[UPD_RP], pw[UPD_RP];
+    d2 pu[RPU], pw[RPU], pb[RPU];
 #pragma unroll
-    for (int r = 0; r < UPD_RP; ++r) {
+    for (int r = 0; r < RPU; ++r) {
       pu[r] = d2{0.0, 0.0};
       pw[r] = d2{0.0, 0.0};
+      pb[r] = d2{0.0, 0.0};
     }
     int c = 0;
     for (; c + 4 <= j; c += 4) {
-      d2 u[4][UPD_RP];
+      d2 u[4][RPU], bq[GEN ? 4 : 1][RPU];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < UPD_RP; ++r)
+        for (int r = 0; r < RPU; ++r) {
           u[q][r] = ld_pair<F, NT>(a.Mu + (c + q) * ld, base + WAVE * r, n);
+          if constexpr (GEN) bq[q][r] = ld_pair<F, NT>(a.Md1 + (c + q) * ld, base + WAVE * r, n);
+        }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < UPD_RP; ++r) {
+        for (int r = 0; r < RPU; ++r) {
           pu[r].x += u[q][r].x * cs[c + q];
           pu[r].y += u[q][r].y * cs[c + q];
           pw[r].x += u[q][r].x * hs[c + q];
           pw[r].y += u[q][r].y * hs[c + q];
+          if constexpr (GEN) {
+            pb[r].x += bq[GEN ? q : 0][r].x * cs[c + q];
+            pb[r].y += bq[GEN ? q : 0][r].y * cs[c + q];
+          }
         }
     }
     for (; c < j; ++c) {
 #pragma unroll
-      for (int r = 0; r < UPD_RP; ++r) {
+      for (int r = 0; r < RPU; ++r) {
         const d2 u = ld_pair<F, NT>(a.Mu + c * ld, base + WAVE * r, n);
         pu[r].x += u.x * cs[c];
         pu[r].y += u.y * cs[c];
         pw[r].x += u.x * hs[c];
         pw[r].y += u.y * hs[c];
+        if constexpr (GEN) {
+          const d2 bu = ld_pair<F, NT>(a.Md1 + c * ld, base + WAVE * r, n);
+          pb[r].x += bu.x * cs[c];
+          pb[r].y += bu.y * cs[c];
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < UPD_RP; ++r) {
+    for (int r = 0; r < RPU; ++r) {
       const int p = base + WAVE * r;
       d2 un{0.0, 0.0};
       if (corr) {
@@ -403,6 +422,13 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
         un.x = (up.x - pu[r].x) * ig;
         un.y = (up.y - pu[r].y) * ig;
         st_pair<F>(ucol, p, n, un);
+        if constexpr (GEN) {
+          const d2 bp = ld_pair<F, false>(bcol, p, n);
+          d2 bn;
+          bn.x = (bp.x - pb[r].x) * ig;
+          bn.y = (bp.y - pb[r].y) * ig;
+          st_pair<F>(bcol, p, n, bn);
+        }
       }
       if (withw) {
         const d2 w = ld_pair<F, false>(a.w, p, n);
@@ -1063,19 +1089,33 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   }
   if (mode == ORTH_UPD2) {
     if (!a.state || !a.c || !a.Mu || (a.w && (!a.h || !a.wout))) return hipErrorInvalidValue;
-    if (nt) hipLaunchKernelGGL(k_upd2<true>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
-    else hipLaunchKernelGGL(k_upd2<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
+    const bool gen = a.Md1 != nullptr && a.Md1 != a.Mu;  // B U corrected too
+    if (gen && a.norm) return hipErrorInvalidValue;     // the B-norm needs a product with B
+    const dim3 g(nblk), b(UPD_THREADS);
+    if (gen) {
+      if (nt) hipLaunchKernelGGL((k_upd2<true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_upd2<false, true>), g, b, 0, s, a);
+    } else {
+      if (nt) hipLaunchKernelGGL((k_upd2<true, false>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_upd2<false, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
   }
   if (mode == ORTH_DOT && a.nvec == 3) {
+    // vec0, vec1 against Md0; vec2 against Md1 (B U for B != I)
     const dim3 g(nblk), b(16 * WAVE);
-    if ((need + 15) / 16 <= 4) {
-      if (nt) hipLaunchKernelGGL((k_orth<4, ORTH_DOT, 3, true, ORTH_RP, true, 16>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_orth<4, ORTH_DOT, 3, true, ORTH_RP, false, 16>), g, b, 0, s, a);
-    } else {
-      if (nt) hipLaunchKernelGGL((k_orth<8, ORTH_DOT, 3, true, ORTH_RP, true, 16>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_orth<8, ORTH_DOT, 3, true, ORTH_RP, false, 16>), g, b, 0, s, a);
-    }
+    const bool same = a.Md1 == nullptr || a.Md1 == a.Md0;
+    const bool narrow = (need + 15) / 16 <= 4;
+#define TRPLK_DOT3(CPWV, SAMEV)                                                          \
+  do {                                                                                   \
+    if (nt) hipLaunchKernelGGL((k_orth<CPWV, ORTH_DOT, 3, SAMEV, ORTH_RP, true, 16>), g, b, 0, s, a);  \
+    else hipLaunchKernelGGL((k_orth<CPWV, ORTH_DOT, 3, SAMEV, ORTH_RP, false, 16>), g, b, 0, s, a);    \
+  } while (0)
+    if (narrow && same) TRPLK_DOT3(4, true);
+    else if (narrow) TRPLK_DOT3(4, false);
+    else if (same) TRPLK_DOT3(8, true);
+    else TRPLK_DOT3(8, false);
+#undef TRPLK_DOT3
     return hipGetLastError();
   }
   return nt ? launch_width<true>(mode, a, need, nblk, s) : launch_width<false>(mode, a, need, nblk, s);

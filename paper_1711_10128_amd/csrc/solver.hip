@@ -393,7 +393,10 @@ struct Solver {
     const bool same = (mode == ORTH_DOT) ? (a.nvec == 1 || a.Md0 == a.Md1) : (a.Mu == a.Md1);
     if (mode == ORTH_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 8LL * n * a.nvec;
     else if (mode == ORTH_UPD_DOT) bytes = 8 * cols * n * (same ? 1 : 2) + 16LL * n;
-    else if (mode == ORTH_UPD2) bytes = 8 * (cols - 1) * n + (a.w ? 32LL : 16LL) * n;
+    else if (mode == ORTH_UPD2) {
+      const bool gen = a.Md1 && a.Md1 != a.Mu;  // B U corrected as well
+      bytes = 8 * (cols - 1) * n * (gen ? 2 : 1) + (gen ? 32LL : 16LL) * n + (a.w ? 16LL : 0LL) * n;
+    }
     else bytes = 8 * cols * n + 16LL * n;
     const int cls = mode == ORTH_DOT ? (a.nvec == 3 ? PC_DCDOT : PC_DOT)
                     : mode == ORTH_UPD_DOT ? PC_UPDDOT : mode == ORTH_UPD2 ? PC_DCUPD : PC_UPD;
@@ -537,13 +540,33 @@ struct Solver {
   // Delayed form, first inner vector: one Gram-Schmidt pass of w against
   // [Q | U] into wtmp with its norm; the second pass is merged into the
   // next dc_step.
+  // Norm of the once-orthogonalised vector in wtmp and its acceptance test
+  // (delayed form): the update pass left ||wtmp||^2 partials for B = I; for
+  // B != I one product B wtmp (kept in tmpB for the append) gives the B-norm.
+  void norm_finish(Status& S, int upd_mode) {
+    FinishArgs f;
+    f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial; f.dc = 1;
+    if (c->hasB) {
+      SpmvArgs b;
+      b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = c->wtmp;
+      b.mode = SPMV_DOT; b.state = c->st; b.y = c->tmpB; b.xd = c->wtmp; b.partial = c->partial;
+      S.check(spmv(c->B, b, false, PC_SPMV, 8LL * n), "spmv B");
+      f.nblk = spmv_partial_blocks(c->B.plan);
+      f.stride = 1;
+    } else {
+      f.nblk = nblk(upd_mode);
+      f.stride = orth_stride();
+    }
+    S.check(fin(f), "fin norm");
+  }
+
   int project_once() {
     Status S;
     const int ncf = c->u0;
     {
       OrthArgs a;
       a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
-      a.Md0 = Wq(); a.vec0 = c->w; a.nvec = 1; a.partial = c->partial;
+      a.Md0 = BWq(); a.vec0 = c->w; a.nvec = 1; a.partial = c->partial;
       S.check(orth(ORTH_DOT, a), "orth h");
       FinishArgs f;
       f.mode = FIN_H; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
@@ -555,22 +578,20 @@ struct Solver {
       a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.state = c->st; a.ncol_max = maxcols();
       a.Mu = Wq(); a.h = c->hbuf; a.w = c->w; a.wout = c->wtmp;
       a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
-      a.norm = true; a.partial = c->partial;
+      a.norm = !c->hasB; a.partial = c->partial;
       S.check(orth(ORTH_UPD, a), "orth upd");
     }
-    FinishArgs f;
-    f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
-    f.nblk = nblk(ORTH_UPD); f.stride = orth_stride(); f.dc = 1;
-    S.check(fin(f), "fin norm");
+    norm_finish(S, ORTH_UPD);
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
   // Delayed form, after the append of u' (column nb, once orthogonalised)
-  // with z' = A u' and, when `more`, the next direction w = M(z' - rho u'):
-  // one dot pass gives U^T [u', z', w]; the finish kernel turns them into
-  // the correction c, the exact T column of the corrected vector and the
-  // coefficients of w; one update pass writes u = (u' - U c) / gamma in
-  // place and the once-orthogonalised w into wtmp with its norm.
+  // with z' = A u', B u' and, when `more`, the next direction
+  // w = M(z' - rho B u'): one dot pass gives U^T B u', U^T z' and (B U)^T w;
+  // the finish kernel turns them into the correction c, the exact T column
+  // of the corrected vector and the coefficients of w; one update pass
+  // writes u = (u' - U c) / gamma (and B u) in place and the
+  // once-orthogonalised w into wtmp, whose (B-)norm follows.
   // plusk: the vector in c->w is a +K vector; the column at nb is corrected
   // only if it is pending (not after a breakdown of the Krylov block)
   int dc_step(bool more, bool plusk = false) {
@@ -580,7 +601,8 @@ struct Solver {
       OrthArgs a;
       a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.ncol_extra = 1; a.state = c->st;
       a.ncol_max = maxcols();
-      a.Md0 = Wq(); a.Md1 = Wq(); a.vec0_base = c->W; a.vec1_base = c->AW; a.vec0_col0 = ncf;
+      a.Md0 = Wq(); a.Md1 = BWq(); a.vec0_base = c->hasB ? c->BW : c->W; a.vec1_base = c->AW;
+      a.vec0_col0 = ncf;
       // three vectors also for the last column (the third, w, is then unused):
       // the finish reads the packed three-vector layout
       a.nvec = 3; a.vec2 = c->w; a.partial = c->partial;
@@ -595,19 +617,15 @@ struct Solver {
       OrthArgs a;
       a.n = n; a.ld = ld; a.ncol_fixed = ncf; a.ncol_extra = 1; a.state = c->st;
       a.ncol_max = maxcols();
-      a.Mu = Wq(); a.c = c->cbuf; a.h = c->hbuf; a.partial = c->partial;
+      a.Mu = Wq(); a.Md1 = c->hasB ? BWq() : nullptr; a.c = c->cbuf; a.h = c->hbuf;
+      a.partial = c->partial;
       if (more) {
         a.w = c->w; a.wout = c->wtmp; a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
-        a.norm = true;
+        a.norm = !c->hasB;
       }
       S.check(orth(ORTH_UPD2, a), "orth dc upd");
     }
-    if (more) {
-      FinishArgs f;
-      f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
-      f.nblk = nblk(ORTH_UPD2); f.stride = orth_stride(); f.dc = 1;
-      S.check(fin(f), "fin dc norm");
-    }
+    if (more) norm_finish(S, ORTH_UPD2);
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
@@ -826,7 +844,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   c->u0 = 0;
   c->solved = false;
   c->fp32_phase = (o.precision == TRPLK_MIXED);
-  dc = o.orth != TRPLK_ORTH_CGS2 && !c->hasB && !hard;
+  dc = o.orth != TRPLK_ORTH_CGS2 && !hard;
   stt.orth_delayed = dc ? 1 : 0;
   int r;
   HIPCHK(c, hipEventRecord(c->ev0, s));
@@ -1698,8 +1716,6 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
   std::string why;
   int r = check_opts(o, n, why);
   if (r) return set_err(nullptr, r, why);
-  if (B && o->method == TRPLK_METHOD_TRPLK && o->orth == TRPLK_ORTH_DELAYED)
-    return set_err(nullptr, TRPLK_EINVAL, "delayed orthogonalisation needs B = I");
   if (mem == TRPLK_MEM_HOST) {
     if ((r = validate_host_csr(A, n, why))) return set_err(nullptr, r, "A: " + why);
     if (B && (r = validate_host_csr(B, n, why))) return set_err(nullptr, r, "B: " + why);

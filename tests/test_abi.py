@@ -76,8 +76,4 @@ def test_orth_option_validation_without_gpu():
     o.p, o.k, o.m = 6, 4, 16                       # p > k: hard locking
     assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), None, ctypes.byref(o), 0, None) == -1
     assert b"soft locking" in L.trplk_last_error(None)
-    o.p = 2
-    assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), 0,
-                          None) == -1
-    assert b"B = I" in L.trplk_last_error(None)
     assert not ctx.value

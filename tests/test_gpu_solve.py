@@ -216,6 +216,8 @@ def test_breakdown_in_an_invariant_subspace(T, s, k, m, prec):
     ("lap3d", dict(N=16, vmax=0.05, p=10, m=40, k=20), "jacobi"),
     ("powerlaw", dict(n=3000, p=8, m=24, k=12), "jacobi"),
     ("lap3d", dict(N=14, vmax=0.05, p=6, m=24, k=12), "fsai"),
+    ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "jacobi"),
+    ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "fsai"),
 ])
 def test_delayed_and_cgs2_orthogonalisation_agree(T, name, kw, prec):
     """The inner vectors orthogonalised with both Gram-Schmidt passes before
@@ -238,18 +240,16 @@ def test_delayed_and_cgs2_orthogonalisation_agree(T, name, kw, prec):
 
 
 def test_orth_option_rules(T):
-    """AUTO picks the delayed form only for B = I with soft locking;
-    an explicit DELAYED request elsewhere is rejected."""
+    """AUTO picks the delayed form for soft locking (B = I or not); an
+    explicit DELAYED request with hard locking is rejected."""
     P = make("fem3d", "small", Ne=6, sigma=0.5, p=4, m=16, k=8)
-    with pytest.raises(T.TrplkError) as e:
-        T.Solver(P.A, P.B, p=4, m=16, k=8, orth="delayed")
-    assert e.value.code == -1
     Q = make("lap2d", "small", N=12)
-    with pytest.raises(T.TrplkError):
+    with pytest.raises(T.TrplkError) as e:
         T.Solver(Q.A, None, p=6, m=16, k=4, orth="delayed")     # hard locking
+    assert e.value.code == -1
     X0 = start_block(P.A.n, 8, 12)
     s = T.Solver(P.A, P.B, p=4, m=16, k=8)
-    assert s.solve(X0)["orth_delayed"] == 0                      # generalized: CGS2
+    assert s.solve(X0)["orth_delayed"] == 1                      # generalized, soft
     s.close()
     X0 = start_block(Q.A.n, 4, 12)
     s = T.Solver(Q.A, None, p=6, m=16, k=4)
