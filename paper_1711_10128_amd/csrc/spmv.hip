@@ -335,8 +335,8 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_stream(const SpmvArgs a) 
 // kernel; the number of lanes per row, G, is the largest power of two with
 // G * rows <= 64, chosen per block.
 template <typename VT, typename XT, typename AT, typename OT>
-__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_adapt(const SpmvArgs a, const int2* blocks,
-                                                             int nblocks) {
+__device__ __forceinline__ void spmv_adapt_body(const SpmvArgs& a, const int2* blocks, int nblocks,
+                                                int bid, int nbid) {
   EpiCtx e{1.0, 0.0, 0};
   if (a.state) {
     if (a.state->skip) return;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_adapt(const SpmvArgs a, c
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   double acc = 0.0;
-  for (int b = blockIdx.x * WPB + wv; b < nblocks; b += gridDim.x * WPB) {
+  for (int b = bid * WPB + wv; b < nblocks; b += nbid * WPB) {
     const int2 blk = blocks[b];
     const int r0 = blk.x;
     const int nr = blk.y - blk.x;  // 1..64
@@ -390,12 +390,12 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_adapt(const SpmvArgs a, c
     if (g == 0 && rl < nr) epilogue<OT>(a, e, r0 + rl, static_cast<double>(sum), acc);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
-  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, bid);
 }
 
 template <typename VT, typename XT, typename AT, typename OT>
-__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
-                                                            int slot0) {
+__device__ __forceinline__ void spmv_long_body(const SpmvArgs& a, const int* long_rows, int slot0,
+                                               int bid) {
   EpiCtx e{1.0, 0.0, 0};
   if (a.state) {
     if (a.state->skip) return;
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, co
     e.nb = a.state->nb;
     if (a.use_beta) e.s = a.state->inv_beta;
   }
-  const int row = long_rows[blockIdx.x];
+  const int row = long_rows[bid];
   const VT* __restrict__ val = static_cast<const VT*>(a.val);
   const XT* __restrict__ x = static_cast<const XT*>(a.x);
   const int beg = a.rowptr[row];
@@ -420,8 +420,28 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, co
     for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
     double acc = 0.0;
     epilogue<OT>(a, e, row, t, acc);
-    if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) a.partial[slot0 + blockIdx.x] = acc;
+    if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) a.partial[slot0 + bid] = acc;
   }
+}
+
+template <typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_long(const SpmvArgs a, const int* long_rows,
+                                                            int slot0) {
+  spmv_long_body<VT, XT, AT, OT>(a, long_rows, slot0, blockIdx.x);
+}
+
+// CSR-Adaptive blocks and the long rows in one launch: the first nlong
+// workgroups take one long row each (they start first, so a hub row does
+// not trail the launch), the rest step over the adaptive blocks.  Partial
+// slots: adaptive workgroup j -> j, long row i -> nadapt + i.
+template <typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_adapt_long(const SpmvArgs a,
+                                                                  const int2* blocks, int nblocks,
+                                                                  int nadapt, const int* long_rows,
+                                                                  int nlong) {
+  const int bid = blockIdx.x;
+  if (bid < nlong) spmv_long_body<VT, XT, AT, OT>(a, long_rows, nadapt, bid);
+  else spmv_adapt_body<VT, XT, AT, OT>(a, blocks, nblocks, bid - nlong, nadapt);
 }
 
 // Row lengths: long-row flags, the longest row and the fullest tile of
@@ -459,17 +479,11 @@ hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
   if (p.nblocks > 0 || p.adaptive) {
-    hipError_t e = hipSuccess;
-    if (p.nblocks > 0) {
-      hipLaunchKernelGGL((k_spmv_adapt<VT, XT, AT, OT>), grd, blk, 0, s, a, p.blocks, p.nblocks);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess && p.nlong > 0) {
-      hipLaunchKernelGGL((k_spmv_long<VT, XT, AT, OT>), dim3(p.nlong), blk, 0, s, a, p.long_rows,
-                         p.nblk_short);
-      e = hipGetLastError();
-    }
-    return e;
+    // with no adaptive blocks the adaptive workgroups find no work; their
+    // partial slots are still written (zero) for the dot epilogues
+    hipLaunchKernelGGL((k_spmv_adapt_long<VT, XT, AT, OT>), dim3(p.nlong + p.nblk_short), blk, 0, s,
+                       a, p.blocks, p.nblocks, p.nblk_short, p.long_rows, p.nlong);
+    return hipGetLastError();
   }
   if (p.kmax == 8) {
     switch (p.tile_rows) {
