@@ -79,15 +79,15 @@ enum { TRPLK_NORM_INF = 0, TRPLK_NORM_FRO = 1 };
  * new basis vector orthogonal to the basis to working accuracy with classical
  * Gram-Schmidt applied twice; they differ in when the second pass runs. */
 enum {
-  TRPLK_ORTH_AUTO = 0,    /* DELAYED where it applies (soft locking, TRPL+K), CGS2
-                             otherwise */
+  TRPLK_ORTH_AUTO = 0,    /* DELAYED for TRPL+K (PL+1 keeps CGS2) */
   TRPLK_ORTH_CGS2 = 1,    /* both passes before the vector is appended: three passes over
                              the basis per inner step */
   TRPLK_ORTH_DELAYED = 2  /* the second pass of vector j is merged with the first pass of
                              vector j + 1 (one dot pass and one update pass per inner step);
-                             the T column and the stored products A U are corrected exactly
-                             from small matrices, B U in the update pass.  Soft locking only
-                             (EINVAL otherwise) */
+                             the T column and the stored products A U are corrected from
+                             small matrices, B U in the update pass (with hard locking the
+                             terms U^T A Q c_Q, second order in the loss of orthogonality
+                             to the converged Q, are left out) */
 };
 
 typedef struct trplk_csr {

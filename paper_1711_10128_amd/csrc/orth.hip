@@ -728,51 +728,57 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
   }
 }
 
-// Finish of the delayed step (FIN_DC).  The pending column is j = nb: u' at
-// U(:, j), z' = A u' at AU(:, j); the three-vector dot pass left, per block,
-// a = U(:, 0:j+1)^T u', t = U^T z' and b = U^T w packed as [a | t | b] (j + 1
-// entries each, j + 1 <= 64).  With c = a(0:j) and gamma^2 = a_j - |c|^2 the
-// corrected column is u = (u' - U c) / gamma; A u = (z' - A U c) / gamma
-// gives, with T = U^T A U and A symmetric,
-//   T(i, j) = (t_i - (T c)_i) / gamma                 (i < j)
-//   T(j, j) = (t_j - 2 c.t + c.(T c)) / gamma^2
-// and the new direction's coefficients h(0:j) = b(0:j),
-// h(j) = (b_j - c.b) / gamma (nvec = 3; nvec = 2 ignores b).  A U(:, j) keeps
-// the stored z': the true products are AU_stored L with
-// L(:, j) = (e_j - L c) / gamma.
-// The block sums: lane l of wavefront w loads entries 2l, 2l + 1 (and
-// 128 + 2l, 129 + 2l) of blocks w, w + 16, ... with 16-byte loads, so one
-// load covers a block's three sums when 3 (j + 1) <= 128.
+// Finish of the delayed step (FIN_DC).  The pending column is j = nb of the
+// active basis, J = F + j in [Q U] (F locked columns): u' at U(:, j),
+// z' = A u' at AU(:, j); the three-vector dot pass left, per block,
+// a = [Q U](:, 0:J+1)^T B u', t = [Q U]^T z' and b = (B [Q U])^T w packed as
+// [a | t | b] (J + 1 <= 128 entries each).  With c = a(0:J) and
+// gamma^2 = a_J - |c|^2 the corrected column is u = (u' - [Q U] c) / gamma;
+// A u = (z' - A [Q U] c) / gamma gives, with T = U^T A U and A symmetric,
+//   T(i, j) = (t_{F+i} - (T c_U)_i) / gamma                 (i < j)
+//   T(j, j) = (t_J - 2 c.t + c_U.(T c_U)) / gamma^2
+// where c_U = c(F:J); the terms with U^T A Q c_Q and c_Q^T Q^T A Q c_Q are
+// left out: Q holds converged eigenvectors (U^T A Q ~ residual size) and
+// c_Q is the loss of orthogonality of one Gram-Schmidt pass, so they are
+// far below rounding of T.  The new direction's coefficients are
+// h(0:J) = b(0:J), h(J) = (b_J - c.b) / gamma (nvec = 3; nvec = 2 ignores
+// b).  A U(:, j) keeps the stored z': the true products are AU_stored L
+// with L(:, j) = (e_j - L c_U) / gamma.
+// The block sums: lane l of wavefront w loads entries 2l, 2l + 1 (+ 128 q,
+// q < SLOTS) of blocks w, w + 16, ... with 16-byte loads, so one load covers
+// a block's three sums when 3 (J + 1) <= 128.
+constexpr int DC_MAXE = 3 * ORTH_MAXCOL;  // packed entries per block row
 template <int SLOTS>
-__device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, double (*red)[3 * WAVE]) {
+__device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, double (*red)[DC_MAXE]) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
-  constexpr int U = 16 / SLOTS;  // blocks in flight per lane
+  constexpr int U = SLOTS == 1 ? 16 : SLOTS == 2 ? 8 : 4;  // blocks in flight per lane
   d2 t[SLOTS][U];
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q)
 #pragma unroll
     for (int u = 0; u < U; ++u) t[q][u] = d2{0.0, 0.0};
   const int64_t st = f.stride;
-  const bool on0 = 2 * lane < tot, on1 = 2 * lane + 2 * WAVE < tot;
+  bool on[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) on[q] = 2 * lane + 2 * WAVE * q < tot;
   int b = wv;
   auto ld = [&](int blk, int q) -> d2 {
     return *reinterpret_cast<const d2*>(f.partial + blk * st + 2 * lane + 2 * WAVE * q);
   };
   for (; b + (U - 1) * FIN_WAVES < f.nblk; b += U * FIN_WAVES) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (on0) t[0][u] += ld(b + u * FIN_WAVES, 0);
-      if (SLOTS == 2 && on1) t[SLOTS - 1][u] += ld(b + u * FIN_WAVES, 1);
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+        if (on[q]) t[q][u] += ld(b + u * FIN_WAVES, q);
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (b + u * FIN_WAVES < f.nblk) {
-      if (on0) t[0][u] += ld(b + u * FIN_WAVES, 0);
-      if (SLOTS == 2 && on1) t[SLOTS - 1][u] += ld(b + u * FIN_WAVES, 1);
-    }
-  }
+  for (int u = 0; u < U; ++u)
+    if (b + u * FIN_WAVES < f.nblk)
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+        if (on[q]) t[q][u] += ld(b + u * FIN_WAVES, q);
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
 #pragma unroll
@@ -780,10 +786,8 @@ __device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, doub
 #pragma unroll
       for (int u = 0; u < w; ++u) t[q][u] += t[q][u + w];
     const int e = 2 * lane + 2 * WAVE * q;
-    if (e < 3 * WAVE) {
-      red[wv][e] = t[q][0].x;
-      red[wv][e + 1] = t[q][0].y;
-    }
+    red[wv][e] = t[q][0].x;
+    red[wv][e + 1] = t[q][0].y;
   }
 }
 
@@ -792,23 +796,26 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   if (st->skip) return;
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int F = f.ncol_fixed;
   const int j = st->nb;
-  const int cnt = j + 1;
+  const int J = F + j;
+  const int cnt = J + 1;
   const int tot = 3 * cnt;
   const bool withw = f.nvec == 3;
   // f.dc: column j is corrected only when it is pending (after a breakdown
-  // nothing is: then only w is projected, against the j final columns)
+  // nothing is: then only w is projected, against the J final columns)
   const bool corr = !f.dc || st->pending;
-  __shared__ double red[FIN_WAVES][3 * WAVE];
-  __shared__ double s3[3 * WAVE];
+  __shared__ double red[FIN_WAVES][DC_MAXE];
+  __shared__ double s3[DC_MAXE];
   __shared__ double ys[WAVE];
   __shared__ double ls[WAVE];
   __shared__ double sc[4];
   if (tot <= 2 * WAVE) dc_block_sums<1>(f, tot, red);
-  else dc_block_sums<2>(f, tot, red);
+  else if (tot <= 4 * WAVE) dc_block_sums<2>(f, tot, red);
+  else dc_block_sums<3>(f, tot, red);
   if (!corr) {
     __syncthreads();
-    for (int e = tid; e < j; e += FIN_THREADS) {
+    for (int e = tid; e < J; e += FIN_THREADS) {
       double u = 0.0;
       for (int q = 0; q < FIN_WAVES; ++q) u += red[q][2 * cnt + e];
       s3[e] = u;
@@ -817,7 +824,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
     __syncthreads();
     if (tid < WAVE) {
       double hh = 0.0;
-      for (int k = tid; k < j; k += WAVE) hh += s3[k] * s3[k];
+      for (int k = tid; k < J; k += WAVE) hh += s3[k] * s3[k];
       hh = wave_sum(hh);
       if (tid == 0) {
         st->h1norm2 = hh;
@@ -826,8 +833,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
     }
     return;
   }
-  // T(0:j, 0:j) and L(0:j, 0:j) entries for T c and L c: lane i owns row i,
-  // wavefront w the columns w, w + 16, ...
+  // T(0:j, 0:j) and L(0:j, 0:j) entries for T c_U and L c_U: lane i owns
+  // row i, wavefront w the columns w, w + 16, ... (j <= 63)
   constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
   double tv[KQ], lv[KQ];
 #pragma unroll
@@ -847,14 +854,15 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   const double* a_ = s3;
   const double* t_ = s3 + cnt;
   const double* b_ = s3 + 2 * cnt;
+  const double* cu = a_ + F;  // c_U
   {
     double y = 0.0, l = 0.0;
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int k = wv + FIN_WAVES * q;
       if (lane < j && k < j) {
-        y += tv[q] * a_[k];
-        l += lv[q] * a_[k];
+        y += tv[q] * cu[k];
+        l += lv[q] * cu[k];
       }
     }
     red[wv][lane] = y;
@@ -869,18 +877,18 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   }
   if (tid < WAVE) {
     double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
-    for (int k = tid; k < j; k += WAVE) {
+    for (int k = tid; k < J; k += WAVE) {
       cc += a_[k] * a_[k];
       ct += a_[k] * t_[k];
-      cy += a_[k] * ys[k];
       if (withw) cb += a_[k] * b_[k];
     }
+    for (int k = tid; k < j; k += WAVE) cy += cu[k] * ys[k];
     cc = wave_sum(cc);
     ct = wave_sum(ct);
     cy = wave_sum(cy);
     cb = wave_sum(cb);
     if (tid == 0) {
-      const double g2 = a_[j] - cc;
+      const double g2 = a_[J] - cc;
       const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
       const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
       if (!ok) {
@@ -889,28 +897,30 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
       }
       st->inv_gamma = ig;
       sc[0] = ig;
-      sc[1] = (t_[j] - 2.0 * ct + cy) * ig * ig;
-      sc[2] = withw ? (b_[j] - cb) * ig : 0.0;
+      sc[1] = (t_[J] - 2.0 * ct + cy) * ig * ig;
+      sc[2] = withw ? (b_[J] - cb) * ig : 0.0;
     }
   }
   __syncthreads();
   const double ig = sc[0];
   for (int i = tid; i < j; i += FIN_THREADS) {
-    const double tij = (t_[i] - ys[i]) * ig;
+    const double tij = (t_[F + i] - ys[i]) * ig;
     f.T[i + static_cast<int64_t>(j) * f.ldT] = tij;
     f.T[j + static_cast<int64_t>(i) * f.ldT] = tij;
     f.L[i + static_cast<int64_t>(j) * f.ldT] = -ls[i] * ig;
-    f.cbuf[i] = a_[i];
-    if (withw) f.h[i] = b_[i];
+  }
+  for (int e = tid; e < J; e += FIN_THREADS) {
+    f.cbuf[e] = a_[e];
+    if (withw) f.h[e] = b_[e];
   }
   if (tid == 0) {
     f.T[j + static_cast<int64_t>(j) * f.ldT] = sc[1];
     f.L[j + static_cast<int64_t>(j) * f.ldT] = ig;
-    if (withw) f.h[j] = sc[2];
+    if (withw) f.h[J] = sc[2];
   }
   if (withw && tid < WAVE) {
     double hh = 0.0;
-    for (int k = tid; k < j; k += WAVE) hh += b_[k] * b_[k];
+    for (int k = tid; k < J; k += WAVE) hh += b_[k] * b_[k];
     hh = wave_sum(hh);
     if (tid == 0) st->h1norm2 = hh + sc[2] * sc[2];
   }

@@ -844,7 +844,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   c->u0 = 0;
   c->solved = false;
   c->fp32_phase = (o.precision == TRPLK_MIXED);
-  dc = o.orth != TRPLK_ORTH_CGS2 && !hard;
+  dc = o.orth != TRPLK_ORTH_CGS2;
   stt.orth_delayed = dc ? 1 : 0;
   int r;
   HIPCHK(c, hipEventRecord(c->ev0, s));
@@ -1700,7 +1700,6 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
   if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
   if (o->precision != TRPLK_FP64 && o->precision != TRPLK_MIXED) { why = "bad precision"; return TRPLK_EINVAL; }
   if (o->orth < TRPLK_ORTH_AUTO || o->orth > TRPLK_ORTH_DELAYED) { why = "bad orth"; return TRPLK_EINVAL; }
-  if (o->orth == TRPLK_ORTH_DELAYED && hard) { why = "delayed orthogonalisation needs soft locking"; return TRPLK_EINVAL; }
   if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
   return TRPLK_OK;
 }

@@ -218,6 +218,7 @@ def test_breakdown_in_an_invariant_subspace(T, s, k, m, prec):
     ("lap3d", dict(N=14, vmax=0.05, p=6, m=24, k=12), "fsai"),
     ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "jacobi"),
     ("fem3d", dict(Ne=10, sigma=0.5, p=8, m=24, k=12), "fsai"),
+    ("aniso3d", dict(N=10, sigma=1.0, p=12, m=16, k=8, tol=1e-9), "jacobi"),   # hard locking
 ])
 def test_delayed_and_cgs2_orthogonalisation_agree(T, name, kw, prec):
     """The inner vectors orthogonalised with both Gram-Schmidt passes before
@@ -240,20 +241,20 @@ def test_delayed_and_cgs2_orthogonalisation_agree(T, name, kw, prec):
 
 
 def test_orth_option_rules(T):
-    """AUTO picks the delayed form for soft locking (B = I or not); an
-    explicit DELAYED request with hard locking is rejected."""
+    """AUTO picks the delayed form for TRPL+K (B = I or not, soft or hard
+    locking); CGS2 on request."""
     P = make("fem3d", "small", Ne=6, sigma=0.5, p=4, m=16, k=8)
     Q = make("lap2d", "small", N=12)
-    with pytest.raises(T.TrplkError) as e:
-        T.Solver(Q.A, None, p=6, m=16, k=4, orth="delayed")     # hard locking
-    assert e.value.code == -1
     X0 = start_block(P.A.n, 8, 12)
     s = T.Solver(P.A, P.B, p=4, m=16, k=8)
     assert s.solve(X0)["orth_delayed"] == 1                      # generalized, soft
     s.close()
     X0 = start_block(Q.A.n, 4, 12)
     s = T.Solver(Q.A, None, p=6, m=16, k=4)
-    assert s.solve(X0)["orth_delayed"] == 0                      # hard locking: CGS2
+    assert s.solve(X0)["orth_delayed"] == 1                      # hard locking
+    s.close()
+    s = T.Solver(Q.A, None, p=6, m=16, k=4, orth="cgs2")
+    assert s.solve(X0)["orth_delayed"] == 0
     s.close()
     s = T.Solver(Q.A, None, p=2, m=16, k=4)
     assert s.solve(X0)["orth_delayed"] == 1
