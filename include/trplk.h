@@ -125,6 +125,9 @@ typedef struct trplk_opts {
                          [x_k, G_k, p_{k-1}] has at most m columns (Krylov block m - 2); the
                          start vector is the first column of x0; cycles = outer steps */
   int32_t orth;       /* TRPLK_ORTH_* (TRPL+K only; PL+1 always uses CGS2) */
+  double breakdown_tol; /* TRPL+K inner loop: stop the Krylov block when a new vector's
+                           (B-)norm squared is at most breakdown_tol^2 (|h|^2 + norm^2),
+                           h its Gram-Schmidt coefficients; 0 selects 1e-14, must be < 1 */
 } trplk_opts;
 
 typedef struct trplk_stats {

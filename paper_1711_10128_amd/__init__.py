@@ -49,7 +49,8 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("locking", ctypes.c_int32),
                 ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("orth", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("orth", ctypes.c_int32),
+                ("breakdown_tol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -189,7 +190,7 @@ class Solver:
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
                  profile=False, mixed_switch=0.0, fallback_window=0, method="trplk",
-                 orth="auto"):
+                 orth="auto", breakdown_tol=0.0):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -200,6 +201,7 @@ class Solver:
         o.fallback_window = fallback_window
         o.method = METHOD[method]
         o.orth = ORTH[orth]
+        o.breakdown_tol = breakdown_tol
         self.opts = o
         self.n = int(A.n)
         self.p = p

@@ -893,7 +893,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
     }
     // ---- inner preconditioned Krylov loop, eq. (3.1) ----
     const int m_in = m - kact - nprev;
-    if ((r = stage_reset(BREAKDOWN_TOL))) return r;
+    if ((r = stage_reset(o.breakdown_tol > 0 ? o.breakdown_tol : BREAKDOWN_TOL))) return r;
     if (dc) HIPCHK(c, set_identity(c->Lm, SYEV_MAXB, SYEV_MAXB, s));
     for (int j = 0; j < m_in; ++j) {
       const bool more = j < m_in - 1;
@@ -1666,6 +1666,7 @@ void trplk_default_opts(trplk_opts* o) {
   o->mixed_switch = 0.0;
   o->method = TRPLK_METHOD_TRPLK;
   o->orth = TRPLK_ORTH_AUTO;
+  o->breakdown_tol = 0.0;
 }
 
 static int check_opts(const trplk_opts* o, int n, std::string& why) {
@@ -1700,6 +1701,7 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
   if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
   if (o->precision != TRPLK_FP64 && o->precision != TRPLK_MIXED) { why = "bad precision"; return TRPLK_EINVAL; }
   if (o->orth < TRPLK_ORTH_AUTO || o->orth > TRPLK_ORTH_DELAYED) { why = "bad orth"; return TRPLK_EINVAL; }
+  if (!(o->breakdown_tol >= 0.0 && o->breakdown_tol < 1.0)) { why = "breakdown_tol must be in [0, 1)"; return TRPLK_EINVAL; }
   if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
   return TRPLK_OK;
 }

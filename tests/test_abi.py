@@ -67,9 +67,14 @@ def test_orth_option_validation_without_gpu():
                val.ctypes.data_as(ctypes.c_void_p))
     o = T._Opts()
     L.trplk_default_opts(ctypes.byref(o))
-    assert o.orth == T.ORTH["auto"]
+    assert o.orth == T.ORTH["auto"] and o.breakdown_tol == 0.0
     ctx = ctypes.c_void_p()
     o.orth = 3
     assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), None, ctypes.byref(o), 0, None) == -1
     assert b"orth" in L.trplk_last_error(None)
+    o.orth = 0
+    o.breakdown_tol = 1.0
+    assert L.trplk_create(ctypes.byref(ctx), ctypes.byref(A), None, ctypes.byref(o), 0, None) == -1
+    assert b"breakdown_tol" in L.trplk_last_error(None)
+    o.breakdown_tol = 0.0
     assert not ctx.value
