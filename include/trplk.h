@@ -117,7 +117,9 @@ typedef struct trplk_opts {
   int32_t fsai_cap;   /* FSAI: keep at most this many entries per row (diagonal included), 0 = no cap, max 64 */
   int32_t profile;    /* 1 = time the SpMV and orthogonalisation kernels with HIP events */
   double mixed_switch; /* MIXED: switch SpMV to float64 once all target residuals are below
-                          mixed_switch * ||A||; 0 selects the default 1e-3 */
+                          mixed_switch * ||A|| (or once they have not halved for 8 cycles:
+                          the float32 error floor can sit above the threshold); 0 selects
+                          the default 1e-3 */
   int32_t fallback_window; /* FSAI / FACTOR: when the target residual has not halved for this
                               many cycles, continue with Jacobi (M may change between cycles,
                               Sec. 3); 0 selects 50, negative disables */

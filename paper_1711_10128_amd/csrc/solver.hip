@@ -36,6 +36,7 @@ using namespace trplk;
 namespace {
 
 constexpr double BREAKDOWN_TOL = 1e-14;  // inner-step breakdown (relative)
+constexpr int MIXED_STALL_CYCLES = 8;    // float32 phase: cycles without halving the residual
 constexpr double PLUSK_DROP_TOL = 1e-12; // +K vector dropped when nearly dependent
 
 struct DevCsr {
@@ -836,6 +837,8 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   // float32 products carry errors of ~u32 ||A|| into T, large against a
   // clustered low spectrum, so the float32 phase ends early by default
   const double mixed_switch = (o.mixed_switch > 0 ? o.mixed_switch : 1e-3) * normA;
+  double fp32_best = 0.0;  // float32 phase: best worst-target residual, its cycle and target
+  int fp32_best_cycle = 0, fp32_target = -1;
   trplk_stats& stt = c->stats;
   stt = trplk_stats{};
   stt.normA = normA;
@@ -1000,12 +1003,21 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
         stt.fallback_cycle = cycle;
       }
     }
-    // mixed form: float64 SpMV once every target residual is small
+    // mixed form: float64 SpMV once every target residual is small, or once
+    // the float32 products stop the residual from falling (their error
+    // floor can sit above the switch threshold)
     if (c->fp32_phase) {
       double worst = 0.0;
       for (int i = t; i < std::min<int>(static_cast<int>(res.size()), hard ? 1 : p); ++i)
         worst = std::max(worst, res[i]);
-      if (worst <= mixed_switch) {
+      const int target = hard ? c->u0 : t;
+      if (target != fp32_target || worst < 0.5 * fp32_best) {
+        fp32_target = target;
+        fp32_best = worst;
+        fp32_best_cycle = cycle;
+      }
+      const bool stalled = cycle - fp32_best_cycle >= MIXED_STALL_CYCLES;
+      if (worst <= mixed_switch || stalled) {
         c->fp32_phase = false;
         stt.fp32_cycles = cycle;
         // theta on the device must hold the active values from index th_off

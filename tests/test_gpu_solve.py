@@ -303,3 +303,36 @@ def test_loose_breakdown_tolerance_still_converges(T, orth):
     assert np.all(res <= P.tol * ref.normA * 1.001)
     assert st["matvecs"] < P.k + (P.m - P.k) * st["cycles"]   # blocks did end early
     assert np.max(np.abs(X.T @ X - np.eye(X.shape[1]))) < 1e-10
+
+
+@pytest.mark.parametrize("name,kw,prec,extra,slack", [
+    ("fem3d", dict(Ne=8, sigma=0.5, p=10, m=18, k=6), "jacobi", {}, 2),              # B != I, hard
+    ("aniso3d", dict(N=10, sigma=1.0, p=12, m=16, k=8, l=0, tol=1e-9), "jacobi", {}, 2),  # hard, l = 0
+    ("fem3d", dict(Ne=16, sigma=0.5, p=8, m=24, k=12), "fsai", {"precision": "mixed"}, 10),
+    ("aniso3d", dict(N=10, sigma=1.0, p=12, m=16, k=8, tol=1e-9), "jacobi", {"precision": "mixed"}, 40),
+])
+def test_delayed_form_locking_and_precision_mix(T, name, kw, prec, extra, slack):
+    """The delayed form with B != I and hard locking, hard locking without
+    +K, and float32 products with B != I and with hard locking: the oracle's
+    pairs."""
+    P = make(name, "small", **kw)
+    print(f"mix {name} {kw} prec={prec} {extra} n={P.A.n}", flush=True)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, prec, X0)
+    st, ev, X, res, conv = _gpu(T, P, prec, X0, **extra)
+    assert st["orth_delayed"] == 1
+    _compare(P, st, ev, X, res, conv, ref, cycle_slack=slack)
+
+
+def test_mixed_form_switches_when_float32_stalls(T):
+    """On a coarse FEM pencil (B entries ~ h^3) the float32 products leave the
+    residual far above the switch threshold; the solve must notice the stall,
+    continue in float64 and converge to the float64 oracle's pairs."""
+    P = make("fem3d", "small", Ne=10, sigma=0.5, p=8, m=24, k=12)
+    X0 = start_block(P.A.n, P.k, 12)
+    ref = _oracle(P, "fsai", X0)
+    st, ev, X, res, conv = _gpu(T, P, "fsai", X0, precision="mixed", max_cycles=400)
+    print(f"  fp32 cycles {st['fp32_cycles']} of {st['cycles']} (oracle {ref.cycles})", flush=True)
+    assert st["fp32_cycles"] < st["cycles"]
+    assert conv.all()
+    assert np.all(np.abs(ev - ref.theta) <= 1e-10 * np.abs(ref.theta))
