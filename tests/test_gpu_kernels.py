@@ -146,6 +146,27 @@ def test_syev_clustered_and_diagonal(T):
     assert np.array_equal(th.cpu().numpy(), np.sort(d))
 
 
+@pytest.mark.parametrize("scale", [1e-200, 1e-30, 1e30, 1e200])
+def test_syev_any_magnitude(T, scale):
+    """The stopping test and the angles use entries scaled by a power of two,
+    so T * 2^k decomposes as T does (eigenvalues scale exactly, eigenvectors
+    are orthonormal to rounding) for magnitudes whose squares over- or
+    underflow."""
+    b = 40
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((b, b))
+    S = (M + M.T) * scale
+    th = torch.zeros(b, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((b, b), dtype=torch.float64, device="cuda")
+    T.syev(_dev(S.T.copy()), th, Y)
+    w = np.linalg.eigh(M + M.T)[0] * scale
+    got = th.cpu().numpy()
+    Yc = Y.cpu().numpy().T
+    nrm = np.linalg.norm(M + M.T, 2) * scale
+    assert np.max(np.abs(got - w)) <= 20 * b * 2.2e-16 * nrm
+    assert np.max(np.abs(Yc.T @ Yc - np.eye(b))) <= 20 * b * 2.2e-16
+
+
 @pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 123457])
 @pytest.mark.parametrize("b,k", [(4, 1), (8, 8), (20, 8), (40, 20), (48, 24), (64, 32), (64, 64)])
 def test_rotate_mfma_parity(T, n, b, k):
