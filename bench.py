@@ -53,7 +53,7 @@ KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients
                                "T column, coefficients of w)",
                 "orth_dc_upd": "k_upd2 (u = (u' - U c) / gamma; w -= U h; ||w||^2)",
                 "spmv": "k_spmv_stream / k_spmv_rows (SpMV + append epilogue)",
-                "prec": "k_spmv_stream / k_spmv_rows (factor apply G, G^T)",
+                "prec": "k_spmv_dia / k_spmv_stream / k_spmv_rows (factor apply G, G^T)",
                 "rot": "k_rotate (MFMA restart rotation)"}
 
 
@@ -295,7 +295,10 @@ def main():
     per_launch_bytes = d["bytes"] / d["launches"]
     avg_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES.get(dom, dom), "achieved": round(achieved, 1),
+    names = dict(KERNEL_NAMES)
+    if st["a_ndiag"]:
+        names["spmv"] = f"k_spmv_dia ({st['a_ndiag']} diagonals; SpMV + append epilogue)"
+    roofline = {"bound": "hbm", "kernel": names.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args, dom),
                 "bytes_per_launch": int(per_launch_bytes), "avg_launch_us": round(avg_ms * 1e3, 2)}
@@ -386,6 +389,8 @@ def main():
         "setup_ms": round(st["setup_ms"], 3),
         "max_resid_rel": float(np.max(res) / normA),
         "checks": checks,
+        "spmv_storage": (f"diagonals ({st['a_ndiag']})" if st["a_ndiag"] else "csr")
+                        + (f", B: diagonals ({st['b_ndiag']})" if st["b_ndiag"] else ""),
         "roofline": roofline,
         "spmv_roofline": spmv_roof,
         "kernel_classes": {k: {kk: (round(v, 3) if isinstance(v, float) else v)

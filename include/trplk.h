@@ -157,6 +157,10 @@ typedef struct trplk_stats {
      (correction, T column, coefficients of the new direction), [4] DELAYED
      correction + update */
   double pass_ms[5];   int64_t pass_launches[5];  int64_t pass_bytes[5];
+  /* storage the products with A and B use: the number of diagonals when
+     the matrix is held by diagonals (at most 32 distinct column offsets and
+     at most 85% of the CSR bytes per product), 0 for CSR */
+  int32_t a_ndiag;     int32_t b_ndiag;
 } trplk_stats;
 
 typedef struct trplk_ctx trplk_ctx;

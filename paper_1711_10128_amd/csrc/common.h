@@ -19,6 +19,7 @@ struct DevState {
   int skip;        // nonzero: step kernels of the current stage return at once
   int bad;         // nonzero: a B-norm squared <= 0 or a non-finite value was seen
   int pending;     // delayed form: column nb holds a vector awaiting its correction
+  int arrive;      // workgroups of the running pass that are done (last-workgroup finish); 0 between passes
   double beta2;    // B-norm squared of the vector being appended
   double inv_beta; // 1 / sqrt(beta2)
   double h1norm2;  // squared norm of the first Gram-Schmidt coefficients
@@ -119,7 +120,18 @@ struct SpmvPlan {
   bool adaptive = false;    // CSR-Adaptive blocks (+ long rows) for irregular matrices
   int nblocks = 0;          // adaptive blocks
   int2* blocks = nullptr;   // device [first row, end row) per block
+  // diagonal storage (set by spmv_plan_dia when every entry lies on one of
+  // at most DIA_MAXD diagonals and the format moves fewer bytes than CSR):
+  // value of diagonal d at row i in dia_val[d * n + i] (0 where the
+  // diagonal leaves the matrix or the pattern has no entry); offsets
+  // ascending.  When ndiag > 0 the launches use these values, not the CSR.
+  int ndiag = 0;
+  int* dia_off = nullptr;       // device, ndiag column offsets (col - row)
+  double* dia_val = nullptr;    // device, ndiag * n (float64 products)
+  float* dia_val32 = nullptr;   // device, ndiag * n (float32 products)
+  int nblk_dia = 0;             // grid of the diagonal kernel
 };
+constexpr int DIA_MAXD = 32;
 constexpr int ADAPT_MAXNNZ = 512;  // entries per adaptive block (LDS per wavefront)
 constexpr int LONG_ROW = 256;
 
@@ -127,6 +139,16 @@ int pick_lanes(double mean_len);
 // Builds the plan (row-length binning) for a device CSR; allocates the long
 // row list on the device.
 hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hipStream_t s);
+// Adds diagonal storage to a plan when the pattern qualifies (see
+// SpmvPlan): the column pattern is inspected on the host, the values are
+// scattered on the device from val64 and/or val32 (either may be null; the
+// matching precision is then unavailable, and a launch in it fails).
+// Must be called again whenever the CSR values change.
+hipError_t spmv_plan_dia(SpmvPlan& plan, int n, const int* rowptr_dev, const int* col_dev,
+                         const double* val64, const float* val32, hipStream_t s);
+// Bytes one product reads and writes for the matrix itself (values, and
+// indices for CSR) in the format the plan launches.
+int64_t spmv_matrix_bytes(const SpmvPlan& plan, int64_t nnz, bool f32);
 void spmv_plan_free(SpmvPlan& plan);
 // Number of blocks a SPMV_DOT / SPMV_RESID launch writes partials for.
 int spmv_partial_blocks(const SpmvPlan& plan);
@@ -168,6 +190,11 @@ struct OrthArgs {
   double* partial = nullptr;    // [nblk][stride]
   int nvec = 1;                 // ORTH_DOT: 1, 2 or 3
   const double* c = nullptr;    // ORTH_UPD2: correction coefficients of the pending column
+  // ORTH_UPD / ORTH_UPD2 with norm: the last workgroup to finish sums the
+  // partials and takes the acceptance decision of FIN_NORM (needs state);
+  // norm_dc is FIN_NORM's dc flag
+  int fuse_norm = 0;
+  int norm_dc = 0;
 };
 
 constexpr int ORTH_MAXCOL = 128;

@@ -85,6 +85,94 @@ __device__ __forceinline__ double pair_sq(int p, int n, d2 v) {
 using Full = std::integral_constant<bool, true>;
 using Part = std::integral_constant<bool, false>;
 
+// Acceptance of the vector just orthogonalised, from its squared (B-)norm
+// b2: a breakdown (b2 not above tol2 relative to the squared norm before
+// the pass) or a non-finite value drops it; otherwise 1 / sqrt(b2) scales
+// the append, and in the delayed form the appended column awaits its
+// correction.
+__device__ __forceinline__ void norm_accept(DevState* st, double b2, int dc, double tol2,
+                                            double h1norm2) {
+  st->beta2 = b2;
+  st->cnt_norm += 1;
+  const bool finite = (b2 == b2) && (b2 < 1.0e308);
+  if (!finite) st->bad = 1;
+  if (!(b2 > tol2 * (h1norm2 + b2)) || !finite) {
+    st->skip = 1;  // breakdown / dropped vector: nothing is appended
+  } else {
+    st->inv_beta = 1.0 / sqrt(b2);
+    if (dc) st->pending = 1;
+  }
+}
+
+// Last-workgroup detection for a finish fused into a pass.  Each workgroup
+// publishes its one partial with a device-scope atomic store (written
+// through to the device-coherent level, so no writeback of the cached
+// output of the pass is needed: a device-scope release fence would write
+// back the whole L2 of every XCD, once per workgroup), waits for that store
+// to be acknowledged, and counts itself in; the workgroup that completes the count resets the
+// counter for the next pass and reads the partials with device-scope atomic
+// loads.  No workgroup waits for another.
+__device__ __forceinline__ void publish_partial(double* dst, double v) {
+  __hip_atomic_store(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double read_partial(const double* src) {
+  return __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// called by every thread after thread 0 published the workgroup's partial
+__device__ __forceinline__ bool last_workgroup(int* counter) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    // wait until the publishing store is acknowledged (s_waitcnt with every
+    // counter at zero); the signal fences keep the compiler from moving the
+    // store or the count across the wait
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == static_cast<int>(gridDim.x) - 1;
+    if (last) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return last;
+}
+
+// Squared norm of the pass output from the per-workgroup partials (stride
+// STRIDE), summed in workgroup order by the last workgroup (NTH threads),
+// then the acceptance decision.
+template <int NTH>
+__device__ __forceinline__ void norm_tail(const OrthArgs& a, double* red) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int nblk = static_cast<int>(gridDim.x);
+  // the state the decision needs, loaded alongside the partials
+  const DevState* st = a.state;
+  const double tol2 = threadIdx.x == 0 ? st->tol2 : 0.0;
+  const double h1 = threadIdx.x == 0 ? st->h1norm2 : 0.0;
+  constexpr int U = 8;  // loads in flight per thread, summed in a fixed order
+  double t = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += U * NTH) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * NTH;
+      v[u] = b < nblk ? read_partial(a.partial + static_cast<int64_t>(b) * STRIDE) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+  }
+  t = wave_sum(t);
+  __syncthreads();
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b2 = 0.0;
+    for (int q = 0; q < NTH / WAVE; ++q) b2 += red[q];
+    norm_accept(const_cast<DevState*>(st), b2, a.norm_dc, tol2, h1);
+  }
+}
+
 // MODE ORTH_DOT: acc[i][v] = (column c of Md_v) . vec_v over the block's
 // slabs.  MODE ORTH_UPD_DOT: w <- w - Mu h, then acc[i][0] = Md1(:,c) . w.
 // NWV wavefronts per workgroup, wavefront w owning columns w + NWV * i.
@@ -320,8 +408,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd(const OrthArgs a) {
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int q = 0; q < UPD_THREADS / WAVE; ++q) t += red[q];
-      a.partial[static_cast<int64_t>(blockIdx.x) * STRIDE] = t;
+      double* dst = a.partial + static_cast<int64_t>(blockIdx.x) * STRIDE;
+      if (a.fuse_norm) publish_partial(dst, t);
+      else *dst = t;
     }
+    if (a.fuse_norm && last_workgroup(&const_cast<DevState*>(a.state)->arrive))
+      norm_tail<UPD_THREADS>(a, red);
   }
 }
 
@@ -453,8 +545,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int q = 0; q < UPD_THREADS / WAVE; ++q) t += red[q];
-      a.partial[static_cast<int64_t>(blockIdx.x) * STRIDE] = t;
+      double* dst = a.partial + static_cast<int64_t>(blockIdx.x) * STRIDE;
+      if (a.fuse_norm) publish_partial(dst, t);
+      else *dst = t;
     }
+    if (a.fuse_norm && last_workgroup(&const_cast<DevState*>(a.state)->arrive))
+      norm_tail<UPD_THREADS>(a, red);
   }
 }
 
@@ -700,20 +796,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
       break;
     }
     case FIN_NORM: {
-      const double b2s = fin_one(f, 0, red);
-      if (tid == 0) {
-        const double b2 = b2s;
-        st->beta2 = b2;
-        st->cnt_norm += 1;
-        const bool finite = (b2 == b2) && (b2 < 1.0e308);
-        if (!finite) st->bad = 1;
-        if (!(b2 > st->tol2 * (st->h1norm2 + b2)) || !finite) {
-          st->skip = 1;  // breakdown / dropped vector: nothing is appended
-        } else {
-          st->inv_beta = 1.0 / sqrt(b2);
-          if (f.dc) st->pending = 1;
-        }
-      }
+      const double b2 = fin_one(f, 0, red);
+      if (tid == 0) norm_accept(st, b2, f.dc, st->tol2, st->h1norm2);
       break;
     }
     default: {
@@ -746,10 +830,12 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(const FinishArgs f) {
 // with L(:, j) = (e_j - L c_U) / gamma.
 // The block sums: lane l of wavefront w loads entries 2l, 2l + 1 (+ 128 q,
 // q < SLOTS) of blocks w, w + 16, ... with 16-byte loads, so one load covers
-// a block's three sums when 3 (J + 1) <= 128.
+// a block's three sums when 3 (J + 1) <= 128.  The row width loaded is the
+// host's bound f.cnt on 3 (J + 1), so the loads need not wait for the
+// state; entries past 3 (J + 1) are summed but never used.
 constexpr int DC_MAXE = 3 * ORTH_MAXCOL;  // packed entries per block row
 template <int SLOTS>
-__device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, double (*red)[DC_MAXE]) {
+__device__ __forceinline__ void dc_block_sums(const FinishArgs& f, double (*red)[DC_MAXE]) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   constexpr int U = SLOTS == 1 ? 16 : SLOTS == 2 ? 8 : 4;  // blocks in flight per lane
@@ -759,9 +845,10 @@ __device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, doub
 #pragma unroll
     for (int u = 0; u < U; ++u) t[q][u] = d2{0.0, 0.0};
   const int64_t st = f.stride;
+  const int width = min(f.cnt, DC_MAXE);
   bool on[SLOTS];
 #pragma unroll
-  for (int q = 0; q < SLOTS; ++q) on[q] = 2 * lane + 2 * WAVE * q < tot;
+  for (int q = 0; q < SLOTS; ++q) on[q] = 2 * lane + 2 * WAVE * q < width;
   int b = wv;
   auto ld = [&](int blk, int q) -> d2 {
     return *reinterpret_cast<const d2*>(f.partial + blk * st + 2 * lane + 2 * WAVE * q);
@@ -793,9 +880,25 @@ __device__ __forceinline__ void dc_block_sums(const FinishArgs& f, int tot, doub
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   DevState* st = f.state;
-  if (st->skip) return;
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1), wv = tid / WAVE;
+  __shared__ double red[FIN_WAVES][DC_MAXE];
+  __shared__ double s3[DC_MAXE];
+  if (f.cnt <= 2 * WAVE) dc_block_sums<1>(f, red);
+  else if (f.cnt <= 4 * WAVE) dc_block_sums<2>(f, red);
+  else dc_block_sums<3>(f, red);
+  // T(0:j, 0:j) and L(0:j, 0:j) entries for T c_U and L c_U: lane i owns
+  // row i, wavefront w the columns w, w + 16, ... (j <= 63).  Loaded over
+  // the whole 64 x 64 array before the state is known, masked below.
+  constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
+  double tv[KQ], lv[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int k = wv + FIN_WAVES * q;
+    tv[q] = f.T[lane + static_cast<int64_t>(k) * f.ldT];
+    lv[q] = f.L[lane + static_cast<int64_t>(k) * f.ldT];
+  }
+  if (st->skip) return;
   const int F = f.ncol_fixed;
   const int j = st->nb;
   const int J = F + j;
@@ -805,14 +908,6 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
   // f.dc: column j is corrected only when it is pending (after a breakdown
   // nothing is: then only w is projected, against the J final columns)
   const bool corr = !f.dc || st->pending;
-  __shared__ double red[FIN_WAVES][DC_MAXE];
-  __shared__ double s3[DC_MAXE];
-  __shared__ double ys[WAVE];
-  __shared__ double ls[WAVE];
-  __shared__ double sc[4];
-  if (tot <= 2 * WAVE) dc_block_sums<1>(f, tot, red);
-  else if (tot <= 4 * WAVE) dc_block_sums<2>(f, tot, red);
-  else dc_block_sums<3>(f, tot, red);
   if (!corr) {
     __syncthreads();
     for (int e = tid; e < J; e += FIN_THREADS) {
@@ -832,17 +927,6 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
       }
     }
     return;
-  }
-  // T(0:j, 0:j) and L(0:j, 0:j) entries for T c_U and L c_U: lane i owns
-  // row i, wavefront w the columns w, w + 16, ... (j <= 63)
-  constexpr int KQ = (WAVE + FIN_WAVES - 1) / FIN_WAVES;
-  double tv[KQ], lv[KQ];
-#pragma unroll
-  for (int q = 0; q < KQ; ++q) {
-    const int k = wv + FIN_WAVES * q;
-    const bool on = lane < j && k < j;
-    tv[q] = on ? f.T[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
-    lv[q] = on ? f.L[lane + static_cast<int64_t>(k) * f.ldT] : 0.0;
   }
   __syncthreads();
   for (int e = tid; e < tot; e += FIN_THREADS) {
@@ -867,65 +951,59 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish_dc(const FinishArgs f) {
     }
     red[wv][lane] = y;
     red[wv][WAVE + lane] = l;
-    __syncthreads();
-    if (wv < 2 && lane < j) {
-      double u = 0.0;
-      for (int q = 0; q < FIN_WAVES; ++q) u += red[q][WAVE * wv + lane];
-      (wv == 0 ? ys : ls)[lane] = u;
-    }
-    __syncthreads();
-  }
-  if (tid < WAVE) {
-    double cc = 0.0, ct = 0.0, cy = 0.0, cb = 0.0;
-    for (int k = tid; k < J; k += WAVE) {
-      cc += a_[k] * a_[k];
-      ct += a_[k] * t_[k];
-      if (withw) cb += a_[k] * b_[k];
-    }
-    for (int k = tid; k < j; k += WAVE) cy += cu[k] * ys[k];
-    cc = wave_sum(cc);
-    ct = wave_sum(ct);
-    cy = wave_sum(cy);
-    cb = wave_sum(cb);
-    if (tid == 0) {
-      const double g2 = a_[J] - cc;
-      const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
-      const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
-      if (!ok) {
-        st->bad = 1;
-        st->skip = 1;
-      }
-      st->inv_gamma = ig;
-      sc[0] = ig;
-      sc[1] = (t_[J] - 2.0 * ct + cy) * ig * ig;
-      sc[2] = withw ? (b_[J] - cb) * ig : 0.0;
-    }
   }
   __syncthreads();
-  const double ig = sc[0];
-  for (int i = tid; i < j; i += FIN_THREADS) {
-    const double tij = (t_[F + i] - ys[i]) * ig;
-    f.T[i + static_cast<int64_t>(j) * f.ldT] = tij;
-    f.T[j + static_cast<int64_t>(i) * f.ldT] = tij;
-    f.L[i + static_cast<int64_t>(j) * f.ldT] = -ls[i] * ig;
+  if (wv != 0) return;
+  // the first wavefront finishes alone: lane i holds (T c_U)_i and (L c_U)_i,
+  // and every lane gets each dot product from the shuffle reduction
+  double ys = 0.0, ls = 0.0;
+  if (lane < j) {
+    for (int q = 0; q < FIN_WAVES; ++q) {
+      ys += red[q][lane];
+      ls += red[q][WAVE + lane];
+    }
   }
-  for (int e = tid; e < J; e += FIN_THREADS) {
+  double cc = 0.0, ct = 0.0, cb = 0.0, bb = 0.0;
+  for (int k = lane; k < J; k += WAVE) {
+    cc += a_[k] * a_[k];
+    ct += a_[k] * t_[k];
+    if (withw) {
+      cb += a_[k] * b_[k];
+      bb += b_[k] * b_[k];
+    }
+  }
+  double cy = lane < j ? cu[lane] * ys : 0.0;
+  cc = wave_sum(cc);
+  ct = wave_sum(ct);
+  cy = wave_sum(cy);
+  cb = wave_sum(cb);
+  bb = wave_sum(bb);
+  const double g2 = a_[J] - cc;
+  const bool ok = (g2 > 0.0) && (g2 < 1.0e308);
+  const double ig = ok ? 1.0 / sqrt(g2) : 0.0;
+  if (lane < j) {
+    const double tij = (t_[F + lane] - ys) * ig;
+    f.T[lane + static_cast<int64_t>(j) * f.ldT] = tij;
+    f.T[j + static_cast<int64_t>(lane) * f.ldT] = tij;
+    f.L[lane + static_cast<int64_t>(j) * f.ldT] = -ls * ig;
+  }
+  for (int e = lane; e < J; e += WAVE) {
     f.cbuf[e] = a_[e];
     if (withw) f.h[e] = b_[e];
   }
-  if (tid == 0) {
-    f.T[j + static_cast<int64_t>(j) * f.ldT] = sc[1];
+  if (lane == 0) {
+    if (!ok) {
+      st->bad = 1;
+      st->skip = 1;
+    }
+    st->inv_gamma = ig;
+    f.T[j + static_cast<int64_t>(j) * f.ldT] = (t_[J] - 2.0 * ct + cy) * ig * ig;
     f.L[j + static_cast<int64_t>(j) * f.ldT] = ig;
-    if (withw) f.h[J] = sc[2];
-  }
-  if (withw && tid < WAVE) {
-    double hh = 0.0;
-    for (int k = tid; k < J; k += WAVE) hh += b_[k] * b_[k];
-    hh = wave_sum(hh);
-    if (tid == 0) st->h1norm2 = hh + sc[2] * sc[2];
-  }
-  __syncthreads();
-  if (tid == 0) {
+    if (withw) {
+      const double hj = (b_[J] - cb) * ig;
+      f.h[J] = hj;
+      st->h1norm2 = bb + hj * hj;
+    }
     st->nb = j + 1;
     st->cnt_append += 1;
     st->pending = 0;
@@ -1092,6 +1170,8 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
   // 16-byte row-pair loads: every column and vector must start 16-byte aligned
   if (a.ld % 2 != 0) return hipErrorInvalidValue;
   const bool nt = static_cast<int64_t>(need) * a.n * 8 >= g_orth_nt_bytes;
+  if (a.fuse_norm && (!a.state || !a.norm || (mode != ORTH_UPD && mode != ORTH_UPD2)))
+    return hipErrorInvalidValue;
   if (mode == ORTH_UPD) {
     if (nt) hipLaunchKernelGGL(k_upd<true>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
     else hipLaunchKernelGGL(k_upd<false>, dim3(nblk), dim3(UPD_THREADS), 0, s, a);
@@ -1134,6 +1214,7 @@ hipError_t orth_pass(int mode, const OrthArgs& a, int nblk, hipStream_t s) {
 hipError_t finish(const FinishArgs& f, hipStream_t s) {
   if (f.mode == FIN_DC) {
     if (!f.state || !f.T || !f.L || !f.cbuf || (f.nvec == 3 && !f.h)) return hipErrorInvalidValue;
+    if (f.cnt < 3 || f.cnt > DC_MAXE || f.stride < f.cnt || f.ldT != SYEV_MAXB) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_finish_dc, dim3(1), dim3(FIN_THREADS), 0, s, f);
     return hipGetLastError();
   }

@@ -237,6 +237,10 @@ int validate_host_csr(const trplk_csr* M, int n, std::string& why) {
   return TRPLK_OK;
 }
 
+int64_t dia_bytes(const SpmvPlan& p) {
+  return static_cast<int64_t>(p.ndiag) * p.n * ((p.dia_val ? 8 : 0) + (p.dia_val32 ? 4 : 0));
+}
+
 int upload_csr(trplk_ctx* c, DevCsr& D, const trplk_csr* M, int32_t mem, bool want32) {
   D.n = M->n;
   D.nnz = M->nnz;
@@ -259,6 +263,8 @@ int upload_csr(trplk_ctx* c, DevCsr& D, const trplk_csr* M, int32_t mem, bool wa
     HIPCHK(c, cast_f32(D.nnz, D.val, D.val32, c->s));
   }
   HIPCHK(c, spmv_plan(D.plan, D.n, D.rowptr, 0, c->s));
+  HIPCHK(c, spmv_plan_dia(D.plan, D.n, D.rowptr, D.col, D.val, D.val32, c->s));
+  c->dev_bytes += dia_bytes(D.plan);
   return TRPLK_OK;
 }
 
@@ -383,9 +389,10 @@ struct Solver {
   double* Wq() const { return c->W; }              // [Q | U] start
   double* BWq() const { return c->hasB ? c->BW : c->W; }
 
+  // matrix (in the format launched) + x read + y written
   int64_t spmv_bytes(const DevCsr& M, bool f32) const {
     const int64_t vb = f32 ? 4 : 8;
-    return M.nnz * (vb + 4) + 4 * (static_cast<int64_t>(M.n) + 1) + 2 * vb * M.n;
+    return spmv_matrix_bytes(M.plan, M.nnz, f32) + 2 * vb * M.n;
   }
 
   hipError_t orth(int mode, const OrthArgs& a) {
@@ -450,22 +457,20 @@ struct Solver {
       a.Mu = Wq(); a.h = c->hbuf; a.w = c->w; a.wout = c->wtmp;
       a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
       a.norm = !c->hasB; a.partial = c->partial;
+      a.fuse_norm = a.norm;  // B = I: the pass's last workgroup takes the decision
       S.check(orth(ORTH_UPD, a), "orth upd");
     }
-    FinishArgs f;
-    f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
     if (c->hasB) {
+      FinishArgs f;
+      f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial;
       SpmvArgs b;
       b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = c->wtmp;
       b.mode = SPMV_DOT; b.state = c->st; b.y = c->tmpB; b.xd = c->wtmp; b.partial = c->partial;
       S.check(spmv(c->B, b, false, PC_SPMV, 8LL * n), "spmv B");
       f.nblk = spmv_partial_blocks(c->B.plan);
       f.stride = 1;
-    } else {
-      f.nblk = nblk(ORTH_UPD);
-      f.stride = orth_stride();
+      S.check(fin(f), "fin norm");
     }
-    S.check(fin(f), "fin norm");
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
@@ -542,22 +547,19 @@ struct Solver {
   // [Q | U] into wtmp with its norm; the second pass is merged into the
   // next dc_step.
   // Norm of the once-orthogonalised vector in wtmp and its acceptance test
-  // (delayed form): the update pass left ||wtmp||^2 partials for B = I; for
-  // B != I one product B wtmp (kept in tmpB for the append) gives the B-norm.
-  void norm_finish(Status& S, int upd_mode) {
+  // (delayed form).  For B = I the update pass left ||wtmp||^2 partials and
+  // its last workgroup took the decision (fuse_norm); for B != I one product
+  // B wtmp (kept in tmpB for the append) gives the B-norm.
+  void norm_finish(Status& S) {
+    if (!c->hasB) return;
     FinishArgs f;
     f.mode = FIN_NORM; f.state = c->st; f.partial = c->partial; f.dc = 1;
-    if (c->hasB) {
-      SpmvArgs b;
-      b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = c->wtmp;
-      b.mode = SPMV_DOT; b.state = c->st; b.y = c->tmpB; b.xd = c->wtmp; b.partial = c->partial;
-      S.check(spmv(c->B, b, false, PC_SPMV, 8LL * n), "spmv B");
-      f.nblk = spmv_partial_blocks(c->B.plan);
-      f.stride = 1;
-    } else {
-      f.nblk = nblk(upd_mode);
-      f.stride = orth_stride();
-    }
+    SpmvArgs b;
+    b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = c->wtmp;
+    b.mode = SPMV_DOT; b.state = c->st; b.y = c->tmpB; b.xd = c->wtmp; b.partial = c->partial;
+    S.check(spmv(c->B, b, false, PC_SPMV, 8LL * n), "spmv B");
+    f.nblk = spmv_partial_blocks(c->B.plan);
+    f.stride = 1;
     S.check(fin(f), "fin norm");
   }
 
@@ -580,9 +582,10 @@ struct Solver {
       a.Mu = Wq(); a.h = c->hbuf; a.w = c->w; a.wout = c->wtmp;
       a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
       a.norm = !c->hasB; a.partial = c->partial;
+      a.fuse_norm = a.norm; a.norm_dc = 1;
       S.check(orth(ORTH_UPD, a), "orth upd");
     }
-    norm_finish(S, ORTH_UPD);
+    norm_finish(S);
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
@@ -612,6 +615,7 @@ struct Solver {
       f.mode = FIN_DC; f.partial = c->partial; f.nblk = orth_blocks_dot3(n); f.stride = orth_stride();
       f.state = c->st; f.ncol_fixed = ncf; f.T = c->T; f.ldT = SYEV_MAXB; f.h = c->hbuf;
       f.nvec = more ? 3 : 2; f.cbuf = c->cbuf; f.L = c->Lm; f.dc = plusk ? 1 : 0;
+      f.cnt = 3 * maxcols();  // bound on the packed row width 3 (J + 1)
       S.check(fin(f), "fin dc");
     }
     {
@@ -623,10 +627,11 @@ struct Solver {
       if (more) {
         a.w = c->w; a.wout = c->wtmp; a.wout32 = c->fp32_phase ? c->wtmp32 : nullptr;
         a.norm = !c->hasB;
+        a.fuse_norm = a.norm; a.norm_dc = 1;
       }
       S.check(orth(ORTH_UPD2, a), "orth dc upd");
     }
-    if (more) norm_finish(S, ORTH_UPD2);
+    if (more) norm_finish(S);
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
@@ -841,6 +846,8 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   int fp32_best_cycle = 0, fp32_target = -1;
   trplk_stats& stt = c->stats;
   stt = trplk_stats{};
+  stt.a_ndiag = c->A.plan.ndiag;
+  stt.b_ndiag = c->hasB ? c->B.plan.ndiag : 0;
   stt.normA = normA;
   c->prof.clear();
   c->evused = 0;
@@ -1132,6 +1139,8 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
   const double thr = o.tol * normA;
   trplk_stats& stt = c->stats;
   stt = trplk_stats{};
+  stt.a_ndiag = c->A.plan.ndiag;
+  stt.b_ndiag = c->hasB ? c->B.plan.ndiag : 0;
   stt.normA = normA;
   c->prof.clear();
   c->evused = 0;
@@ -1396,6 +1405,9 @@ int finish_factor(trplk_ctx* c) {
   }
   HIPCHK(c, spmv_plan(G.plan, G.n, G.rowptr, 0, c->s));
   HIPCHK(c, spmv_plan(Gt.plan, Gt.n, Gt.rowptr, 0, c->s));
+  HIPCHK(c, spmv_plan_dia(G.plan, G.n, G.rowptr, G.col, G.val, G.val32, c->s));
+  HIPCHK(c, spmv_plan_dia(Gt.plan, Gt.n, Gt.rowptr, Gt.col, Gt.val, Gt.val32, c->s));
+  c->dev_bytes += dia_bytes(G.plan) + dia_bytes(Gt.plan);
   HIPCHK(c, hipStreamSynchronize(c->s));
   return TRPLK_OK;
 }
@@ -1583,6 +1595,9 @@ int trplk_learned_factor(trplk_ctx* c, const float* params) {
   }
   HIPCHK(c, spmv_plan(c->G.plan, c->n, c->G.rowptr, 0, c->s));
   HIPCHK(c, spmv_plan(c->Gt.plan, c->n, c->Gt.rowptr, 0, c->s));
+  HIPCHK(c, spmv_plan_dia(c->G.plan, c->n, c->G.rowptr, c->G.col, c->G.val, c->G.val32, c->s));
+  HIPCHK(c, spmv_plan_dia(c->Gt.plan, c->n, c->Gt.rowptr, c->Gt.col, c->Gt.val, c->Gt.val32, c->s));
+  c->dev_bytes += dia_bytes(c->G.plan) + dia_bytes(c->Gt.plan);
   HIPCHK(c, hipStreamSynchronize(c->s));
   c->prec = TRPLK_PREC_FACTOR;
   return TRPLK_OK;
@@ -1942,7 +1957,11 @@ int trplk_spmv(int32_t n, const int32_t* rowptr, const int32_t* col, const doubl
   hipStream_t s = static_cast<hipStream_t>(stream);
   SpmvPlan plan;
   hipError_t e = spmv_plan(plan, n, rowptr, lanes, s);
-  if (e != hipSuccess) return kernel_err(e);
+  if (e == hipSuccess && lanes == 0) e = spmv_plan_dia(plan, n, rowptr, col, val, nullptr, s);
+  if (e != hipSuccess) {
+    spmv_plan_free(plan);
+    return kernel_err(e);
+  }
   SpmvArgs a;
   a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = x; a.y = y; a.mode = SPMV_STORE;
   e = spmv_f64(plan, a, s);
@@ -1958,7 +1977,11 @@ int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const f
   hipStream_t s = static_cast<hipStream_t>(stream);
   SpmvPlan plan;
   hipError_t e = spmv_plan(plan, n, rowptr, lanes, s);
-  if (e != hipSuccess) return kernel_err(e);
+  if (e == hipSuccess && lanes == 0) e = spmv_plan_dia(plan, n, rowptr, col, nullptr, val, s);
+  if (e != hipSuccess) {
+    spmv_plan_free(plan);
+    return kernel_err(e);
+  }
   SpmvArgs a;
   a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = x; a.y = y; a.mode = SPMV_STORE;
   e = spmv_f32(plan, a, s);

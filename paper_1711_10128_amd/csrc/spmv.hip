@@ -15,7 +15,11 @@
 //    reduces with cross-lane shuffles; rows of a wavefront are consecutive, so
 //    the value and index streams of the wavefront are contiguous;
 //  * workgroup-per-row for rows longer than LONG_ROW entries (power-law hubs),
-//    listed once at plan time, so a hub row does not stall a wavefront.
+//    listed once at plan time, so a hub row does not stall a wavefront;
+//  * diagonal storage for matrices whose entries lie on a few diagonals
+//    (stencils and structured meshes): no column indices or row pointers
+//    are read, a thread owns a row and reads its value on each diagonal and
+//    the shifted x with loads that are contiguous across the wavefront.
 // The epilogue fuses the work that touches the row's own entries of the
 // dense vectors: scaling by 1/beta, writing the new basis column and its
 // products, and forming the next inner direction M (A g - rho B g) for the
@@ -23,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -463,6 +468,89 @@ __global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen, i
   for (int q = 0; q < 4; ++q) atomicMax(maxtile + q, mt[q]);
 }
 
+// Diagonal storage: thread i of the grid-stride loop owns row i; the row
+// sum runs over the diagonals in ascending offset order (ascending column),
+// skipping the zeros that pad the diagonals; x is read at the clamped
+// column, which only the padding ever needs.  MAXD bounds the unrolled
+// diagonal count (ndiag <= MAXD).
+template <int MAXD, typename VT, typename XT, typename AT, typename OT>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, const int* __restrict__ off,
+                                                        int ndiag, const VT* __restrict__ dval) {
+  EpiCtx e{1.0, 0.0, 0};
+  if (a.state) {
+    if (a.state->skip) return;
+    e.rho = a.state->rho;
+    e.nb = a.state->nb;
+    if (a.use_beta) e.s = a.state->inv_beta;
+  }
+  const XT* __restrict__ x = static_cast<const XT*>(a.x);
+  const int n = a.n;
+  int o[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) o[d] = d < ndiag ? off[d] : 0;
+  double acc = 0.0;
+  for (int row = blockIdx.x * SPMV_THREADS + threadIdx.x; row < n; row += gridDim.x * SPMV_THREADS) {
+    VT v[MAXD];
+    XT xv[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+      if (d < ndiag) {
+        v[d] = dval[static_cast<int64_t>(d) * n + row];
+        const int64_t c = static_cast<int64_t>(row) + o[d];
+        xv[d] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
+      }
+    }
+    AT sum = 0;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d)
+      if (d < ndiag && v[d] != VT(0)) sum += static_cast<AT>(v[d]) * static_cast<AT>(xv[d]);
+    epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
+  }
+  if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
+}
+
+// scatter of the CSR values into diagonal storage (zeroed beforehand): one
+// thread per row; repeated entries of a position are summed, as the CSR
+// kernels do
+template <typename VT>
+__global__ void k_dia_fill(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                           const VT* __restrict__ val, const int* __restrict__ off, int ndiag,
+                           VT* __restrict__ dval) {
+  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < n; row += gridDim.x * blockDim.x) {
+    for (int k = rowptr[row]; k < rowptr[row + 1]; ++k) {
+      const int o = col[k] - row;
+      int d = 0;
+      while (d < ndiag - 1 && off[d] != o) ++d;  // every offset is listed (checked on the host)
+      dval[static_cast<int64_t>(d) * n + row] += val[k];
+    }
+  }
+}
+
+template <typename VT, typename XT, typename AT, typename OT>
+hipError_t launch_dia(const SpmvPlan& p, const SpmvArgs& a, const VT* dval, hipStream_t s) {
+  if (!dval) return hipErrorInvalidValue;  // this precision was not prepared
+  const dim3 grd(p.nblk_dia), blk(SPMV_THREADS);
+  if (p.ndiag <= 8)
+    hipLaunchKernelGGL((k_spmv_dia<8, VT, XT, AT, OT>), grd, blk, 0, s, a, p.dia_off, p.ndiag, dval);
+  else if (p.ndiag <= 16)
+    hipLaunchKernelGGL((k_spmv_dia<16, VT, XT, AT, OT>), grd, blk, 0, s, a, p.dia_off, p.ndiag, dval);
+  else
+    hipLaunchKernelGGL((k_spmv_dia<DIA_MAXD, VT, XT, AT, OT>), grd, blk, 0, s, a, p.dia_off, p.ndiag,
+                       dval);
+  return hipGetLastError();
+}
+
+void dia_free(SpmvPlan& plan) {
+  if (plan.dia_off) (void)hipFree(plan.dia_off);
+  if (plan.dia_val) (void)hipFree(plan.dia_val);
+  if (plan.dia_val32) (void)hipFree(plan.dia_val32);
+  plan.dia_off = nullptr;
+  plan.dia_val = nullptr;
+  plan.dia_val32 = nullptr;
+  plan.ndiag = 0;
+  plan.nblk_dia = 0;
+}
+
 // Grid of the tile kernels: one tile per wavefront up to a cap.  The
 // software-pipelined CSR-stream kernel runs best with two rounds of resident
 // blocks (16 blocks of 4 wavefronts per compute unit, measured on MI355X for
@@ -476,6 +564,10 @@ int short_blocks(int n, bool stream, int rows = WAVE) {
 template <typename VT, typename XT, typename AT, typename OT>
 hipError_t launch(const SpmvPlan& p, const SpmvArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (p.ndiag > 0) {
+    if constexpr (std::is_same<VT, double>::value) return launch_dia<VT, XT, AT, OT>(p, a, p.dia_val, s);
+    else return launch_dia<VT, XT, AT, OT>(p, a, p.dia_val32, s);
+  }
   const dim3 blk(SPMV_THREADS);
   const dim3 grd(p.nblk_short);
   if (p.nblocks > 0 || p.adaptive) {
@@ -580,6 +672,7 @@ hipError_t adaptive_plan(SpmvPlan& plan, int n, const int* rowptr_dev, hipStream
 }
 
 hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hipStream_t s) {
+  dia_free(plan);
   plan.n = n;
   int nnz = 0;
   hipError_t e = hipSuccess;
@@ -645,6 +738,76 @@ hipError_t spmv_plan(SpmvPlan& plan, int n, const int* rowptr_dev, int lanes, hi
   return e;
 }
 
+hipError_t spmv_plan_dia(SpmvPlan& plan, int n, const int* rowptr_dev, const int* col_dev,
+                         const double* val64, const float* val32, hipStream_t s) {
+  dia_free(plan);
+  if (n <= 0 || (!val64 && !val32)) return hipSuccess;
+  std::vector<int> rp(static_cast<size_t>(n) + 1);
+  hipError_t e = hipMemcpyAsync(rp.data(), rowptr_dev, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const int64_t nnz = rp[n];
+  if (rp[0] != 0 || nnz <= 0) return hipSuccess;  // keep CSR
+  // the diagonal format reads 8 bytes per diagonal and row against CSR's 12
+  // per entry plus 4 per row: used only at or below 85% of the CSR bytes
+  const int64_t max_d =
+      std::min<int64_t>(DIA_MAXD, (85 * (12 * nnz + 4 * (int64_t(n) + 1))) / (100 * 8 * int64_t(n)));
+  if (max_d < 1) return hipSuccess;
+  std::vector<int> cl(static_cast<size_t>(nnz));
+  e = hipMemcpyAsync(cl.data(), col_dev, sizeof(int) * nnz, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<int> offs;
+  for (int i = 0; i < n; ++i) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int o = cl[k] - i;
+      if (std::find(offs.begin(), offs.end(), o) == offs.end()) {
+        offs.push_back(o);
+        if (static_cast<int64_t>(offs.size()) > max_d) return hipSuccess;  // CSR stays
+      }
+    }
+  }
+  std::sort(offs.begin(), offs.end());
+  const int nd = static_cast<int>(offs.size());
+  const int64_t cells = static_cast<int64_t>(nd) * n;
+  e = hipMalloc(&plan.dia_off, sizeof(int) * nd);
+  if (e == hipSuccess) e = hipMemcpyAsync(plan.dia_off, offs.data(), sizeof(int) * nd, hipMemcpyHostToDevice, s);
+  const int grid = std::min((n + 255) / 256, 4096);
+  if (e == hipSuccess && val64) {
+    e = hipMalloc(&plan.dia_val, sizeof(double) * cells);
+    if (e == hipSuccess) e = hipMemsetAsync(plan.dia_val, 0, sizeof(double) * cells, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_dia_fill<double>, dim3(grid), dim3(256), 0, s, n, rowptr_dev, col_dev, val64,
+                         plan.dia_off, nd, plan.dia_val);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess && val32) {
+    e = hipMalloc(&plan.dia_val32, sizeof(float) * cells);
+    if (e == hipSuccess) e = hipMemsetAsync(plan.dia_val32, 0, sizeof(float) * cells, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_dia_fill<float>, dim3(grid), dim3(256), 0, s, n, rowptr_dev, col_dev, val32,
+                         plan.dia_off, nd, plan.dia_val32);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dia_free(plan);
+    return e;
+  }
+  plan.ndiag = nd;
+  // every block resident at once: 8 blocks of 4 wavefronts per compute unit
+  plan.nblk_dia = std::max(1, std::min((n + SPMV_THREADS - 1) / SPMV_THREADS, 2048));
+  return hipSuccess;
+}
+
+int64_t spmv_matrix_bytes(const SpmvPlan& plan, int64_t nnz, bool f32) {
+  const int64_t vb = f32 ? 4 : 8;
+  if (plan.ndiag > 0) return vb * plan.ndiag * static_cast<int64_t>(plan.n);
+  return nnz * (vb + 4) + 4 * (static_cast<int64_t>(plan.n) + 1);
+}
+
 void spmv_plan_free(SpmvPlan& plan) {
   if (plan.long_rows) (void)hipFree(plan.long_rows);
   if (plan.blocks) (void)hipFree(plan.blocks);
@@ -652,9 +815,11 @@ void spmv_plan_free(SpmvPlan& plan) {
   plan.blocks = nullptr;
   plan.nlong = 0;
   plan.nblocks = 0;
+  dia_free(plan);
 }
 
 int spmv_partial_blocks(const SpmvPlan& plan) {
+  if (plan.ndiag > 0) return plan.nblk_dia;
   return plan.kmax ? plan.nblk_short : plan.nblk_short + plan.nlong;
 }
 

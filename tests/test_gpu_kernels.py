@@ -5,7 +5,8 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from workloads import lap2d, lap3d, fem3d, powerlaw, aniso3d  # noqa: E402
+from workloads import CSR, lap2d, lap3d, fem3d, powerlaw, aniso3d  # noqa: E402
+from spmv_format import dia_ndiag as _dia_ndiag  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -51,7 +52,50 @@ def _stream_rows(A):
     return 0
 
 
+def _band(n, offsets, seed, drop=0.0, dup=0):
+    """n x n matrix with random values on the given diagonals (entries that
+    leave the matrix are absent); a fraction `drop` of the entries removed;
+    `dup` entries stored twice (CSR with repeated positions, summed)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for o in offsets:
+        i = np.arange(max(0, -o), min(n, n - o))
+        rows.append(i)
+        cols.append(i + o)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    keep = rng.random(r.size) >= drop
+    r, c = r[keep], c[keep]
+    if dup:
+        pick = rng.choice(r.size, dup, replace=False)
+        r = np.concatenate([r, r[pick]])
+        c = np.concatenate([c, c[pick]])
+    order = np.lexsort((c, r))
+    r, c = r[order], c[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, r + 1, 1)
+    return CSR(n, np.cumsum(rowptr).astype(np.int32), c.astype(np.int32), rng.standard_normal(r.size))
+
+
+BANDS = {
+    # 27 and 14 diagonals: the 32- and 16-diagonal instances of the kernel
+    "band27": lambda: _band(5000, list(range(-299, 300, 23)), 3),
+    "band14": lambda: _band(3001, [-1200, -700, -64, -9, -2, -1, 0, 1, 2, 9, 64, 700, 1200, 1999], 4),
+    "diagonal": lambda: _band(777, [0], 5),
+    # holes inside the diagonals (zero padding) and repeated positions
+    "band_gaps": lambda: _band(4099, [-90, -1, 0, 1, 90], 6, drop=0.08),
+    "band_dup": lambda: _band(2500, [-50, -1, 0, 1, 50], 7, dup=40),
+}
+
+
 def test_spmv_cases_cover_every_kernel():
+    dia = {k: _dia_ndiag(f()) for k, f in {**MATS, **BANDS}.items()}
+    assert dia["lap2d"] == 5 and dia["lap3d"] == 7 and dia["aniso"] == 7
+    assert dia["band27"] == 27 and dia["band14"] == 14 and dia["diagonal"] == 1
+    assert dia["band_gaps"] == 5 and dia["band_dup"] == 5
+    # too few entries per diagonal at this size, or not banded: CSR kernels
+    assert dia["fem3d_A"] == 0 and dia["fem3d_B"] == 0
+    assert all(dia[k] == 0 for k in MATS if k.startswith("powerlaw"))
     picked = {k: _stream_rows(f()) for k, f in MATS.items()}
     assert picked["lap3d"] == 64 and picked["fem3d_A"] == 16
     assert picked["powerlaw_flat"] == 32 and picked["powerlaw_dense"] == 8
@@ -76,7 +120,31 @@ def test_spmv_f64_parity(T, name, lanes):
     assert np.all(np.abs(got - ref) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["lap3d", "powerlaw_hubs", "fem3d_A"])
+@pytest.mark.parametrize("name", list(BANDS))
+def test_spmv_diagonal_storage_parity(T, name):
+    """Banded matrices take the diagonal-storage kernel (lanes=0) and the
+    CSR-stream kernel (lanes=4); both match scipy to rounding."""
+    A = BANDS[name]()
+    print(f"spmv dia {name} n={A.n} nnz={A.nnz}", flush=True)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(A.n)
+    S = A.to_scipy()  # repeated positions are summed
+    ref = S @ x
+    bound = 4 * 2.2e-16 * (abs(S) @ np.abs(x)) * np.diff(A.rowptr).max()
+    for lanes in (0, 4):
+        y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        T.spmv(_dev(A.rowptr), _dev(A.col), _dev(A.val), _dev(x), y, lanes)
+        assert np.all(np.abs(y.cpu().numpy() - ref) <= bound + 1e-300), lanes
+    x32 = x.astype(np.float32)
+    y32 = torch.zeros(A.n, dtype=torch.float32, device="cuda")
+    T.spmv(_dev(A.rowptr), _dev(A.col), _dev(A.val.astype(np.float32)), _dev(x32), y32, 0)
+    S32 = A.to_scipy().astype(np.float32).astype(np.float64)
+    ref32 = S32 @ x32.astype(np.float64)
+    scale = abs(S32) @ np.abs(x32.astype(np.float64))
+    assert np.all(np.abs(y32.cpu().numpy() - ref32) <= 1e-6 * scale * np.diff(A.rowptr).max())
+
+
+@pytest.mark.parametrize("name", ["lap3d", "powerlaw_hubs", "fem3d_A", "aniso"])
 def test_spmv_f32_against_f64(T, name):
     A = MATS[name]()
     rng = np.random.default_rng(2)

@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 from oracle import precond as PC  # noqa: E402
 from oracle import trplk as O  # noqa: E402
 from workloads import island_block, lap2d_island, make, start_block  # noqa: E402
+from spmv_format import dia_ndiag  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -86,6 +87,9 @@ def test_solve_parity(T, name, kw, prec, extra):
     X0 = start_block(P.A.n, P.k, 12)
     ref = _oracle(P, prec, X0)
     st, ev, X, res, conv = _gpu(T, P, prec, X0, **extra)
+    # storage of the products: by diagonals for the grid operators that qualify
+    assert st["a_ndiag"] == dia_ndiag(P.A)
+    assert st["b_ndiag"] == (dia_ndiag(P.B) if P.B is not None else 0)
     # matvec law on the standard problem: k + (m - k) per cycle (Sec. 5)
     if P.B is None and P.p <= P.k:
         assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
