@@ -52,8 +52,8 @@ KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients
                 "orth_dc_dot": "k_orth<ORTH_DOT, 3 vectors> (U^T [u', A u', w]: delayed correction, "
                                "T column, coefficients of w)",
                 "orth_dc_upd": "k_upd2 (u = (u' - U c) / gamma; w -= U h; ||w||^2)",
-                "spmv": "k_spmv_stream / k_spmv_rows (SpMV + append epilogue)",
-                "prec": "k_spmv_dia / k_spmv_stream / k_spmv_rows (factor apply G, G^T)",
+                "spmv": "k_spmv_stream / k_spmv_adapt_long (CSR; SpMV + append epilogue)",
+                "prec": "k_spmv_stream / k_spmv_adapt_long (CSR; factor apply G, G^T)",
                 "rot": "k_rotate (MFMA restart rotation)"}
 
 
@@ -298,6 +298,8 @@ def main():
     names = dict(KERNEL_NAMES)
     if st["a_ndiag"]:
         names["spmv"] = f"k_spmv_dia ({st['a_ndiag']} diagonals; SpMV + append epilogue)"
+    if st["g_ndiag"]:
+        names["prec"] = f"k_spmv_dia ({st['g_ndiag']} diagonals; factor apply G, G^T)"
     roofline = {"bound": "hbm", "kernel": names.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args, dom),
@@ -390,7 +392,8 @@ def main():
         "max_resid_rel": float(np.max(res) / normA),
         "checks": checks,
         "spmv_storage": (f"diagonals ({st['a_ndiag']})" if st["a_ndiag"] else "csr")
-                        + (f", B: diagonals ({st['b_ndiag']})" if st["b_ndiag"] else ""),
+                        + (f", B: diagonals ({st['b_ndiag']})" if st["b_ndiag"] else "")
+                        + (f", G: diagonals ({st['g_ndiag']})" if st["g_ndiag"] else ""),
         "roofline": roofline,
         "spmv_roofline": spmv_roof,
         "kernel_classes": {k: {kk: (round(v, 3) if isinstance(v, float) else v)

@@ -161,6 +161,8 @@ typedef struct trplk_stats {
      the matrix is held by diagonals (at most 32 distinct column offsets and
      at most 85% of the CSR bytes per product), 0 for CSR */
   int32_t a_ndiag;     int32_t b_ndiag;
+  int32_t g_ndiag;     /* the same for the factor G of FSAI / FACTOR (0 also when none) */
+  int32_t pad_;
 } trplk_stats;
 
 typedef struct trplk_ctx trplk_ctx;

@@ -71,7 +71,8 @@ class _Stats(ctypes.Structure):
                 ("rr_ms", ctypes.c_double), ("rr_launches", ctypes.c_int64),
                 ("pass_ms", ctypes.c_double * 5), ("pass_launches", ctypes.c_int64 * 5),
                 ("pass_bytes", ctypes.c_int64 * 5),
-                ("a_ndiag", ctypes.c_int32), ("b_ndiag", ctypes.c_int32)]
+                ("a_ndiag", ctypes.c_int32), ("b_ndiag", ctypes.c_int32),
+                ("g_ndiag", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}

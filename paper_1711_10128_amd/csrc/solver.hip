@@ -848,6 +848,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   stt = trplk_stats{};
   stt.a_ndiag = c->A.plan.ndiag;
   stt.b_ndiag = c->hasB ? c->B.plan.ndiag : 0;
+  stt.g_ndiag = c->G.val ? c->G.plan.ndiag : 0;
   stt.normA = normA;
   c->prof.clear();
   c->evused = 0;
@@ -1141,6 +1142,7 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
   stt = trplk_stats{};
   stt.a_ndiag = c->A.plan.ndiag;
   stt.b_ndiag = c->hasB ? c->B.plan.ndiag : 0;
+  stt.g_ndiag = c->G.val ? c->G.plan.ndiag : 0;
   stt.normA = normA;
   c->prof.clear();
   c->evused = 0;

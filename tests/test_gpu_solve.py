@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import precond as PC  # noqa: E402
 from oracle import trplk as O  # noqa: E402
-from workloads import island_block, lap2d_island, make, start_block  # noqa: E402
+from workloads import CSR, island_block, lap2d_island, make, start_block  # noqa: E402
 from spmv_format import dia_ndiag  # noqa: E402
 
 
@@ -90,6 +90,10 @@ def test_solve_parity(T, name, kw, prec, extra):
     # storage of the products: by diagonals for the grid operators that qualify
     assert st["a_ndiag"] == dia_ndiag(P.A)
     assert st["b_ndiag"] == (dia_ndiag(P.B) if P.B is not None else 0)
+    if prec == "fsai":  # G has the pattern of tril(A)
+        assert st["g_ndiag"] == dia_ndiag(CSR.from_scipy(PC.fsai(P.A.to_scipy())))
+    else:
+        assert st["g_ndiag"] == 0
     # matvec law on the standard problem: k + (m - k) per cycle (Sec. 5)
     if P.B is None and P.p <= P.k:
         assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
