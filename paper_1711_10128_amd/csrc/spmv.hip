@@ -490,20 +490,44 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
   for (int d = 0; d < MAXD; ++d) o[d] = d < ndiag ? off[d] : 0;
   double acc = 0.0;
   for (int row = blockIdx.x * SPMV_THREADS + threadIdx.x; row < n; row += gridDim.x * SPMV_THREADS) {
-    VT v[MAXD];
-    XT xv[MAXD];
+    AT sum = 0;
+    if constexpr (MAXD <= 8) {
+      VT v[MAXD];
+      XT xv[MAXD];
 #pragma unroll
-    for (int d = 0; d < MAXD; ++d) {
-      if (d < ndiag) {
-        v[d] = dval[static_cast<int64_t>(d) * n + row];
-        const int64_t c = static_cast<int64_t>(row) + o[d];
-        xv[d] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
+      for (int d = 0; d < MAXD; ++d) {
+        if (d < ndiag) {
+          v[d] = dval[static_cast<int64_t>(d) * n + row];
+          const int64_t c = static_cast<int64_t>(row) + o[d];
+          xv[d] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < MAXD; ++d)
+        if (d < ndiag && v[d] != VT(0)) sum += static_cast<AT>(v[d]) * static_cast<AT>(xv[d]);
+    } else {
+      // diagonals in chunks of 8, the loads of a chunk in flight together:
+      // fewer registers than holding every diagonal's loads keep more
+      // wavefronts resident (the same summation order)
+#pragma unroll 1
+      for (int d0 = 0; d0 < MAXD; d0 += 8) {
+        if (d0 >= ndiag) break;
+        VT v[8];
+        XT xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int d = d0 + q;
+          if (d < ndiag) {
+            v[q] = dval[static_cast<int64_t>(d) * n + row];
+            const int64_t c = static_cast<int64_t>(row) + o[d];
+            xv[q] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (d0 + q < ndiag && v[q] != VT(0)) sum += static_cast<AT>(v[q]) * static_cast<AT>(xv[q]);
       }
     }
-    AT sum = 0;
-#pragma unroll
-    for (int d = 0; d < MAXD; ++d)
-      if (d < ndiag && v[d] != VT(0)) sum += static_cast<AT>(v[d]) * static_cast<AT>(xv[d]);
     epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
   }
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
