@@ -1,0 +1,111 @@
+"""Full-size solves in the configurations bench.py times, checked by
+properties that hold at any size (the oracle needs seconds per cycle at
+these sizes, minutes per solve): residuals and Rayleigh quotients recomputed
+pair by pair with SciPy products, (B-)orthonormality of the returned
+vectors, the product count of the standard problem, the closed-form bounds
+of the Laplacian's spectrum, the exact smallest eigenvalue of the shifted
+graph Laplacian, and the full-size SpMV row by row against SciPy."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workloads import make, start_block  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_10128_amd as T
+    T.lib()
+    return T
+
+
+def _solve(T, P, prec, precision):
+    """The solve as bench.py runs it: device-resident CSR and start block."""
+    Ad = T.DeviceCSR(P.A)
+    Bd = T.DeviceCSR(P.B) if P.B is not None else None
+    X0 = start_block(P.A.n, P.k, P.seed)
+    Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
+    s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=prec, precision=precision)
+    st = s.solve(Xd)
+    ev, X, res, conv = s.eigpairs()
+    s.close()
+    return st, ev, X, res, conv
+
+
+def _check_pairs(P, st, ev, X, res, conv):
+    """Residuals, Rayleigh quotients and orthonormality from CPU products."""
+    A = P.A.to_scipy()
+    B = P.B.to_scipy() if P.B is not None else None
+    normA = st["normA"]
+    assert conv.all()
+    AX = A @ X
+    BX = X if B is None else B @ X
+    xn = np.linalg.norm(X, axis=0)
+    r = np.linalg.norm(AX - BX * ev[None, :], axis=0) / xn
+    assert np.all(r <= P.tol * normA * 1.001)
+    # the reported residuals are the same quantity
+    assert np.all(np.abs(r - res) <= 1e-6 * P.tol * normA + 1e-3 * res)
+    # Rayleigh quotient: |x^T (A x - theta B x)| / x^T B x <= ||x|| ||r|| / x^T B x
+    xbx = np.einsum("ij,ij->j", X, BX)
+    rq = np.einsum("ij,ij->j", X, AX) / xbx
+    assert np.all(np.abs(rq - ev) <= xn * r * xn / xbx * 1.001 + 1e-14 * np.abs(ev))
+    G = X.T @ BX
+    assert np.max(np.abs(G - np.eye(G.shape[0]))) < 1e-10
+    assert np.all(np.diff(ev) >= 0)
+
+
+def test_laplacian_128_cubed(T):
+    """The 3-D Laplacian 128^3 + V, p = 10, m = 40, k = 20, Jacobi, float64."""
+    P = make("lap3d", "full")
+    print(f"full lap3d n={P.A.n}", flush=True)
+    st, ev, X, res, conv = _solve(T, P, "jacobi", "fp64")
+    print(f"  cycles={st['cycles']} mv={st['matvecs']} storage={st['a_ndiag']}", flush=True)
+    assert st["a_ndiag"] == 7
+    assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
+    _check_pairs(P, st, ev, X, res, conv)
+    # Weyl: lambda_i(A0) <= theta_i (Ritz values bound from above, V >= 0)
+    # and theta_i <= lambda_i(A0) + max V + the residual
+    N = P.meta["N"]
+    s1 = 4 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    lam0 = np.sort((s1[:, None, None] + s1[None, :, None] + s1[None, None, :]).ravel())[:P.p]
+    assert np.all(ev >= lam0 - 1e-12)
+    assert np.all(ev <= lam0 + P.meta["vmax"] + res)
+    # the product in the same storage and launch configuration, every row
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(P.A.n)
+    A = P.A.to_scipy()
+    y = torch.zeros(P.A.n, dtype=torch.float64, device="cuda")
+    T.spmv(torch.from_numpy(P.A.rowptr).cuda(), torch.from_numpy(P.A.col).cuda(),
+           torch.from_numpy(P.A.val).cuda(), torch.from_numpy(x).cuda(), y, 0)
+    bound = 4 * 2.2e-16 * (abs(A) @ np.abs(x)) * 7
+    assert np.all(np.abs(y.cpu().numpy() - A @ x) <= bound)
+
+
+def test_power_law_graph_one_million(T):
+    """The power-law graph Laplacian + 0.01 I, n = 10^6, p = 20, m = 48,
+    k = 24, Jacobi, float64 (CSR: too many distinct column offsets)."""
+    P = make("powerlaw", "full")
+    print(f"full powerlaw n={P.A.n}", flush=True)
+    st, ev, X, res, conv = _solve(T, P, "jacobi", "fp64")
+    print(f"  cycles={st['cycles']} mv={st['matvecs']}", flush=True)
+    assert st["a_ndiag"] == 0
+    assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
+    _check_pairs(P, st, ev, X, res, conv)
+    # connected graph: the smallest eigenvalue is the shift, eigenvector 1/sqrt(n)
+    assert ev[0] >= 0.01 - 1e-12 and abs(ev[0] - 0.01) <= max(res[0], 1e-12)
+
+
+def test_fem_pencil_97_cubed(T):
+    """The Q1 FEM pencil on 97^3 elements, p = 16, m = 48, k = 24, FSAI,
+    mixed precision; A, B and the factor held by diagonals."""
+    P = make("fem3d", "full")
+    print(f"full fem3d n={P.A.n}", flush=True)
+    st, ev, X, res, conv = _solve(T, P, "fsai", "mixed")
+    print(f"  cycles={st['cycles']} mv={st['matvecs']} fp32 cycles={st['fp32_cycles']}", flush=True)
+    assert (st["a_ndiag"], st["b_ndiag"], st["g_ndiag"]) == (27, 27, 14)
+    assert st["fp32_cycles"] >= 1
+    _check_pairs(P, st, ev, X, res, conv)
