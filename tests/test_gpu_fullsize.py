@@ -109,3 +109,29 @@ def test_fem_pencil_97_cubed(T):
     assert (st["a_ndiag"], st["b_ndiag"], st["g_ndiag"]) == (27, 27, 14)
     assert st["fp32_cycles"] >= 1
     _check_pairs(P, st, ev, X, res, conv)
+
+
+def test_anisotropic_256_cubed_product(T):
+    """The largest operator (256^3 anisotropic flux form, 117M entries): its
+    product in the storage the solver uses (7 diagonals), float64 and
+    float32, every row against SciPy.  (A solve at this size takes minutes;
+    the solver's kernels are those of the 128^3 runs above.)"""
+    P = make("aniso3d", "full")
+    print(f"full aniso3d n={P.A.n} nnz={P.A.nnz}", flush=True)
+    from spmv_format import dia_ndiag
+    assert dia_ndiag(P.A) == 7
+    A = P.A.to_scipy()
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(P.A.n)
+    rp, cl = torch.from_numpy(P.A.rowptr).cuda(), torch.from_numpy(P.A.col).cuda()
+    y = torch.zeros(P.A.n, dtype=torch.float64, device="cuda")
+    T.spmv(rp, cl, torch.from_numpy(P.A.val).cuda(), torch.from_numpy(x).cuda(), y, 0)
+    ref = A @ x
+    scale = abs(A) @ np.abs(x)
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 4 * 2.2e-16 * scale * 7)
+    x32 = x.astype(np.float32)
+    y32 = torch.zeros(P.A.n, dtype=torch.float32, device="cuda")
+    T.spmv(rp, cl, torch.from_numpy(P.A.val.astype(np.float32)).cuda(), torch.from_numpy(x32).cuda(), y32, 0)
+    A32 = A.astype(np.float32).astype(np.float64)
+    ref32 = A32 @ x32.astype(np.float64)
+    assert np.all(np.abs(y32.cpu().numpy() - ref32) <= 1e-6 * (abs(A32) @ np.abs(x32.astype(np.float64))) * 7)
