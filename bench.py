@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
-"""Time-to-solution of the HIP TRPL+K on one MI355X.
+"""Time and matrix-vector products of the HIP TRPL+K on one MI355X.
 
-One step = one complete solve (every stage of the path: SpMV, preconditioner
-apply, inner Krylov loop with full B-reorthogonalisation, +K augmentation,
-Rayleigh-Ritz, thick restart and locking) from the same seeded start block,
-on a matrix already resident in HBM.
+Default workload: the largest one, 3-D 7-point anisotropic diffusion on 256^3
+(axis weights 1, 1e-2, 1e-4 times the harmonic mean of a lognormal sigma = 1
+field; n = 16,777,216, nnz = 117,047,296), p = 50 smallest pairs, m = 64,
+k = 32, l = 1, hard locking (p > k), tol = 1e-8 * ||A||_inf, learned factor
+G^T G + float32 SpMV with float64 orthogonalisation, Rayleigh-Ritz and
+rotation.  A complete solve runs thousands of restart cycles (minutes), so one
+step is a fixed number of full-size restart cycles (--cycles, default 10) of
+TRPL+K from the seeded start block (drawn on the device, SplitMix64 seed 12),
+every stage of the path included (SpMV, preconditioner apply, inner Krylov
+loop with full reorthogonalisation, +K, Rayleigh-Ritz, rotation, locking);
+--converged adds one complete solve of the timed form and of plain float64
+Jacobi (time to solution, products, cycles).
 
-Default workload: 3-D 7-point Laplacian on 128^3 plus a random diagonal
-potential U[0, 0.05] (n = 2,097,152, nnz = 14,581,760), p = 10, m = 40,
-k = 20, l = 1, tol = 1e-8 * ||A||_inf, Jacobi, float64.  --workload selects
-the other four (2-D Laplacian 64^2, Q1 FEM pencil 97^3, power-law graph
-n = 1e6, anisotropic diffusion 256^3).  Prints one JSON line.
+The other workloads (--workload: 2-D Laplacian 64^2, 3-D Laplacian 128^3,
+Q1 FEM pencil 97^3, power-law graph n = 1e6) are timed as complete solves
+(one step = one solve to convergence).  Prints one JSON line; --summarize DIR
+turns rocprofv3 output under DIR into the text summaries kept in profiles/.
 """
 from __future__ import annotations
 
@@ -28,21 +35,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# workload name -> generator arguments, solver sizes, timed (precond, precision)
+# workload name -> generator arguments, solver sizes, timed (precond, precision),
+# restart cycles per step (0 = a step is a complete solve)
 WORKLOADS = {
-    "lap2d": dict(gen=dict(N=64), p=5, m=20, k=8, form=("jacobi", "fp64"),
+    "lap2d": dict(gen=dict(N=64), p=5, m=20, k=8, form=("jacobi", "fp64"), cycles=0,
                   desc="2-D 5-point Laplacian 64^2"),
-    "lap3d": dict(gen=dict(N=128, vmax=0.05), p=10, m=40, k=20, form=("jacobi", "fp64"),
+    "lap3d": dict(gen=dict(N=128, vmax=0.05), p=10, m=40, k=20, form=("jacobi", "fp64"), cycles=0,
                   desc="3-D 7-point Laplacian 128^3 + V~U[0,0.05]"),
-    "fem3d": dict(gen=dict(Ne=97, sigma=0.5), p=16, m=48, k=24, form=("fsai", "mixed"),
+    "fem3d": dict(gen=dict(Ne=97, sigma=0.5), p=16, m=48, k=24, form=("fsai", "mixed"), cycles=0,
                   desc="Q1 FEM pencil 97^3 elements, lognormal sigma=0.5, consistent mass"),
-    "powerlaw": dict(gen=dict(n=1_000_000), p=20, m=48, k=24, form=("learned", "fp64"),
+    "powerlaw": dict(gen=dict(n=1_000_000), p=20, m=48, k=24, form=("learned", "fp64"), cycles=0,
                      desc="shifted Laplacian of a Chung-Lu power-law graph, n=1e6",
                      # gather-bound SpMV and well-separated wanted eigenvalues: a long
                      # float32 phase pays here (measured), unlike on the grids
                      mixed_switch=1e-5),
     "aniso3d": dict(gen=dict(N=256, sigma=1.0), p=50, m=64, k=32, form=("learned", "mixed"),
-                    desc="anisotropic 7-point diffusion 256^3, lognormal sigma=1"),
+                    cycles=10,
+                    desc="anisotropic 7-point diffusion 256^3 (axis weights 1, 1e-2, 1e-4 x "
+                         "harmonic mean of a lognormal sigma=1 field)"),
 }
 
 
@@ -56,18 +66,32 @@ KERNEL_NAMES = {"orth_dot": "k_orth<ORTH_DOT> (T column + first CGS coefficients
                 "prec": "k_spmv_stream / k_spmv_adapt_long (CSR; factor apply G, G^T)",
                 "rot": "k_rotate (MFMA restart rotation)"}
 
+# rocprofv3 kernel name -> profile class (the classes bench.py times with events)
+PROF_CLASSES = [("k_orth<4, 0, 3", "orth_dc_dot"), ("k_upd2", "orth_dc_upd"),
+                ("k_orth<8, 1", "orth_upd_dot"), ("k_orth<", "orth_dot"), ("k_upd<", "orth_upd"),
+                ("k_spmv", "spmv"), ("k_rotate", "rot"), ("k_finish", "finish"),
+                ("k_syev", "syev"), ("copyBuffer", "copy")]
 
-def measured_traffic(args, dom):
+
+def counters_file(args, form):
+    size = args.size or list(WORKLOADS[args.workload]["gen"].values())[0]
+    return os.path.join(ROOT, "profiles", f"{args.workload}_{size}_{form[0]}_{form[1]}_hbm_counters.txt")
+
+
+def measured_traffic(args, form, dom):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary of this exact configuration, or None when there is none."""
-    if args.workload != "lap3d" or args.size or args.precond or args.precision:
-        return None
-    path = os.path.join(ROOT, "profiles", "lap3d_128_jacobi_fp64_hbm_counters.txt")
+    path = counters_file(args, form)
     if not os.path.exists(path):
         return None
+    cyc = None
     for line in open(path):
         parts = line.split()
+        if len(parts) >= 2 and parts[0] == "STEP_CYCLES":
+            cyc = int(parts[1])
         if len(parts) >= 4 and parts[0] == "TRAFFIC" and parts[1] == dom:
+            if cyc is not None and cyc != args.cycles:
+                return None
             return int(parts[2])
     return None
 
@@ -77,17 +101,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lap3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="aniso3d", choices=sorted(WORKLOADS))
     ap.add_argument("--size", type=int, default=0,
                     help="override the grid edge / node count (0 = the workload's own size)")
+    ap.add_argument("--cycles", type=int, default=-1,
+                    help="restart cycles per step (0 = a complete solve; default per workload)")
+    ap.add_argument("--converged", action="store_true",
+                    help="also run one complete solve of the timed form and of float64 Jacobi")
     ap.add_argument("--precond", default="", help="timed form's preconditioner (default per workload)")
     ap.add_argument("--precision", default="", choices=["", "fp64", "mixed"])
     ap.add_argument("--variants", type=int, default=1, help="also time the other forms once")
-    ap.add_argument("--cpu-cycles", type=int, default=3, help="oracle cycles in the CPU sample (0 = skip)")
+    ap.add_argument("--cpu", type=int, default=1, help="time the CPU oracle on the same input")
     ap.add_argument("--train-count", type=int, default=6, help="learned factor: training instances")
     ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
     ap.add_argument("--epochs", type=int, default=120)
-    ap.add_argument("--profile-only", action="store_true", help="one profiled solve (for rocprofv3 runs)")
+    ap.add_argument("--profile-only", action="store_true", help="one profiled step (for rocprofv3 runs)")
     ap.add_argument("--method", default="trplk", choices=["trplk", "pl1", "pl1_practical"],
                     help="outer method of the timed solve: TRPL+K (Alg. 1) or PL+1 (Alg. 2, "
                          "the smallest pair; p = k = l = 1, the other methods as variants)")
@@ -96,9 +124,16 @@ def parse():
                          "Fig. 2) or the number l of previous Ritz vectors (+K, Fig. 3; l = 0 is "
                          "thick-restart Lanczos) and print one JSON line with every setting")
     ap.add_argument("--sweep-values", default="", help="comma-separated values (default per sweep)")
-    ap.add_argument("--max-cycles", type=int, default=5000,
-                    help="cap the restart cycles (a capped run reports per-cycle time)")
-    return ap.parse_args()
+    ap.add_argument("--max-cycles", type=int, default=5000, help="cap of a complete solve")
+    ap.add_argument("--progress", type=int, default=0,
+                    help="complete solves print a line every this many cycles (0 = silent)")
+    ap.add_argument("--summarize", default="",
+                    help="summarize rocprofv3 output in this directory (kernel stats or counters) "
+                         "instead of running anything on the GPU")
+    args = ap.parse_args()
+    if args.cycles < 0:
+        args.cycles = WORKLOADS[args.workload]["cycles"]
+    return args
 
 
 def make_workload(name, size, seed=12):
@@ -164,15 +199,116 @@ def run_sweep(args, T, P, Ad, Bd, Xd, precond, precision, log):
         S.close()
         rows.append({"m": m, "l": l, "s": round(dt, 4), "cycles": st["cycles"],
                      "matvecs": st["matvecs"], "converged": bool(conv.all()),
-                     "max_resid_rel": float(np.max(res) / st["normA"])})
+                     "max_resid_rel": float(np.nanmax(res) / st["normA"])})
         log(f"# sweep {args.sweep}={v}: {st['cycles']} cycles, {st['matvecs']} MV, {dt:.3f} s")
     print(json.dumps({"sweep": args.sweep, "workload": args.workload, "n": P.A.n,
                       "p": P.p, "k": P.k, "precond": precond, "precision": precision,
                       "tol": P.tol, "results": rows}))
 
 
+def kernel_profile(sp, st, log):
+    """Per-class device time, launches and algorithmic bytes of one profiled
+    step (HIP events recorded on the solver's stream around each launch)."""
+    classes = {}
+    for cls in ("spmv", "orth", "prec", "rot", "rr"):
+        ms = sp[f"{cls}_ms"]
+        if sp[f"{cls}_launches"]:
+            nbytes = sp.get(f"{cls}_bytes", 0)
+            classes[cls] = {"ms": ms, "launches": sp[f"{cls}_launches"], "bytes": nbytes,
+                            "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 and nbytes else None}
+    for q, name in enumerate(("orth_dot", "orth_upd_dot", "orth_upd", "orth_dc_dot", "orth_dc_upd")):
+        if sp["pass_launches"][q]:
+            ms, nbytes = sp["pass_ms"][q], sp["pass_bytes"][q]
+            classes[name] = {"ms": ms, "launches": sp["pass_launches"][q], "bytes": nbytes,
+                             "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    return classes
+
+
+def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log):
+    """The FP64 NumPy/SciPy oracle on the same input, on this host's cores.
+
+    Per-cycle time: from the oracle's hook before the Rayleigh-Ritz of cycle 1
+    to the same point of cycle 2, i.e. exactly one full restart cycle (its
+    start-block phase excluded).  A step of C cycles is priced at C times
+    that; a complete-solve step at the oracle's own cycle count when the
+    full-size reference run (tests/golden) records one, else the sample's
+    per-cycle time times the GPU's cycles (labelled)."""
+    from oracle import trplk as O
+    A = P.A.to_scipy()
+    B = None if P.B is None else P.B.to_scipy()
+    cores = len(os.sched_getaffinity(0))
+    stamps = []
+    c0 = time.perf_counter()
+    r = O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=O.jacobi(A), max_cycles=2,
+                trace=lambda c, *a: stamps.append(time.perf_counter()))
+    c1 = time.perf_counter()
+    per_cycle = stamps[1] - stamps[0] if len(stamps) >= 2 else (c1 - c0)
+    log(f"# oracle: start + {r.cycles} cycles in {c1 - c0:.1f} s, one cycle {per_cycle:.2f} s")
+    base = {"unit": "s", "cores": cores, "kind": "oracle", "per_cycle_s": round(per_cycle, 3),
+            "threads_note": f"NumPy BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}; "
+                            "SciPy SpMV single-threaded"}
+    if cycles_per_step:
+        return dict(base, value=round(per_cycle * cycles_per_step, 3),
+                    sample=f"FP64 oracle (Jacobi) on the same full-size input and start block: one "
+                           f"complete restart cycle (cycle 1 -> 2, hook to hook) took "
+                           f"{per_cycle:.2f} s of {c1 - c0:.1f} s (start block + 2 cycles); value "
+                           f"= {cycles_per_step} cycles, the GPU step's unit")
+    gold = None
+    try:
+        sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+        import make_fullsize_goldens as G
+        case = f"{P.name}_jacobi_1e-08"
+        if case in G.CASES and os.path.exists(G.path(case)):
+            gold = G.load(case)["cycles"]
+    except Exception:
+        gold = None
+    if gold:
+        return dict(base, value=round(per_cycle * gold, 2),
+                    sample=f"one complete restart cycle of the FP64 oracle (Jacobi) on the same input "
+                           f"took {per_cycle:.2f} s; value = that x the {gold} cycles the oracle "
+                           f"itself needs to converge (its full-size reference run, tests/golden)")
+    return dict(base, value=round(per_cycle * gpu_cycles, 2),
+                sample=f"one complete restart cycle of the FP64 oracle took {per_cycle:.2f} s; value "
+                       f"= that x the {gpu_cycles} cycles of the timed GPU form (extrapolated)")
+
+
+def summarize(d):
+    """Text summary of rocprofv3 CSV output under d: kernel statistics
+    (*kernel_stats.csv) or per-class HBM counters (*counter_collection.csv)."""
+    import csv
+    import glob
+    out = []
+    ks = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    cc = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if ks:
+        rows = list(csv.DictReader(open(ks[0])))
+        tot = sum(float(r["TotalDurationNs"]) for r in rows)
+        out.append(f"# source: {os.path.relpath(ks[0], d)}")
+        out.append(f"# {'rocprofv3 kernel':<92} {'calls':>6} {'total ms':>9} {'avg us':>9} {'%':>6}")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            out.append(f"{r['Name'][:92]:<92} {int(r['Calls']):>6} "
+                       f"{float(r['TotalDurationNs']) / 1e6:>9.2f} {float(r['AverageNs']) / 1e3:>9.2f} "
+                       f"{100 * float(r['TotalDurationNs']) / tot:>6.2f}")
+    for f in cc:
+        rows = list(csv.DictReader(open(f)))
+        agg = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            cls = next((c for key, c in PROF_CLASSES if key in name), "other")
+            a = agg.setdefault((cls, r["Counter_Name"]), [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        out.append(f"# source: {os.path.relpath(f, d)}")
+        out.append(f"{'class':<14} {'counter':<12} {'dispatches':>10} {'mean KiB':>14}")
+        for (cls, cn), (cnt, tot) in sorted(agg.items()):
+            out.append(f"{cls:<14} {cn:<12} {cnt:>10} {tot / cnt:>14.1f}")
+    print("\n".join(out))
+
+
 def main():
     args = parse()
+    if args.summarize:
+        return summarize(args.summarize)
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on exactly one GPU; multi-GPU runs are not "
                                    "part of it (--gpus must be 1)"}))
@@ -180,7 +316,7 @@ def main():
     import torch
 
     import paper_1711_10128_amd as T
-    from workloads import start_block
+    from workloads import splitmix64_block, start_block
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -189,16 +325,22 @@ def main():
     W = WORKLOADS[args.workload]
     precond = args.precond or W["form"][0]
     precision = args.precision or W["form"][1]
+    C = args.cycles
     t0 = time.time()
     P = make_workload(args.workload, args.size)
     if args.method != "trplk":
         import dataclasses
         P = dataclasses.replace(P, p=1, k=1, l=1)
-    X0 = start_block(P.A.n, P.k, P.seed)
     log(f"# workload {args.workload} n={P.A.n} nnz={P.A.nnz} generated in {time.time() - t0:.1f}s")
     Ad = T.DeviceCSR(P.A)
     Bd = T.DeviceCSR(P.B) if P.B is not None else None
-    Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
+    # step-of-C-cycles workloads start from the block the library draws on
+    # the device (x0 = NULL, seed 12); complete solves from the host-seeded block
+    if C:
+        Xd = None
+    else:
+        X0 = start_block(P.A.n, P.k, P.seed)
+        Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
     torch.cuda.synchronize()
 
     if args.sweep:
@@ -212,16 +354,18 @@ def main():
     if need_learned:
         learned, learn_info = train_factor(T, args.workload, args, log)
 
-    def make_solver(pc, pr, profile=False, method=None):
+    def make_solver(pc, pr, profile=False, method=None, cycles=None):
         base = "jacobi" if pc == "learned" else pc
+        cap = (C or args.max_cycles) if cycles is None else cycles
         s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
-                     precision=pr, profile=profile, max_cycles=args.max_cycles,
-                     method=method or args.method, mixed_switch=W.get("mixed_switch", 0.0))
+                     precision=pr, profile=profile, max_cycles=cap, seed=P.seed,
+                     method=method or args.method, mixed_switch=W.get("mixed_switch", 0.0),
+                     progress=args.progress if cap > 100 else 0)
         if pc == "learned":
             s.learned_factor(learned)
         return s
 
-    # ---- timed region: K solves of the selected form ----
+    # ---- timed region: K steps of the selected form ----
     S = make_solver(precond, precision)
     if args.profile_only:
         st = S.solve(Xd)
@@ -238,7 +382,7 @@ def main():
         return
     for _ in range(args.warmup):
         w = S.solve(Xd)
-        log(f"# warmup solve: {w['cycles']} cycles, {w['solve_ms']:.1f} ms")
+        log(f"# warmup step: {w['cycles']} cycles, {w['solve_ms']:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = []
@@ -251,44 +395,46 @@ def main():
     st = stats[-1]
     ev, X, res, conv = S.eigpairs(vectors=False)
     normA = st["normA"]
+    nret = int(np.sum(np.isfinite(ev)))
     converged = bool(conv.all() and np.all(res <= P.tol * normA * 1.001))
     if st["status"] == 1:
-        log(f"# capped at {st['cycles']} cycles: {int(conv.sum())} of {P.p} pairs converged")
+        log(f"# step ended after {st['cycles']} cycles: {int(conv.sum())} of {P.p} pairs converged")
     checks = {}
-    if args.workload == "lap3d":
+    if not C and args.workload == "lap3d":
         N = P.meta["N"]
         i = np.arange(1, N + 1)
         s1 = 4 * np.sin(i * np.pi / (2 * (N + 1))) ** 2
         lam0 = np.sort((s1[:, None, None] + s1[None, :, None] + s1[None, None, :]).ravel())[:P.p]
         checks["eigs_within_weyl_bounds"] = bool(np.all(ev >= lam0 - 1e-12) and np.all(ev <= lam0 + 0.05 + 1e-12))
-    if args.workload == "lap2d":
+    if not C and args.workload == "lap2d":
         N = P.meta["N"]
         i = np.arange(1, N + 1)
         s1 = 4 * np.sin(i * np.pi / (2 * (N + 1))) ** 2
         lam = np.sort((s1[:, None] + s1[None, :]).ravel())[:P.p]
         checks["max_rel_err_vs_closed_form"] = float(np.max(np.abs(ev - lam) / lam))
-    if args.workload == "powerlaw":
+    if not C and args.workload == "powerlaw":
         checks["lambda1_minus_shift_rel"] = float(abs(ev[0] - 0.01) / 0.01)
+    if not C and args.method == "trplk":
+        # against the FP64 oracle's full-size reference run (tests/golden), when one exists
+        try:
+            sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+            import make_fullsize_goldens as G
+            case = f"{args.workload}_{precond}_1e-08"
+            if not args.size and case in G.CASES and os.path.exists(G.path(case)):
+                g = G.load(case)
+                checks["max_rel_eig_err_vs_oracle"] = float(np.max(np.abs(ev - g["theta"]) /
+                                                                   np.abs(g["theta"])))
+                checks["oracle_cycles"] = g["cycles"]
+        except Exception as e:  # a reference file that does not parse is reported, not fatal
+            checks["oracle_reference_error"] = str(e)
     S.close()
 
-    # ---- kernel profile of the same solve (HIP events around each launch) ----
+    # ---- kernel profile of one step (HIP events around each launch) ----
     Sp = make_solver(precond, precision, profile=True)
     sp = Sp.solve(Xd)
     Sp.close()
-    log(f"# profiled solve: {sp['solve_ms']:.1f} ms")
-    classes = {}
-    for cls in ("spmv", "orth", "prec", "rot", "rr"):
-        ms = sp[f"{cls}_ms"]
-        if sp[f"{cls}_launches"]:
-            nbytes = sp.get(f"{cls}_bytes", 0)
-            classes[cls] = {"ms": ms, "launches": sp[f"{cls}_launches"], "bytes": nbytes,
-                            "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 and nbytes else None}
-    # the orthogonalisation by pass (one kernel each)
-    for q, name in enumerate(("orth_dot", "orth_upd_dot", "orth_upd", "orth_dc_dot", "orth_dc_upd")):
-        if sp["pass_launches"][q]:
-            ms, nbytes = sp["pass_ms"][q], sp["pass_bytes"][q]
-            classes[name] = {"ms": ms, "launches": sp["pass_launches"][q], "bytes": nbytes,
-                             "GBs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    log(f"# profiled step: {sp['solve_ms']:.1f} ms")
+    classes = kernel_profile(sp, st, log)
     kernels = [c for c in classes if c != "orth" and classes[c]["bytes"]]
     dom = max(kernels, key=lambda c: classes[c]["ms"])
     d = classes[dom]
@@ -302,7 +448,7 @@ def main():
         names["prec"] = f"k_spmv_dia ({st['g_ndiag']} diagonals; factor apply G, G^T)"
     roofline = {"bound": "hbm", "kernel": names.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args, dom),
+                "traffic": measured_traffic(args, (precond, precision), dom),
                 "bytes_per_launch": int(per_launch_bytes), "avg_launch_us": round(avg_ms * 1e3, 2)}
     spmv = classes.get("spmv")
     spmv_roof = None
@@ -312,7 +458,26 @@ def main():
                      "frac": round(g / HBM_PEAK_GBS, 4), "launches": spmv["launches"],
                      "avg_launch_us": round(spmv["ms"] / spmv["launches"] * 1e3, 2)}
 
-    # ---- other forms (one warm solve each, outside the timed region) ----
+    # ---- other forms (one warm step each, outside the timed region) ----
+    def one(pc, pr, mm=None, cycles=None, warm=True):
+        V = make_solver(pc, pr, method=mm, cycles=cycles)
+        if warm:
+            V.solve(Xd)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sv = V.solve(Xd)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        evv, _, rv, cv = V.eigpairs(vectors=False)
+        V.close()
+        ok = np.isfinite(evv) & np.isfinite(ev)
+        return {"s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
+                "fp32_cycles": sv["fp32_cycles"], "converged_pairs": int(cv.sum()),
+                "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
+                "max_resid_rel": float(np.nanmax(rv) / normA),
+                "max_rel_eig_diff_vs_timed": (float(np.max(np.abs(evv[ok] - ev[ok]) / np.abs(ev[ok])))
+                                              if ok.any() else None)}
+
     variants = {}
     if args.variants:
         forms = [("jacobi", "fp64", None), ("fsai", "fp64", None), ("fsai", "mixed", None),
@@ -326,43 +491,34 @@ def main():
         for pc, pr, mm in forms:
             if mm is None and (pc, pr) == (precond, precision):
                 continue
-            V = make_solver(pc, pr, method=mm)
-            V.solve(Xd)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            sv = V.solve(Xd)
-            torch.cuda.synchronize()
-            b = time.perf_counter()
-            evv, _, rv, cv = V.eigpairs(vectors=False)
-            V.close()
             label = f"{pc}-{pr}" if mm is None else f"{mm}-{pc}-{pr}"
-            log(f"# variant {label}: {sv['cycles']} cycles, {b - a:.3f} s")
-            variants[label] = {
-                "s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
-                "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
-                "max_resid_rel": float(np.max(rv) / normA),
-                "max_rel_eig_diff_vs_timed": float(np.max(np.abs(evv - ev) / np.abs(ev)))}
+            variants[label] = one(pc, pr, mm)
+            log(f"# variant {label}: {variants[label]['cycles']} cycles, {variants[label]['s']:.3f} s")
 
-    # ---- CPU oracle sample: a few cycles of the FP64 NumPy/SciPy oracle ----
+    # ---- complete solves (time to solution), outside the timed region ----
+    solutions = None
+    if args.converged and C:
+        solutions = {}
+        for pc, pr in [(precond, precision), ("jacobi", "fp64")]:
+            label = f"{pc}-{pr}"
+            log(f"# complete solve {label} (max {args.max_cycles} cycles)")
+            solutions[label] = one(pc, pr, cycles=args.max_cycles, warm=False)
+            log(f"# complete solve {label}: {solutions[label]['cycles']} cycles, "
+                f"{solutions[label]['matvecs']} MV, {solutions[label]['s']:.1f} s, "
+                f"{solutions[label]['converged_pairs']}/{P.p} pairs")
+
+    # ---- CPU oracle on the same input ----
     cpu = None
-    if args.cpu_cycles > 0:
-        from oracle import trplk as O
-        A = P.A.to_scipy()
-        B = None if P.B is None else P.B.to_scipy()
-        cores = len(os.sched_getaffinity(0))
-        c0 = time.perf_counter()
-        r = O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=O.jacobi(A),
-                    max_cycles=args.cpu_cycles)
-        c1 = time.perf_counter()
-        per_cycle = (c1 - c0) / r.cycles
-        cpu = {"value": round(per_cycle * st["cycles"], 2), "unit": "s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"{r.cycles} cycle(s) of the FP64 oracle (Jacobi, plus its start-block "
-                         f"Rayleigh-Ritz) on the same input took {c1 - c0:.1f} s; value = that per-cycle "
-                         f"time x the {st['cycles']} cycles of the timed GPU form. NumPy BLAS "
-                         f"threads = {cores}; SciPy SpMV single-threaded",
-               "per_cycle_s": round(per_cycle, 3)}
+    if args.cpu and args.method == "trplk":
+        X0h = splitmix64_block(P.A.n, P.k, P.seed) if C else start_block(P.A.n, P.k, P.seed)
+        cpu = cpu_oracle(P, X0h, C, st["cycles"], log)
+        del X0h
 
+    if C:
+        step_desc = (f"one step = {C} restart cycles of TRPL+K from the seeded start block "
+                     f"(drawn on the device, SplitMix64 seed {P.seed})")
+    else:
+        step_desc = "one step = one complete solve from the seeded start block"
     out = {
         "metric": "time & matvecs to p eigpairs at resid 1e-8; SpMV HBM GB/s vs peak",
         "value": round(ms_per_step / 1e3, 5),
@@ -376,20 +532,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l={P.l} tol=1e-8, "
-                               f"{precond} {precision}"
-                               + ("" if args.method == "trplk" else f", {args.method}"),
+        "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l={P.l} tol=1e-8*||A||_inf, "
+                               f"{'hard' if P.p > P.k else 'soft'} locking, {precond} {precision}"
+                               + ("" if args.method == "trplk" else f", {args.method}")
+                               + f"; {step_desc}",
                    "name": args.workload, "n": P.A.n, "nnz": P.A.nnz,
-                   "generalized": P.B is not None},
+                   "generalized": P.B is not None, "cycles_per_step": C or None},
         "converged": converged,
         "capped": st["status"] == 1,
         "ms_per_cycle": round(st["solve_ms"] / max(1, st["cycles"]), 3),
         "matvecs": st["matvecs"],
         "bmatvecs": st["bmatvecs"],
         "cycles": st["cycles"],
+        "pairs_returned": nret,
+        "converged_pairs": int(conv.sum()),
         "device_solve_ms": round(st["solve_ms"], 3),
         "setup_ms": round(st["setup_ms"], 3),
-        "max_resid_rel": float(np.max(res) / normA),
+        "max_resid_rel": float(np.nanmax(res) / normA) if nret else None,
         "checks": checks,
         "spmv_storage": (f"diagonals ({st['a_ndiag']})" if st["a_ndiag"] else "csr")
                         + (f", B: diagonals ({st['b_ndiag']})" if st["b_ndiag"] else "")
@@ -399,6 +558,7 @@ def main():
         "kernel_classes": {k: {kk: (round(v, 3) if isinstance(v, float) else v)
                                for kk, v in c.items()} for k, c in classes.items()},
         "variants": variants,
+        "time_to_solution": solutions,
         "learned": learn_info,
         "cpu_baseline": cpu,
     }

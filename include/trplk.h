@@ -114,7 +114,11 @@ typedef struct trplk_opts {
   int32_t precond;    /* TRPLK_PREC_* */
   int32_t precision;  /* TRPLK_FP64 or TRPLK_MIXED */
   int32_t locking;    /* TRPLK_LOCK_AUTO: soft when p <= k, else hard */
-  int32_t fsai_cap;   /* FSAI: keep at most this many entries per row (diagonal included), 0 = no cap, max 64 */
+  int32_t fsai_cap;   /* FSAI: keep at most this many entries per row of the factor (the
+                         diagonal and the fsai_cap - 1 largest |a_ij|, j < i; ties to the
+                         smaller column), 1..64.  0 = no cap: the whole lower pattern of
+                         each row; trplk_create then fails with EINVAL when a row has more
+                         than 64 lower-triangular entries (diagonal included) */
   int32_t profile;    /* 1 = time the SpMV and orthogonalisation kernels with HIP events */
   double mixed_switch; /* MIXED: switch SpMV to float64 once all target residuals are below
                           mixed_switch * ||A|| (or once they have not halved for 8 cycles:
@@ -130,6 +134,18 @@ typedef struct trplk_opts {
   double breakdown_tol; /* TRPL+K inner loop: stop the Krylov block when a new vector's
                            (B-)norm squared is at most breakdown_tol^2 (|h|^2 + norm^2),
                            h its Gram-Schmidt coefficients; 0 selects 1e-14, must be < 1 */
+  uint64_t seed;      /* start block drawn on the device when trplk_solve gets x0 = NULL: the
+                         paper starts from a seeded uniform random block (Sec. 5; default 12).
+                         Entry e of the column-major n x k block (e = column * n + row) is
+                         b * 2^-52 - 1, b the top 53 bits of SplitMix64's e-th output:
+                         mix(seed + (e + 1) * 0x9e3779b97f4a7c15) with mix(z) = z ^= z >> 30,
+                         z *= 0xbf58476d1ce4e5b9, z ^= z >> 27, z *= 0x94d049bb133111eb,
+                         z ^= z >> 31 (Steele, Lea and Flood, OOPSLA 2014), so any exact
+                         implementation of that definition reproduces the block */
+  int32_t progress;   /* > 0: TRPL+K writes one line to stderr every `progress` restart
+                         cycles (cycle, converged pairs, target residual, products);
+                         0 = silent */
+  int32_t pad_;
 } trplk_opts;
 
 typedef struct trplk_stats {
@@ -144,7 +160,9 @@ typedef struct trplk_stats {
   int32_t orth_delayed; /* 1 when the inner vectors used TRPLK_ORTH_DELAYED */
   double normA;        /* the ||A|| used in the stopping test */
   double solve_ms;     /* device time of trplk_solve (HIP events on the context stream) */
-  double setup_ms;     /* device time of trplk_create's preconditioner setup */
+  double setup_ms;     /* wall time of trplk_create: CSR upload, SpMV plans (including the
+                          host scan of the column pattern and the diagonal copies), norms,
+                          preconditioner, workspace; the stream drained at both ends */
   /* kernel profile (opts.profile = 1): summed device time and launch count */
   double spmv_ms;      int64_t spmv_launches;     int64_t spmv_bytes;
   double orth_ms;      int64_t orth_launches;     int64_t orth_bytes;
@@ -169,7 +187,8 @@ typedef struct trplk_ctx trplk_ctx;
 
 /* Fill *o with defaults: p=1 m=18 k=8 l=1 tol=1e-8 norm=INF max_cycles=5000
  * precond=JACOBI precision=FP64 locking=AUTO fsai_cap=0 profile=0 method=TRPLK
- * orth=AUTO. */
+ * orth=AUTO seed=12 (the settings of the paper's experiments, Sec. 5, with
+ * its maxBasisSize 18 and minRestartSize 8). */
 void trplk_default_opts(trplk_opts* o);
 
 /* Create a solver context for the pencil (A, B) (paper eq. (1.1)).
@@ -182,25 +201,56 @@ void trplk_default_opts(trplk_opts* o);
 int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B,
                  const trplk_opts* o, int32_t mem, void* stream);
 
-/* Install M = G^T G with G sparse lower triangular with a positive diagonal
- * (e.g. the learned factor); switches the context to TRPLK_PREC_FACTOR.
- * G in host or device memory per `mem`; it is copied.  Errors: EINVAL when G
- * is not square n x n, not lower triangular, or a diagonal entry is missing. */
+/* Bytes of caller workspace trplk_create_ws needs for a pencil of order n
+ * (has_b != 0: B != I) under options o: the basis W = [Q | U] (hard locking:
+ * p + m columns, else m), A W, B W (has_b), the l previous Ritz vectors
+ * (Sec. 3, +K) and the n-vectors of one inner step (eq. (3.1)), each column
+ * padded to a multiple of 32 doubles and each piece to 256 bytes.  -1 when
+ * the options are invalid for n. */
+int64_t trplk_workspace_size(int32_t n, int32_t has_b, const trplk_opts* o);
+
+/* trplk_create with the n-length solver workspace supplied by the caller (a
+ * framework's allocator owns the memory): `workspace` is device memory of
+ * the current device, 256-byte aligned, at least trplk_workspace_size(n,
+ * B != NULL, o) bytes, owned by the caller and left untouched by
+ * trplk_destroy; it must outlive the context and no other context may use
+ * it at the same time.  The library still allocates the setup structures
+ * (SpMV plans, diagonal copies, the preconditioner, host-copied CSR arrays)
+ * and buffers of O(m^2) doubles and of one reduction partial per workgroup.
+ * Errors: those of trplk_create, and EINVAL for a NULL, misaligned or too
+ * small workspace. */
+int trplk_create_ws(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B,
+                    const trplk_opts* o, int32_t mem, void* stream, void* workspace,
+                    int64_t workspace_bytes);
+
+/* Install the preconditioner M = G^T G (M approximates the inverse of the
+ * shifted operator, paper Sec. 2.2; applied in the inner step as
+ * M (A g - rho B g), eq. (3.1)) for G sparse lower triangular with a positive
+ * diagonal (e.g. the learned factor); switches the context to
+ * TRPLK_PREC_FACTOR.  G in host or device memory per `mem`; it is copied.
+ * Errors: EINVAL when G is not n x n, or (host memory only) not lower
+ * triangular, a diagonal entry missing or not positive.  A device-memory G
+ * is taken as given: its structure is not checked. */
 int trplk_set_factor(trplk_ctx* ctx, const trplk_csr* G, int32_t mem);
 
 /* Run TRPL+K (paper Alg. 1 with eq. (3.1) and the +K placement of Sec. 3;
  * generalized form with B-inner products, Sec. 3 and Alg. 2).
  * x0: n x k start block, column-major, any full-rank block (it is
- * B-orthonormalised first); host or device per `mem`; NULL is EINVAL.
+ * B-orthonormalised first); host or device per `mem`; NULL draws the block
+ * on the device from opts.seed (see trplk_opts.seed).  PL+1 uses column 0.
  * st: optional, filled on return.  Returns OK when all p pairs converged,
  * ENOCONV after max_cycles (results are still available), or an error. */
 int trplk_solve(trplk_ctx* ctx, const double* x0, int32_t mem, trplk_stats* st);
 
-/* Copy the result of the last solve: evals (p, ascending), evecs (n x p,
- * column-major, B-orthonormal; may be NULL), resid (p; the residual norms
- * ||A x - theta B x||_2 / ||x||_2 recomputed with fresh float64 products;
- * may be NULL), conv (p flags; may be NULL).  `mem` applies to every output.
- * Errors: EINVAL before a successful solve. */
+/* Copy the result of the last solve, the outputs theta_i, x_i of Alg. 1:
+ * evals (p, ascending), evecs (n x p, column-major, B-orthonormal; may be
+ * NULL), resid (p; the residual norms ||A x - theta B x||_2 / ||x||_2 of
+ * eq. (5.1) recomputed with fresh float64 products; may be NULL), conv (p
+ * flags: resid <= tol ||A||; may be NULL).  `mem` applies to every output.
+ * A hard-locking solve stopped by max_cycles before the locked and active
+ * vectors number p returns fewer pairs: the missing entries are NaN (evals,
+ * resid), 0 (conv) and left unwritten (evecs).  Returns after the stream has
+ * drained.  Errors: EINVAL before a successful solve or for a bad `mem`. */
 int trplk_get_eigpairs(trplk_ctx* ctx, double* evals, double* evecs, double* resid,
                        int32_t* conv, int32_t mem);
 
@@ -243,15 +293,36 @@ int trplk_factor_values(trplk_ctx* ctx, double* val, int32_t mem);
 int trplk_factor_loss_grad(trplk_ctx* ctx, const float* params, int32_t S, const double* E,
                            const double* R, int32_t mem, double* loss, double* grad);
 
-/* One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the
- * pairs (u, A u) the last trplk_solve on this context left in its basis (the
- * first S <= min(m, 64) stored columns and their products: the kept Ritz
- * vectors followed by the last cycle's inner Krylov vectors).  params,
- * adam_m, adam_v: host arrays of TRPLK_MLP_NPARAM floats, updated in place;
- * step: Adam step count (>= 1); loss: optional output (before the update).
+/* One Adam step (Kingma and Ba, Algorithm 1: beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected moments; float32 state) on the pairs (u, A u)
+ * the last trplk_solve on this context left in its basis (the first
+ * S <= min(m, 64) stored columns and their products: the kept Ritz vectors
+ * followed by the last cycle's inner Krylov vectors).  params, adam_m,
+ * adam_v: host arrays of TRPLK_MLP_NPARAM floats, updated in place; step:
+ * Adam step count (>= 1); loss: optional output (before the update); grad:
+ * optional output of the TRPLK_MLP_NPARAM-double gradient the step used.
  * Call it on several contexts in turn to train on several problems. */
 int trplk_train_step(trplk_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
-                     double lr, int32_t S, double* loss);
+                     double lr, int32_t S, double* loss, double* grad);
+
+/* Convergence history of the last solve: theta1[c] = the smallest Ritz
+ * value of the active basis after the Rayleigh-Ritz of restart cycle c + 1
+ * (Alg. 1; with hard locking the smallest not yet locked), or for PL+1 the
+ * Rayleigh quotient rho(x_{c+1}) after outer step c + 1 (Alg. 2) -- the
+ * rho(x_k) of the quasi-optimality ratio of Sec. 4.3.  Host
+ * memory, at most cap values written.  Returns the number of cycles
+ * recorded, or a negative status (EINVAL before a completed solve). */
+int32_t trplk_get_history(trplk_ctx* ctx, double* theta1, int32_t cap);
+
+/* The factor G of the installed preconditioner M = G^T G (Sec. 2.2: M
+ * approximates the inverse of the shifted operator): the FSAI factor built
+ * by trplk_create, the learned factor or the one given to trplk_set_factor,
+ * as CSR (n + 1 row pointers, nnz columns sorted within a row, nnz values;
+ * host or device memory per `mem`).  With rowptr, col and val all NULL it
+ * only returns nnz.  Returns nnz, or a negative status (EINVAL when no
+ * factor is installed). */
+int64_t trplk_get_factor(trplk_ctx* ctx, int32_t* rowptr, int32_t* col, double* val,
+                         int32_t mem);
 
 /* Bytes of device memory the context holds (matrices, preconditioner and the
  * solver workspace sized for its options). */
@@ -261,6 +332,8 @@ int64_t trplk_device_bytes(const trplk_ctx* ctx);
  * failed trplk_create when ctx is NULL). */
 const char* trplk_last_error(const trplk_ctx* ctx);
 
+/* Release the context and every device buffer it allocated (not a caller
+ * workspace); waits for the context stream first.  NULL is a no-op. */
 void trplk_destroy(trplk_ctx* ctx);
 
 /* ------------------------------------------------------------------------

@@ -50,7 +50,8 @@ class _Opts(ctypes.Structure):
                 ("fsai_cap", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("orth", ctypes.c_int32),
-                ("breakdown_tol", ctypes.c_double)]
+                ("breakdown_tol", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("progress", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -84,11 +85,13 @@ class _Stats(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_set_factor", "trplk_solve",
+EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_workspace_size", "trplk_create_ws",
+           "trplk_set_factor", "trplk_solve",
            "trplk_get_eigpairs", "trplk_device_bytes", "trplk_last_error", "trplk_destroy",
            "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
            "trplk_rotate", "trplk_learned_factor", "trplk_factor_nnz", "trplk_factor_values",
-           "trplk_factor_loss_grad", "trplk_train_step"]
+           "trplk_factor_loss_grad", "trplk_train_step", "trplk_get_factor",
+           "trplk_get_history"]
 MLP_NPARAM = 1217
 MLP_NF, MLP_NIN, MLP_NH = 8, 17, 64
 
@@ -108,6 +111,11 @@ def lib():
     L.trplk_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
                                ctypes.POINTER(_Opts), i32, vp]
     L.trplk_create.restype = ctypes.c_int
+    L.trplk_workspace_size.argtypes = [i32, i32, ctypes.POINTER(_Opts)]
+    L.trplk_workspace_size.restype = i64
+    L.trplk_create_ws.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
+                                  ctypes.POINTER(_Opts), i32, vp, vp, i64]
+    L.trplk_create_ws.restype = ctypes.c_int
     L.trplk_set_factor.argtypes = [vp, ctypes.POINTER(_Csr), i32]
     L.trplk_set_factor.restype = ctypes.c_int
     L.trplk_solve.argtypes = [vp, vp, i32, ctypes.POINTER(_Stats)]
@@ -137,8 +145,12 @@ def lib():
     L.trplk_factor_values.restype = ctypes.c_int
     L.trplk_factor_loss_grad.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
     L.trplk_factor_loss_grad.restype = ctypes.c_int
-    L.trplk_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp]
+    L.trplk_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp]
     L.trplk_train_step.restype = ctypes.c_int
+    L.trplk_get_history.argtypes = [vp, vp, i32]
+    L.trplk_get_history.restype = i32
+    L.trplk_get_factor.argtypes = [vp, vp, vp, vp, i32]
+    L.trplk_get_factor.restype = i64
     _lib = L
     return L
 
@@ -185,14 +197,18 @@ def _host_csr(csr, keep):
 class Solver:
     """One TRPL+K context on the current HIP device.
 
-    A, B   CSR matrices: objects with n/rowptr/col/val numpy arrays (copied
-           to the device by the library) or DeviceCSR (referenced)
+    A, B       CSR matrices: objects with n/rowptr/col/val numpy arrays (copied
+               to the device by the library) or DeviceCSR (referenced)
+    seed       start block drawn on the device when solve() gets no X0
+    workspace  True: the n-length solver workspace is a torch tensor owned
+               here and handed to trplk_create_ws (the library allocates the
+               rest); False: the library allocates everything
     """
 
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
                  profile=False, mixed_switch=0.0, fallback_window=0, method="trplk",
-                 orth="auto", breakdown_tol=0.0):
+                 orth="auto", breakdown_tol=0.0, seed=12, workspace=False, progress=0):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -204,6 +220,8 @@ class Solver:
         o.method = METHOD[method]
         o.orth = ORTH[orth]
         o.breakdown_tol = breakdown_tol
+        o.seed = seed
+        o.progress = progress
         self.opts = o
         self.n = int(A.n)
         self.p = p
@@ -217,9 +235,22 @@ class Solver:
             cb = _host_csr(B, keep) if B is not None else None
         self._refs = (A, B)
         ctx = ctypes.c_void_p()
-        code = L.trplk_create(ctypes.byref(ctx), ctypes.byref(ca),
-                              ctypes.byref(cb) if cb is not None else None, ctypes.byref(o),
-                              MEM_DEVICE if dev else MEM_HOST, _stream())
+        self.workspace = None
+        if workspace:
+            import torch
+            nbytes = int(L.trplk_workspace_size(self.n, int(B is not None), ctypes.byref(o)))
+            if nbytes < 0:
+                raise TrplkError(-1, "invalid options for trplk_workspace_size")
+            # torch's caching allocator returns 512-byte aligned blocks
+            self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+            code = L.trplk_create_ws(ctypes.byref(ctx), ctypes.byref(ca),
+                                     ctypes.byref(cb) if cb is not None else None,
+                                     ctypes.byref(o), MEM_DEVICE if dev else MEM_HOST, _stream(),
+                                     _ptr(self.workspace), nbytes)
+        else:
+            code = L.trplk_create(ctypes.byref(ctx), ctypes.byref(ca),
+                                  ctypes.byref(cb) if cb is not None else None, ctypes.byref(o),
+                                  MEM_DEVICE if dev else MEM_HOST, _stream())
         _check(code, None)
         self.ctx = ctx
         self.stats = None
@@ -230,18 +261,26 @@ class Solver:
         cg = _host_csr(G, keep)
         _check(lib().trplk_set_factor(self.ctx, ctypes.byref(cg), MEM_HOST), self.ctx)
 
-    def solve(self, X0):
+    def solve(self, X0=None):
         """Run the solver from the start block X0 (n x k): numpy (column-major
-        is produced here) or a torch device tensor laid out column-major
-        (i.e. X0.T contiguous)."""
+        is produced here), a torch device tensor holding the column-major
+        block as a contiguous (k, n) tensor (PL+1: (1, n) or more rows), or
+        None (the block is drawn on the device from the seed)."""
         import torch
         st = _Stats()
-        if isinstance(X0, torch.Tensor):
-            assert X0.is_cuda and X0.dtype == torch.float64
+        if X0 is None:
+            code = lib().trplk_solve(self.ctx, None, MEM_HOST, ctypes.byref(st))
+        elif isinstance(X0, torch.Tensor):
+            cols = self.k if self.opts.method == METHOD["trplk"] else 1
+            if not (X0.is_cuda and X0.dtype == torch.float64 and X0.is_contiguous()
+                    and X0.dim() == 2 and X0.shape[1] == self.n and X0.shape[0] >= cols):
+                raise ValueError(f"X0 must be a contiguous float64 CUDA tensor of shape "
+                                 f"({cols}, {self.n}) (the column-major n x {cols} block)")
             code = lib().trplk_solve(self.ctx, _ptr(X0), MEM_DEVICE, ctypes.byref(st))
         else:
             X = np.asfortranarray(X0, dtype=np.float64)
-            assert X.shape == (self.n, self.k)
+            if X.shape != (self.n, self.k):
+                raise ValueError(f"X0 must be {self.n} x {self.k}")
             code = lib().trplk_solve(self.ctx, X.ctypes.data_as(ctypes.c_void_p), MEM_HOST,
                                      ctypes.byref(st))
         _check(code, self.ctx)
@@ -284,16 +323,38 @@ class Solver:
                                             ctypes.byref(loss), grad.ctypes.data_as(vp)), self.ctx)
         return loss.value, grad
 
-    def train_step(self, params, m, v, step, lr, S):
-        """One Adam step on the pairs of the last solve; arrays updated in place."""
+    def train_step(self, params, m, v, step, lr, S, grad=None):
+        """One Adam step on the pairs of the last solve; arrays updated in
+        place.  grad: optional float64 array that receives the gradient."""
         loss = ctypes.c_double()
         vp = ctypes.c_void_p
         for a in (params, m, v):
             assert a.dtype == np.float32 and a.flags.c_contiguous and a.shape == (MLP_NPARAM,)
+        if grad is not None:
+            assert grad.dtype == np.float64 and grad.flags.c_contiguous and grad.shape == (MLP_NPARAM,)
         _check(lib().trplk_train_step(self.ctx, params.ctypes.data_as(vp), m.ctypes.data_as(vp),
-                                      v.ctypes.data_as(vp), step, lr, S, ctypes.byref(loss)),
+                                      v.ctypes.data_as(vp), step, lr, S, ctypes.byref(loss),
+                                      grad.ctypes.data_as(vp) if grad is not None else None),
                self.ctx)
         return loss.value
+
+    def history(self):
+        """Smallest active Ritz value after each restart cycle of the last solve."""
+        nc = _check(int(lib().trplk_get_history(self.ctx, None, 0)), self.ctx)
+        h = np.empty(max(nc, 1))
+        _check(int(lib().trplk_get_history(self.ctx, h.ctypes.data_as(ctypes.c_void_p), nc)),
+               self.ctx)
+        return h[:nc]
+
+    def factor(self):
+        """The installed factor G (M = G^T G) as (rowptr, col, val) numpy arrays."""
+        nnz = _check(int(lib().trplk_get_factor(self.ctx, None, None, None, MEM_HOST)), self.ctx)
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        cl = np.empty(max(nnz, 1), dtype=np.int32)
+        vl = np.empty(max(nnz, 1))
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(int(lib().trplk_get_factor(self.ctx, vp(rp), vp(cl), vp(vl), MEM_HOST)), self.ctx)
+        return rp, cl[:nnz], vl[:nnz]
 
     def device_bytes(self):
         return int(lib().trplk_device_bytes(self.ctx))

@@ -2,8 +2,9 @@
 // the GPU, and the CSR transpose used to apply M = G^T G.
 //
 // For each row i the pattern P_i is the lower-triangular part of row i of A
-// (columns <= i), capped to the `cap` entries of largest magnitude with the
-// diagonal always kept (ties: smaller column first).  G(i, P_i) = y /
+// (columns <= i); with a cap, rows longer than `cap` keep the cap - 1
+// off-diagonal entries of largest magnitude and the diagonal (ties: smaller
+// column first).  Without a cap a row may hold at most FS = 64 lower entries.  G(i, P_i) = y /
 // sqrt(y_i) with A(P_i, P_i) y = e_i, so (G A)(i, j) = 0 for j in P_i \ {i}
 // and (G A G^T)(i, i) = 1.  One wavefront owns one row: it selects the
 // pattern, gathers the local s x s matrix (s <= 64) into LDS with binary
@@ -38,16 +39,24 @@ __device__ __forceinline__ int diag_pos(const int* col, int beg, int end, int i)
   return pos;
 }
 
+// bad: bit 0 = a row without its diagonal entry, bit 1 = a row whose lower
+// pattern is longer than the local solve holds (FS) with no cap given
 __global__ void k_fsai_count(int n, const int* rowptr, const int* col, int cap, int* cnt, int* bad) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int beg = rowptr[i], end = rowptr[i + 1];
     const int dp = diag_pos(col, beg, end, i);
     if (dp < beg || col[dp] != i) {
-      *bad = 1;
+      atomicOr(bad, 1);
       cnt[i] = 0;
       continue;
     }
-    cnt[i] = min(dp - beg + 1, cap);
+    const int len = dp - beg + 1;
+    if (cap == 0 && len > FS) {
+      atomicOr(bad, 2);
+      cnt[i] = 0;
+      continue;
+    }
+    cnt[i] = cap > 0 ? min(len, cap) : len;
   }
 }
 
@@ -75,9 +84,10 @@ __global__ __launch_bounds__(WAVE) void k_fsai_rows(int n, const int* rowptr, co
     const int dp = diag_pos(col, beg, end, i);
     if (dp < beg || col[dp] != i) continue;  // reported by the count kernel
     const int len = dp - beg + 1;            // lower entries incl. diagonal
-    const int s = min(len, cap);
+    if (cap == 0 && len > FS) continue;      // reported by the count kernel
+    const int s = cap > 0 ? min(len, cap) : len;
     // ---- pattern ----
-    if (len <= cap) {
+    if (len == s) {
       for (int a = lane; a < s; a += WAVE) P[a] = col[beg + a];
     } else {
       // keep the cap-1 largest |a_ij| (j < i), ties to the smaller column
@@ -129,7 +139,7 @@ __global__ __launch_bounds__(WAVE) void k_fsai_rows(int n, const int* rowptr, co
       __syncthreads();
     }
     if (fail) {
-      if (lane == 0) *bad = 1;
+      if (lane == 0) atomicOr(bad, 1);
       continue;
     }
     // ---- L^T y = z, z = e_s / L(s-1,s-1); lane a owns y_a ----
@@ -197,7 +207,9 @@ hipError_t fsai_build(int n, const int* rowptr, const int* col, const double* va
   *g_rowptr = nullptr;
   *g_col = nullptr;
   *g_val = nullptr;
-  const int ecap = (cap > 0 && cap < FS) ? cap : FS;
+  // cap = 0: the whole lower pattern of every row (rows longer than FS are
+  // rejected through `bad`); otherwise at most cap <= FS entries per row
+  const int ecap = cap > 0 ? std::min(cap, FS) : 0;
   int* cnt = nullptr;
   int* bad = nullptr;
   hipError_t e = hipMalloc(&cnt, sizeof(int) * (n + 1));

@@ -29,6 +29,8 @@
 // training step is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 
 #include "common.h"
@@ -414,14 +416,16 @@ __global__ void k_sum_small(int nblk, const double* part, double* out) {
 }
 
 // Adam (Kingma and Ba), float32 parameters and moments, step count t >= 1
-__global__ void k_adam(float* P, float* m, float* v, const double* grad, int t, float lr, float b1,
-                       float b2, float eps) {
-  const float c1 = 1.0f - powf(b1, static_cast<float>(t));
-  const float c2 = 1.0f - powf(b2, static_cast<float>(t));
+// Adam (Kingma and Ba, Algorithm 1) in float32.  The weights 1 - beta and
+// the bias corrections 1 - beta^t come from the host, formed in float64 and
+// rounded once: 1 - 0.999f in float32 is 0.99998713e-3, 1.3e-5 off the
+// method's 1e-3.
+__global__ void k_adam(float* P, float* m, float* v, const double* grad, float lr, float b1,
+                       float om1, float b2, float om2, float c1, float c2, float eps) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < NP; p += gridDim.x * blockDim.x) {
     const float g = static_cast<float>(grad[p]);
-    m[p] = b1 * m[p] + (1.0f - b1) * g;
-    v[p] = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = b1 * m[p] + om1 * g;
+    v[p] = b2 * v[p] + om2 * (g * g);
     const float mh = m[p] / c1, vh = v[p] / c2;
     P[p] -= lr * mh / (sqrtf(vh) + eps);
   }
@@ -566,7 +570,11 @@ hipError_t gather_values(int64_t nnz, const double* src, const double* permd, do
 
 hipError_t adam_step(float* P, float* m, float* v, const double* grad, int t, float lr,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(8), dim3(256), 0, s, P, m, v, grad, t, lr, 0.9f, 0.999f, 1e-8f);
+  const double b1 = 0.9, b2 = 0.999;
+  hipLaunchKernelGGL(k_adam, dim3(8), dim3(256), 0, s, P, m, v, grad, lr, static_cast<float>(b1),
+                     static_cast<float>(1.0 - b1), static_cast<float>(b2), static_cast<float>(1.0 - b2),
+                     static_cast<float>(1.0 - std::pow(b1, t)), static_cast<float>(1.0 - std::pow(b2, t)),
+                     1e-8f);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -107,6 +108,7 @@ struct trplk_ctx {
   double* YA = nullptr;     // delayed form: Lm Y, the rotation coefficients of AU
   double* partial = nullptr;
   double* resout = nullptr;
+  double* thout = nullptr;  // Ritz values of the returned pairs (get_eigpairs)
   DevState* st = nullptr;
   Report* rep_h = nullptr;
   Report* rep_d = nullptr;
@@ -114,6 +116,8 @@ struct trplk_ctx {
   int64_t partial_bytes = 0;
   int64_t partial_cap = 0;  // doubles in `partial`
   bool ws_ready = false;
+  void* ws_base = nullptr;  // caller's workspace (trplk_create_ws), not owned
+  int64_t ws_size = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> evpool;
   std::vector<Prof> prof;
@@ -124,6 +128,7 @@ struct trplk_ctx {
   int nout = 0;           // result columns in W starting at column 0
   std::vector<double> theta_out, res_out;
   std::vector<int> conv_out;
+  std::vector<double> hist;  // smallest active Ritz value after each cycle's Rayleigh-Ritz
   trplk_stats stats{};
   std::string err;
   int64_t dev_bytes = 0;
@@ -307,27 +312,77 @@ struct ProfScope {
 };
 
 // ------------------------------------------------------------ workspace --
+// The n-length part of the solver workspace: W = [Q | U], A W, B W, the
+// previous Ritz vectors, PL+1's search-direction products and the n-vectors.
+// It is carved in this order from one region (256-byte aligned pieces): the
+// caller's workspace (trplk_create_ws) or one allocation per piece.
+struct WsPiece {
+  void** ptr;
+  int64_t bytes;
+};
+
+bool hard_locking(const trplk_opts& o) {
+  return (o.locking == TRPLK_LOCK_HARD) || (o.locking == TRPLK_LOCK_AUTO && o.p > o.k);
+}
+
+int64_t ws_align(int64_t b) { return (b + 255) / 256 * 256; }
+
+void ws_pieces(trplk_ctx* c, std::vector<WsPiece>& out) {
+  const trplk_opts& o = c->o;
+  const int64_t ld = (static_cast<int64_t>(c->n) + 31) / 32 * 32;
+  const int64_t cols = (hard_locking(o) ? o.p : 0) + o.m;
+  const int64_t d = 8 * ld, f = 4 * ld;
+  out.clear();
+  out.push_back({reinterpret_cast<void**>(&c->W), d * cols});
+  out.push_back({reinterpret_cast<void**>(&c->AW), d * cols});
+  if (c->hasB) out.push_back({reinterpret_cast<void**>(&c->BW), d * cols});
+  out.push_back({reinterpret_cast<void**>(&c->Xprev), d * std::max(o.l, 1)});
+  out.push_back({reinterpret_cast<void**>(&c->pl1_Ap), d});
+  if (c->hasB) out.push_back({reinterpret_cast<void**>(&c->pl1_Bp), d});
+  out.push_back({reinterpret_cast<void**>(&c->w), d});
+  out.push_back({reinterpret_cast<void**>(&c->wtmp), d});
+  out.push_back({reinterpret_cast<void**>(&c->vtmp), d});
+  out.push_back({reinterpret_cast<void**>(&c->ytmp), d});
+  if (c->hasB) out.push_back({reinterpret_cast<void**>(&c->tmpB), d});
+  out.push_back({reinterpret_cast<void**>(&c->v32), f});
+  out.push_back({reinterpret_cast<void**>(&c->y32), f});
+  out.push_back({reinterpret_cast<void**>(&c->wtmp32), f});
+}
+
+int64_t ws_bytes_needed(trplk_ctx* c) {
+  std::vector<WsPiece> pcs;
+  ws_pieces(c, pcs);
+  int64_t b = 0;
+  for (const WsPiece& q : pcs) b += ws_align(q.bytes);
+  return b;
+}
+
 int ensure_workspace(trplk_ctx* c) {
   if (c->ws_ready) return TRPLK_OK;
   const int n = c->n;
   const trplk_opts& o = c->o;
   c->m = o.m;
   c->ld = (static_cast<int64_t>(n) + 31) / 32 * 32;
-  const bool hard = (o.locking == TRPLK_LOCK_HARD) || (o.locking == TRPLK_LOCK_AUTO && o.p > o.k);
-  c->pcap = hard ? o.p : 0;
-  const int64_t cols = c->pcap + c->m;
-  HIPCHK(c, dalloc(c, &c->W, c->ld * cols));
-  HIPCHK(c, dalloc(c, &c->AW, c->ld * cols));
-  if (c->hasB) HIPCHK(c, dalloc(c, &c->BW, c->ld * cols));
-  HIPCHK(c, dalloc(c, &c->w, c->ld));
-  HIPCHK(c, dalloc(c, &c->wtmp, c->ld));
-  HIPCHK(c, dalloc(c, &c->vtmp, c->ld));
-  HIPCHK(c, dalloc(c, &c->ytmp, c->ld));
-  if (c->hasB) HIPCHK(c, dalloc(c, &c->tmpB, c->ld));
-  HIPCHK(c, dalloc(c, &c->v32, c->ld));
-  HIPCHK(c, dalloc(c, &c->y32, c->ld));
-  HIPCHK(c, dalloc(c, &c->wtmp32, c->ld));
-  HIPCHK(c, dalloc(c, &c->Xprev, c->ld * std::max(o.l, 1)));
+  c->pcap = hard_locking(o) ? o.p : 0;
+  std::vector<WsPiece> pcs;
+  ws_pieces(c, pcs);
+  if (c->ws_base) {
+    const int64_t need = ws_bytes_needed(c);
+    if (c->ws_size < need)
+      return set_err(c, TRPLK_EINVAL, "workspace smaller than trplk_workspace_size()");
+    char* base = static_cast<char*>(c->ws_base);
+    int64_t off = 0;
+    for (const WsPiece& q : pcs) {
+      *q.ptr = base + off;
+      off += ws_align(q.bytes);
+    }
+  } else {
+    for (const WsPiece& q : pcs) {
+      char* ptr = nullptr;
+      HIPCHK(c, dalloc(c, &ptr, static_cast<size_t>(q.bytes)));
+      *q.ptr = ptr;
+    }
+  }
   HIPCHK(c, dalloc(c, &c->T, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->theta, SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->Y, SYEV_MAXB * SYEV_MAXB));
@@ -336,6 +391,8 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &c->Lm, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->YA, SYEV_MAXB * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->thout, SYEV_MAXB));
+  HIPCHK(c, dalloc(c, &c->pl1_s, 2 * ORTH_MAXCOL));
   c->orth_nblk = orth_blocks_max(n);
   c->rot_nblk = rot_blocks(n);
   int64_t pb = static_cast<int64_t>(c->orth_nblk) * orth_stride();
@@ -353,6 +410,29 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, hipEventCreate(&c->ev1));
   c->ws_ready = true;
   return TRPLK_OK;
+}
+
+// ---------------------------------------------------------- start block --
+// The default start block is uniform on [-1, 1) (the paper starts from a
+// seeded random block, Sec. 5).  Entry e of the column-major n x k block is
+// the e-th output of SplitMix64 (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014) seeded with `seed`: the
+// state seed + (e + 1) * gamma, gamma = 0x9e3779b97f4a7c15, through the
+// generator's 64-bit finaliser; its top 53 bits b give b * 2^-52 - 1.  The
+// scaling is exact and the subtraction rounds once, so any IEEE
+// implementation of the same definition produces the same doubles.
+__device__ __forceinline__ uint64_t splitmix64_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_start_column(int n, uint64_t seed, uint64_t first, double* w) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t e = first + static_cast<uint64_t>(i);
+    const uint64_t z = splitmix64_out(seed + (e + 1ull) * 0x9e3779b97f4a7c15ull);
+    w[i] = static_cast<double>(z >> 11) * 0x1.0p-52 - 1.0;
+  }
 }
 
 // ------------------------------------------------------------- building --
@@ -652,7 +732,15 @@ struct Solver {
     return TRPLK_OK;
   }
 
-  int load_w(const double* src, int32_t mem) {
+  // Column j of the start block into w: copied from src, or, when src is
+  // NULL, drawn on the device from the seeded counter-based stream.
+  int load_w(const double* src, int32_t mem, int j) {
+    if (!src) {
+      hipLaunchKernelGGL(k_start_column, dim3(std::max(1, std::min((n + 255) / 256, 4096))), dim3(256), 0, s, n, c->o.seed,
+                         static_cast<uint64_t>(j) * static_cast<uint64_t>(n), c->w);
+      HIPCHK(c, hipGetLastError());
+      return TRPLK_OK;
+    }
     HIPCHK(c, hipMemcpyAsync(c->w, src, sizeof(double) * n,
                              mem == TRPLK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
     return TRPLK_OK;
@@ -855,6 +943,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   c->u0 = 0;
   c->solved = false;
   c->fp32_phase = (o.precision == TRPLK_MIXED);
+  c->hist.clear();
   dc = o.orth != TRPLK_ORTH_CGS2;
   stt.orth_delayed = dc ? 1 : 0;
   int r;
@@ -864,7 +953,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   // ---- start block: B-orthonormalise X0 column by column, A X0, T0 ----
   nbh = 0;
   for (int j = 0; j < k; ++j) {
-    if ((r = load_w(x0 + static_cast<int64_t>(j) * n, mem))) return r;
+    if ((r = load_w(x0 ? x0 + static_cast<int64_t>(j) * n : nullptr, mem, j))) return r;
     if ((r = add_vector(BREAKDOWN_TOL))) return r;
   }
   if ((r = rayleigh_ritz(k, std::min(k, SYEV_MAXB)))) return r;
@@ -929,7 +1018,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       // last appended vector is corrected at the end
       for (int j = 0; j < nprev; ++j) {
         if ((r = stage_reset(PLUSK_DROP_TOL))) return r;
-        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
+        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE, j))) return r;
         if ((r = dc_step(true, true))) return r;
         if ((r = append(0))) return r;
       }
@@ -937,7 +1026,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       nbh += nprev;
     } else {
       for (int j = 0; j < nprev; ++j) {
-        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE))) return r;
+        if ((r = load_w(c->Xprev + j * ld, TRPLK_MEM_DEVICE, j))) return r;
         if ((r = add_vector(PLUSK_DROP_TOL))) return r;
       }
     }
@@ -954,6 +1043,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
     prev_app = R.cnt_append;
     const int kk = std::min(kout, R.nb);
     th.assign(R.theta, R.theta + kk);
+    c->hist.push_back(kk > 0 ? th[0] : NAN);
     res.assign(R.res, R.res + kk);
     nprev = lcnt;
     th_off = 0;
@@ -993,6 +1083,13 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
         break;
       }
       if (kact <= 0) return set_err(c, TRPLK_EINVAL, "restart size exhausted by locking");
+    }
+    if (o.progress > 0 && cycle % o.progress == 0) {
+      const int tt = hard ? 0 : std::min<int>(t, static_cast<int>(res.size()) - 1);
+      std::fprintf(stderr, "trplk: cycle %d  converged %d/%d  target residual %.3e (threshold %.3e)  MV %lld\n",
+                   cycle, hard ? c->u0 : t, p, res.empty() ? 0.0 : res[std::max(tt, 0)], thr,
+                   static_cast<long long>(stt.matvecs));
+      std::fflush(stderr);
     }
     // a factor preconditioner that stops making progress hands over to
     // Jacobi; the residuals (float64, true A and B) decide convergence
@@ -1149,17 +1246,15 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
   c->u0 = 0;
   c->solved = false;
   c->fp32_phase = false;
+  c->hist.clear();
   int r;
-  if (!c->pl1_Ap) HIPCHK(c, dalloc(c, &c->pl1_Ap, c->ld));
-  if (c->hasB && !c->pl1_Bp) HIPCHK(c, dalloc(c, &c->pl1_Bp, c->ld));
-  if (!c->pl1_s) HIPCHK(c, dalloc(c, &c->pl1_s, 2 * ORTH_MAXCOL));
   HIPCHK(c, hipEventRecord(c->ev0, s));
   HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
   HIPCHK(c, hipMemsetAsync(c->T, 0, sizeof(double) * SYEV_MAXB * SYEV_MAXB, s));
   // ---- x_0: B-normalised, A x_0, rho_0 = x_0^T A x_0, r_0 ----
   skip0 = 0;
   nbh = 0;
-  if ((r = load_w(x0, mem))) return r;
+  if ((r = load_w(x0, mem, 0))) return r;
   if ((r = add_vector(BREAKDOWN_TOL))) return r;
   if ((r = rayleigh_ritz(1, 1))) return r;
   if (c->rep_h->nb != 1) return set_err(c, TRPLK_EINVAL, "start vector is zero");
@@ -1324,6 +1419,7 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
     have_p = true;
     rho_prev = rho;
     rho = lambda;
+    c->hist.push_back(rho);
     res = c->rep_h->res[0];
     done = res <= thr;
   }
@@ -1427,6 +1523,9 @@ int trplk_internal_build_fsai(trplk_ctx* c) {
   c->G.nnz = nnz;
   c->G.owned = true;
   c->dev_bytes += nnz * 12 + 4 * (c->n + 1);
+  if (bad & 2)
+    return set_err(c, TRPLK_EINVAL,
+                   "FSAI: a row has more than 64 lower-triangular entries; set fsai_cap (<= 64)");
   if (bad) return set_err(c, TRPLK_ENOTSPD, "FSAI: missing diagonal or a local matrix is not SPD");
   return finish_factor(c);
 }
@@ -1647,7 +1746,7 @@ int trplk_factor_loss_grad(trplk_ctx* c, const float* params, int32_t S, const d
 }
 
 int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, int32_t step,
-                     double lr, int32_t S, double* loss) {
+                     double lr, int32_t S, double* loss, double* grad) {
   if (!c || !params || !adam_m || !adam_v) return set_err(c, TRPLK_EINVAL, "null argument");
   if (step < 1) return set_err(c, TRPLK_EINVAL, "step counts from 1");
   if (S < 1 || S > LEARN_MAXS || S > c->m) return set_err(c, TRPLK_EINVAL, "S must be in 1..min(64, m)");
@@ -1673,6 +1772,8 @@ int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, 
   HIPCHK(c, hipMemcpyAsync(adam_m, L.am, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
   HIPCHK(c, hipMemcpyAsync(adam_v, L.av, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
   if (loss) HIPCHK(c, hipMemcpyAsync(loss, L.loss, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  if (grad)
+    HIPCHK(c, hipMemcpyAsync(grad, L.grad, sizeof(double) * MLP_NPARAM, hipMemcpyDeviceToHost, c->s));
   HIPCHK(c, hipStreamSynchronize(c->s));
   return TRPLK_OK;
 }
@@ -1696,6 +1797,7 @@ void trplk_default_opts(trplk_opts* o) {
   o->method = TRPLK_METHOD_TRPLK;
   o->orth = TRPLK_ORTH_AUTO;
   o->breakdown_tol = 0.0;
+  o->seed = 12;
 }
 
 static int check_opts(const trplk_opts* o, int n, std::string& why) {
@@ -1735,8 +1837,8 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
   return TRPLK_OK;
 }
 
-int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const trplk_opts* o,
-                 int32_t mem, void* stream) {
+static int create_impl(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const trplk_opts* o,
+                       int32_t mem, void* stream, void* ws, int64_t ws_bytes) {
   if (!out) return set_err(nullptr, TRPLK_EINVAL, "out is NULL");
   *out = nullptr;
   if (!A || !o) return set_err(nullptr, TRPLK_EINVAL, "A or opts is NULL");
@@ -1759,9 +1861,12 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
   c->o = *o;
   c->n = n;
   c->hasB = B != nullptr;
+  c->ws_base = ws;
+  c->ws_size = ws_bytes;
   c->prec = o->precond;
-  hipEvent_t e0, e1;
-  bool timing = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  // setup time: host wall clock from here to the drained stream (uploads,
+  // SpMV plans and diagonal copies, norms, preconditioner, workspace)
+  const auto t_setup0 = std::chrono::steady_clock::now();
   auto fail = [&](int code) {
     std::string msg = c->err;
     trplk_destroy(c);
@@ -1771,7 +1876,6 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
   if ((r = upload_csr(c, c->A, A, mem, mixed))) return fail(r);
   if (B && (r = upload_csr(c, c->B, B, mem, false))) return fail(r);
   if ((r = compute_norms(c))) return fail(r);
-  if (timing) (void)hipEventRecord(e0, c->s);
   // the Jacobi diagonal is also the fallback of the factor preconditioners
   if ((r = build_jacobi(c))) return fail(r);
   if (c->prec == TRPLK_PREC_FSAI) {
@@ -1780,19 +1884,41 @@ int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const 
     // installed later by trplk_set_factor; Jacobi-equivalent until then
     c->err = "";
   }
-  if (timing) {
-    (void)hipEventRecord(e1, c->s);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    c->stats.setup_ms = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  }
   if ((r = ensure_workspace(c))) return fail(r);
   if (hipStreamSynchronize(c->s) != hipSuccess) return fail(set_err(c, TRPLK_EDEVICE, "sync"));
+  c->stats.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                t_setup0).count();
   *out = c;
   return TRPLK_OK;
+}
+
+int trplk_create(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const trplk_opts* o,
+                 int32_t mem, void* stream) {
+  return create_impl(out, A, B, o, mem, stream, nullptr, 0);
+}
+
+int64_t trplk_workspace_size(int32_t n, int32_t has_b, const trplk_opts* o) {
+  if (!o || n < 1) return -1;
+  std::string why;
+  if (check_opts(o, n, why)) return -1;
+  trplk_ctx tmp;
+  tmp.n = n;
+  tmp.hasB = has_b != 0;
+  tmp.o = *o;
+  return ws_bytes_needed(&tmp);
+}
+
+int trplk_create_ws(trplk_ctx** out, const trplk_csr* A, const trplk_csr* B, const trplk_opts* o,
+                    int32_t mem, void* stream, void* workspace, int64_t workspace_bytes) {
+  if (!workspace) return set_err(nullptr, TRPLK_EINVAL, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+    return set_err(nullptr, TRPLK_EINVAL, "workspace must be 256-byte aligned");
+  if (A && o) {
+    const int64_t need = trplk_workspace_size(A->n, B != nullptr, o);
+    if (need < 0 || workspace_bytes < need)
+      return set_err(nullptr, TRPLK_EINVAL, "workspace smaller than trplk_workspace_size()");
+  }
+  return create_impl(out, A, B, o, mem, stream, workspace, workspace_bytes);
 }
 
 int trplk_set_factor(trplk_ctx* c, const trplk_csr* G, int32_t mem) {
@@ -1802,9 +1928,9 @@ int trplk_set_factor(trplk_ctx* c, const trplk_csr* G, int32_t mem) {
 
 int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
-  if (!x0) return set_err(c, TRPLK_EINVAL, "x0 is NULL");
+  if (mem != TRPLK_MEM_HOST && mem != TRPLK_MEM_DEVICE) return set_err(c, TRPLK_EINVAL, "bad mem");
   if (c->prec >= TRPLK_PREC_FSAI && !c->G.val) return set_err(c, TRPLK_EINVAL, "no factor installed");
-  if (mem == TRPLK_MEM_HOST) {
+  if (x0 && mem == TRPLK_MEM_HOST) {
     const int64_t ncols = c->o.method == TRPLK_METHOD_TRPLK ? c->o.k : 1;
     for (int64_t i = 0; i < static_cast<int64_t>(c->n) * ncols; ++i)
       if (!std::isfinite(x0[i])) return set_err(c, TRPLK_ENUMERIC, "non-finite start block");
@@ -1813,7 +1939,6 @@ int trplk_solve(trplk_ctx* c, const double* x0, int32_t mem, trplk_stats* st) {
   if (r) return r;
   c->L.pairs = false;
   Solver S{c, c->n, c->ld, c->s};
-  c->stats.setup_ms = c->stats.setup_ms;
   const double setup = c->stats.setup_ms;
   const int prec0 = c->prec;
   r = c->o.method == TRPLK_METHOD_TRPLK ? S.run(x0, mem, st) : S.run_pl1(x0, mem, st);
@@ -1827,66 +1952,104 @@ int trplk_get_eigpairs(trplk_ctx* c, double* evals, double* evecs, double* resid
                        int32_t mem) {
   if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
   if (!c->solved) return set_err(c, TRPLK_EINVAL, "no solve has completed");
+  if (mem != TRPLK_MEM_HOST && mem != TRPLK_MEM_DEVICE) return set_err(c, TRPLK_EINVAL, "bad mem");
   const int p = c->o.p;
   const int nout = c->nout;
   const int n = c->n;
   const int64_t ld = c->ld;
-  const hipMemcpyKind kd = mem == TRPLK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  const hipMemcpyKind kh = mem == TRPLK_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
-  std::vector<double> ev(p, NAN);
+  const bool host = mem == TRPLK_MEM_HOST;
+  // Host staging lives until the stream has drained: every exit below goes
+  // through done(), which synchronises before these vectors are released.
+  std::vector<double> ev(p, NAN), rr(p, NAN);
+  std::vector<int32_t> cv(p, 0);
   for (int i = 0; i < std::min<int>(p, c->theta_out.size()); ++i) ev[i] = c->theta_out[i];
-  if (evals) HIPCHK(c, hipMemcpyAsync(evals, ev.data(), sizeof(double) * p, kh, c->s));
-  if (conv) {
-    std::vector<int32_t> cv(p, 0);
-    for (int i = 0; i < std::min<int>(p, c->conv_out.size()); ++i) cv[i] = c->conv_out[i];
-    HIPCHK(c, hipMemcpyAsync(conv, cv.data(), sizeof(int32_t) * p, kh, c->s));
-    HIPCHK(c, hipStreamSynchronize(c->s));
-  }
-  if (evecs) {
-    HIPCHK(c, hipMemcpy2DAsync(evecs, sizeof(double) * n, c->W, sizeof(double) * ld, sizeof(double) * n,
-                               nout, kd, c->s));
-  }
-  if (resid) {
-    // true residuals ||A x - theta B x|| / ||x|| with fresh float64 products
-    std::vector<double> rr(p, NAN);
-    double* d_th = nullptr;
-    HIPCHK(c, hipMalloc(&d_th, sizeof(double) * std::max(nout, 1)));
-    HIPCHK(c, hipMemcpyAsync(d_th, ev.data(), sizeof(double) * nout, hipMemcpyHostToDevice, c->s));
-    std::vector<double> h(2);
+  for (int i = 0; i < std::min<int>(p, c->conv_out.size()); ++i) cv[i] = c->conv_out[i];
+  auto done = [&](int code, const char* what, hipError_t e) {
+    (void)hipStreamSynchronize(c->s);
+    if (code == TRPLK_OK) return TRPLK_OK;
+    return set_err(c, code, std::string(what) + ": " + hipGetErrorString(e));
+  };
+#define GETCHK(call)                                               \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return done(TRPLK_EDEVICE, #call, e_);   \
+  } while (0)
+  if (evecs)
+    GETCHK(hipMemcpy2DAsync(evecs, sizeof(double) * n, c->W, sizeof(double) * ld,
+                            sizeof(double) * n, nout, host ? hipMemcpyDeviceToHost
+                                                           : hipMemcpyDeviceToDevice, c->s));
+  if (resid && nout > 0) {
+    // true residuals ||A x - theta B x|| / ||x|| with fresh float64 products;
+    // the Ritz values go to the context's own device buffer (no allocation)
+    GETCHK(hipMemcpyAsync(c->thout, ev.data(), sizeof(double) * nout, hipMemcpyHostToDevice, c->s));
+    double h[2];
     for (int i = 0; i < nout; ++i) {
       const double* x = c->W + i * ld;
       if (c->hasB) {
         SpmvArgs b;
         b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = x;
         b.mode = SPMV_STORE; b.y = c->tmpB;
-        HIPCHK(c, spmv_f64(c->B.plan, b, c->s));
+        GETCHK(spmv_f64(c->B.plan, b, c->s));
       }
       SpmvArgs a;
       a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = x; a.xd = x;
       a.mode = SPMV_RESID; a.y = c->ytmp; a.bx = c->hasB ? c->tmpB : nullptr;
-      a.partial = c->partial; a.theta = d_th; a.theta_idx = i;
-      HIPCHK(c, spmv_f64(c->A.plan, a, c->s));
+      a.partial = c->partial; a.theta = c->thout; a.theta_idx = i;
+      GETCHK(spmv_f64(c->A.plan, a, c->s));
       FinishArgs f;
       f.mode = FIN_SUM; f.partial = c->partial; f.nblk = spmv_partial_blocks(c->A.plan); f.stride = 1;
       f.out = c->resout; f.cnt = 1;
-      HIPCHK(c, finish(f, c->s));
+      GETCHK(finish(f, c->s));
       OrthArgs o;
       o.n = n; o.ld = ld; o.ncol_fixed = 1; o.ncol_max = 1; o.Md0 = x; o.vec0 = x; o.nvec = 1;
       o.partial = c->partial;
-      HIPCHK(c, orth_pass(ORTH_DOT, o, orth_blocks(n, ORTH_DOT), c->s));
+      GETCHK(orth_pass(ORTH_DOT, o, orth_blocks(n, ORTH_DOT), c->s));
       FinishArgs g;
       g.mode = FIN_SUM; g.partial = c->partial; g.nblk = orth_blocks(n, ORTH_DOT); g.stride = orth_stride();
       g.out = c->resout + 1; g.cnt = 1;
-      HIPCHK(c, finish(g, c->s));
-      HIPCHK(c, hipMemcpyAsync(h.data(), c->resout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-      HIPCHK(c, hipStreamSynchronize(c->s));
+      GETCHK(finish(g, c->s));
+      GETCHK(hipMemcpyAsync(h, c->resout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      GETCHK(hipStreamSynchronize(c->s));
       rr[i] = std::sqrt(h[0]) / std::sqrt(h[1]);
     }
-    (void)hipFree(d_th);
-    HIPCHK(c, hipMemcpyAsync(resid, rr.data(), sizeof(double) * p, kh, c->s));
   }
-  HIPCHK(c, hipStreamSynchronize(c->s));
+  if (host) {
+    // host outputs: plain copies, nothing left in flight that reads ev/rr/cv
+    if (evals) std::memcpy(evals, ev.data(), sizeof(double) * p);
+    if (conv) std::memcpy(conv, cv.data(), sizeof(int32_t) * p);
+    if (resid) std::memcpy(resid, rr.data(), sizeof(double) * p);
+  } else {
+    if (evals) GETCHK(hipMemcpyAsync(evals, ev.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->s));
+    if (conv) GETCHK(hipMemcpyAsync(conv, cv.data(), sizeof(int32_t) * p, hipMemcpyHostToDevice, c->s));
+    if (resid) GETCHK(hipMemcpyAsync(resid, rr.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->s));
+  }
+#undef GETCHK
+  hipError_t e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return set_err(c, TRPLK_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
   return TRPLK_OK;
+}
+
+int32_t trplk_get_history(trplk_ctx* c, double* theta1, int32_t cap) {
+  if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
+  if (!c->solved) return set_err(c, TRPLK_EINVAL, "no solve has completed");
+  if (cap < 0 || (cap > 0 && !theta1)) return set_err(c, TRPLK_EINVAL, "bad history buffer");
+  const int32_t nc = static_cast<int32_t>(c->hist.size());
+  for (int32_t i = 0; i < std::min(cap, nc); ++i) theta1[i] = c->hist[i];
+  return nc;
+}
+
+int64_t trplk_get_factor(trplk_ctx* c, int32_t* rowptr, int32_t* col, double* val, int32_t mem) {
+  if (!c) return set_err(nullptr, TRPLK_EINVAL, "ctx is NULL");
+  if (!c->G.val) return set_err(c, TRPLK_EINVAL, "no factor installed");
+  if (mem != TRPLK_MEM_HOST && mem != TRPLK_MEM_DEVICE) return set_err(c, TRPLK_EINVAL, "bad mem");
+  const int64_t nnz = c->G.nnz;
+  if (!rowptr && !col && !val) return nnz;
+  const hipMemcpyKind kd = mem == TRPLK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (rowptr) HIPCHK(c, hipMemcpyAsync(rowptr, c->G.rowptr, sizeof(int32_t) * (c->n + 1), kd, c->s));
+  if (col) HIPCHK(c, hipMemcpyAsync(col, c->G.col, sizeof(int32_t) * nnz, kd, c->s));
+  if (val) HIPCHK(c, hipMemcpyAsync(val, c->G.val, sizeof(double) * nnz, kd, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return nnz;
 }
 
 int64_t trplk_device_bytes(const trplk_ctx* c) { return c ? c->dev_bytes : 0; }
@@ -1902,14 +2065,18 @@ void trplk_destroy(trplk_ctx* c) {
   free_csr(c->B);
   free_csr(c->G);
   free_csr(c->Gt);
-  void* ptrs[] = {c->dinv, c->W, c->AW, c->BW, c->w, c->wtmp, c->tmpB, c->vtmp, c->ytmp, c->v32,
-                  c->y32, c->wtmp32, c->Xprev, c->T, c->theta, c->Y, c->hbuf, c->partial,
-                  c->resout, c->st, c->rep_d};
+  if (!c->ws_base) {
+    std::vector<WsPiece> pcs;
+    ws_pieces(c, pcs);
+    for (const WsPiece& q : pcs) dfree(*q.ptr);
+  }
+  void* ptrs[] = {c->dinv, c->pl1_s, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
+                  c->partial, c->resout, c->thout, c->st, c->rep_d};
   for (void* p : ptrs) dfree(p);
   auto& L = c->L;
   void* lp[] = {L.Lrow, L.Lcol, L.lr, L.lval, L.Trow, L.Tcol, L.permd, L.dinv, L.F, L.Fz,
                 L.gval, L.gvalT, L.P, L.am, L.av, L.Er, L.Rr, L.Y, L.D, L.Uu, L.Z, L.coef, L.w,
-                L.dout, L.part, L.loss, L.grad, L.scratch};
+                L.dout, L.part, L.loss, L.grad, L.scratch, L.cbar};
   for (void* p : lp) dfree(p);
   if (c->rep_h) (void)hipHostFree(c->rep_h);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1929,7 +2096,7 @@ struct Scratch {
 };
 Scratch g_scratch;
 
-double* scratch(size_t bytes) {
+double* kernel_scratch(size_t bytes) {
   if (bytes > g_scratch.bytes) {
     if (g_scratch.buf) (void)hipFree(g_scratch.buf);
     g_scratch.buf = nullptr;
@@ -2001,7 +2168,7 @@ int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const doubl
   if (ldu % 2 != 0 || !aligned16(U) || !aligned16(v)) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nblk = orth_blocks(n, ORTH_DOT);
-  double* part = scratch(sizeof(double) * nblk * orth_stride());
+  double* part = kernel_scratch(sizeof(double) * nblk * orth_stride());
   if (!part) return TRPLK_ENOMEM;
   OrthArgs a;
   a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Md0 = U; a.vec0 = v; a.nvec = 1;
@@ -2020,7 +2187,7 @@ int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, con
   if (ldu % 2 != 0 || !aligned16(U) || !aligned16(w)) return TRPLK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nblk = orth_blocks(n, ORTH_UPD_DOT);
-  double* part = scratch(sizeof(double) * nblk * orth_stride());
+  double* part = kernel_scratch(sizeof(double) * nblk * orth_stride());
   if (!part) return TRPLK_ENOMEM;
   OrthArgs a;
   a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Mu = U; a.Md1 = U; a.h = h; a.w = w;

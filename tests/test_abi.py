@@ -78,3 +78,48 @@ def test_orth_option_validation_without_gpu():
     assert b"breakdown_tol" in L.trplk_last_error(None)
     o.breakdown_tol = 0.0
     assert not ctx.value
+
+
+def test_splitmix64_start_block_published_outputs():
+    """The default start block's generator: SplitMix64 seeded with 0 gives
+    0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f first (the
+    published outputs of the reference generator); entry e of the block is
+    (output_e >> 11) * 2^-52 - 1, column-major."""
+    import numpy as np
+    from workloads import splitmix64_block
+    X = splitmix64_block(3, 1, 0)
+    outs = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    want = [(o >> 11) * 2.0 ** -52 - 1.0 for o in outs]
+    assert list(X[:, 0]) == want
+    Y = splitmix64_block(4, 3, 12)
+    assert Y.flags.f_contiguous and Y.shape == (4, 3)
+    assert np.all(Y >= -1.0) and np.all(Y < 1.0)
+    # column c continues the stream: entry (i, c) is output c * n + i
+    assert splitmix64_block(12, 1, 12)[:, 0].tolist() == Y.T.ravel().tolist()
+
+
+def test_workspace_size_without_gpu():
+    """trplk_workspace_size is host arithmetic: W, A W (and B W) with p + m
+    columns under hard locking, m otherwise, each column padded to 32
+    doubles, the +K block, PL+1's products and the n-vectors, each piece
+    rounded to 256 bytes."""
+    import paper_1711_10128_amd as T
+    L = T.lib()
+    o = T._Opts()
+    L.trplk_default_opts(ctypes.byref(o))
+    assert o.seed == 12
+    o.p, o.m, o.k, o.l = 10, 40, 20, 1
+    n = 1000
+    ld = 1024
+    d, f = 8 * ld, 4 * ld
+    std = 2 * d * 40 + d + d + 4 * d + 3 * f
+    assert L.trplk_workspace_size(n, 0, ctypes.byref(o)) == std
+    gen = 3 * d * 40 + d + 2 * d + 5 * d + 3 * f
+    assert L.trplk_workspace_size(n, 1, ctypes.byref(o)) == gen
+    o.p, o.k = 50, 20   # p > k: hard locking, p + m columns
+    assert L.trplk_workspace_size(n, 0, ctypes.byref(o)) == 2 * d * 90 + d + d + 4 * d + 3 * f
+    o.m = 65            # invalid options
+    assert L.trplk_workspace_size(n, 0, ctypes.byref(o)) == -1
+    ctx = ctypes.c_void_p()
+    assert L.trplk_create_ws(ctypes.byref(ctx), None, None, ctypes.byref(o), 0, None, None, 0) == -1
+    assert not ctx.value

@@ -77,3 +77,42 @@ def test_pl1_rejects_p_above_one(T):
     A = lap2d(10).to_scipy()
     with pytest.raises(Exception):
         T.Solver(_Csr(A), None, p=2, m=8, k=2, l=1, method="pl1")
+
+
+def test_quasi_optimality_of_one_inner_step(T):
+    """Sec. 5.1, Fig. 1: TRPL+K with one inner step (PL+1 with the practical
+    direction and a one-vector Krylov block, no preconditioner) on the
+    64 x 64 Laplacian.  The GPU's Rayleigh quotients rho(x_k) follow the
+    oracle's step for step; the quasi-optimality ratio against the
+    unrestarted Krylov minimum (Sec. 4.3) formed from them falls as the
+    start vector's angle to v1 shrinks."""
+    import math
+    from oracle import quasiopt as Q
+    N, K = 64, 20
+    A = lap2d(N).to_scipy()
+    s = np.sin(np.arange(1, N + 1) * np.pi / (N + 1))
+    v1 = np.outer(s, s).ravel()
+    lam1 = 8 * math.sin(math.pi / (2 * (N + 1))) ** 2
+    rows = []
+    for th in (0.5, 0.1, 0.02):
+        x0 = Q.start_vector(v1, th, np.random.default_rng(3))
+        S = T.Solver(_Csr(A), None, p=1, m=3, k=1, l=1, tol=1e-300, method="pl1_practical",
+                     precond="none", max_cycles=K)
+        st = S.solve(x0[:, None])
+        rho_gpu = S.history()
+        S.close()
+        assert st["cycles"] == K and rho_gpu.shape == (K,)
+        rho_ref = Q.one_inner_step(A, x0, K)
+        print(f"  theta0={th}: max |rho_gpu - rho_oracle| = {np.max(np.abs(rho_gpu - rho_ref)):.2e}",
+              flush=True)
+        assert np.all(np.abs(rho_gpu - rho_ref) <= 1e-13 * 8)
+        r, _, _ = Q.quasi_optimality(A, x0, lam1, K, rho_x=rho_gpu)
+        rows.append(r)
+    # iterations 3, 5, 10, 20: theta0 = 0.5 -> 0.1 lowers the ratio about
+    # sin^2 ratio-fold (25x; measured ~1000x); at theta0 = 0.02 the numerator
+    # rho(x_k) - rho(y*) is down to ~1e-16, the rounding of rho itself, so
+    # there only its size is checked
+    for k in (2, 4, 9, 19):
+        assert rows[0][k] > 100 * rows[1][k] > 0, [r[k] for r in rows]
+    for k in (2, 4, 9):
+        assert abs(rows[2][k]) < 2e-9 < rows[1][k], [r[k] for r in rows]

@@ -423,3 +423,74 @@ def test_mutant_prev_vectors_fail_mv_pin():
     except IndexError:
         return  # the basis overflows its m columns
     assert r.matvecs != 8 + 10 * r.cycles
+
+
+# --------------------------------------------------------------------------
+# the paper's stopping norm and the un-flag branch of the convergence test
+# --------------------------------------------------------------------------
+
+def test_frobenius_norm_and_paper_stopping_rule():
+    """eq. (5.1) stops on ||A u - theta u|| <= ||A||_F tol.  For the 64 x 64
+    5-point Laplacian ||A||_F^2 = 4096 * 4^2 + 2 * (2 * 64 * 63) * 1^2 =
+    81664 (diagonal entries plus both triangles of the 2 * 64 * 63 grid
+    edges), ||A||_F = 285.769..., and ||A||_inf = 8 (max row sum)."""
+    A = lap2d(64).to_scipy()
+    assert O.matrix_norm(A, "fro") == math.sqrt(81664.0)
+    assert abs(math.sqrt(81664.0) - 285.769) < 5e-4
+    assert O.matrix_norm(A, "inf") == 8.0
+    # a hand-sized matrix: [[3, -4], [-4, 0]]: F = sqrt(9 + 32) , inf = 7
+    M = sp.csr_matrix(np.array([[3.0, -4.0], [-4.0, 0.0]]))
+    assert O.matrix_norm(M, "fro") == math.sqrt(41.0)
+    assert O.matrix_norm(M, "inf") == 7.0
+    # the solve under the Frobenius rule: threshold tol * 285.769, every
+    # returned pair meets it, the inf-norm run (a 35x tighter threshold)
+    # needs more cycles
+    P = make("lap2d", "small", N=24, p=5, m=20, k=8)
+    r_f, A24, _ = _solve(P, norm="fro")
+    r_i, _, _ = _solve(P, norm="inf")
+    nf = math.sqrt(float(np.sum(A24.data ** 2)))
+    assert r_f.normA == nf
+    assert np.all(r_f.true_res <= P.tol * nf)
+    assert r_f.cycles < r_i.cycles
+    assert np.any(r_f.true_res > P.tol * 8.0)   # looser than the inf rule
+    ref = lap2d_closed(24, 5)
+    assert np.all(np.abs(r_f.theta - ref) <= 1e-8 * nf)
+
+
+def weak_island_problem(delta=1e-2, eps=1e-12, N=16, s=16, k=4):
+    """A 2-D Laplacian next to a disconnected path whose lowest eigenvalue
+    lies delta below the grid's, started from a block whose path part is
+    scaled by eps.  The grid's lowest pair converges first; the path's mode,
+    amplified from eps, then enters below it (R8 un-flag), and the solve
+    recovers both.  Block-diagonal A and a diagonal M keep the path part of
+    every vector a function of the path part alone, so the event does not
+    hang on rounding."""
+    lam1 = 8 * np.sin(np.pi / (2 * (N + 1))) ** 2
+    dg = lam1 - delta + 2 * np.cos(np.pi / (s + 1))
+    A = lap2d_island(N, s, dg)
+    X0 = start_block(A.n, k, 12).copy(order="F")
+    X0[N * N:, :] *= eps
+    return A, X0
+
+
+def test_soft_locked_pair_unflagged_when_a_lower_mode_appears():
+    """R8: a flagged (soft-locked) pair whose residual leaves the tolerance is
+    unflagged and the target moves back; the final pairs are the two lowest
+    eigenpairs of the whole matrix (dense LAPACK)."""
+    Ac, X0 = weak_island_problem()
+    A = Ac.to_scipy()
+    r = O.solve(A, None, 2, 12, 4, 1, 1e-8, X0, apply_M=O.jacobi(A), keep_history=True)
+    ts = [h[2] for h in r.history]
+    drops = [c for c in range(1, len(ts)) if ts[c] < ts[c - 1]]
+    assert drops, ts
+    c = drops[0]
+    thr = 1e-8 * r.normA
+    # the pair flagged before the drop had met the tolerance, the new lowest
+    # Ritz value after it is far from converged and lies below the old one
+    assert r.history[c - 1][1][0] <= thr
+    assert r.history[c][1][0] > 100 * thr
+    assert r.history[c][0][0] < r.history[c - 1][0][0] - 1e-3
+    ev = np.linalg.eigvalsh(A.toarray())[:2]
+    assert r.converged.all()
+    assert np.all(np.abs(r.theta - ev) <= 1e-12)
+    assert (r.cycles, r.matvecs) == (20, 4 + 8 * 20)

@@ -211,3 +211,66 @@ def test_learned_offdiagonal_scale_by_hand():
     assert np.isclose(G[2, 0], 2.0 * 1.0 / (cb * 9.0 * 1.0), rtol=1e-15)
     assert np.isclose(G[2, 1], 2.0 * -0.5 / (cb * 4.0 * 1.0), rtol=1e-15)
     assert np.isclose(G[0, 0], 1.0 / 3.0, rtol=1e-15)
+
+
+def test_adam_step_by_hand():
+    """One and two Adam steps (Kingma and Ba, Algorithm 1: biased moments
+    m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2, bias corrections
+    1 - b^t, update lr * mhat / (sqrt(vhat) + eps)) worked out by hand.
+
+    Step 1 with g = 2: m = 0.2, v = 0.004, mhat = 2, vhat = 4, so the update
+    is lr * 2 / (2 + eps).  Step 2 with g = -1: m = 0.18 - 0.1 = 0.08,
+    v = 0.003996 + 0.001 = 0.004996, mhat = 0.08 / 0.19, vhat = 0.004996 /
+    0.001999.  A missing bias correction or a wrong moment weight changes
+    both numbers by far more than the tolerance."""
+    lr, eps = 1e-2, 1e-8
+    p = {"w": np.array([1.0, -3.0])}
+    st = {}
+    PC.adam_step(p, {"w": np.array([2.0, 0.5])}, st, lr=lr, eps=eps)
+    # the second entry: g = 0.5, mhat = 0.5, vhat = 0.25 -> lr * 0.5 / (0.5 + eps)
+    assert np.allclose(p["w"], [1.0 - lr * 2.0 / (2.0 + eps), -3.0 - lr * 0.5 / (0.5 + eps)],
+                       rtol=0, atol=1e-15)
+    assert st["t"] == 1
+    assert np.allclose(st["m_w"], [0.2, 0.05], rtol=1e-15)
+    assert np.allclose(st["v_w"], [0.004, 0.00025], rtol=1e-15)
+    w1 = p["w"].copy()
+    PC.adam_step(p, {"w": np.array([-1.0, 0.5])}, st, lr=lr, eps=eps)
+    m2 = 0.9 * 0.2 + 0.1 * -1.0
+    v2 = 0.999 * 0.004 + 0.001 * 1.0
+    mh, vh = m2 / (1 - 0.9 ** 2), v2 / (1 - 0.999 ** 2)
+    assert abs(m2 - 0.08) < 1e-15 and abs(v2 - 0.004996) < 1e-15
+    assert abs(p["w"][0] - (w1[0] - lr * mh / (math.sqrt(vh) + eps))) < 1e-15
+    # the numbers themselves: mhat = 0.421052..., vhat = 0.004996 / 0.001999 = 2.49925...
+    assert abs(mh - 0.08 / 0.19) < 1e-15
+    assert abs(vh - 2.4992496) < 1e-7
+    # a constant gradient keeps the step at lr (mhat / sqrt(vhat) = 1)
+    q = {"w": np.zeros(1)}
+    s2 = {}
+    for _ in range(5):
+        PC.adam_step(q, {"w": np.array([3.0])}, s2, lr=0.1, eps=0.0)
+    assert abs(q["w"][0] + 0.5) < 1e-14
+
+
+@pytest.mark.parametrize("old,new", [
+    ("mh = mk / (1 - b1 ** t)", "mh = mk"),                          # no bias correction
+    ("vh = vk / (1 - b2 ** t)", "vh = vk"),
+    ("mk[...] = b1 * mk + (1 - b1) * grads[key]",
+     "mk[...] = b1 * mk + 0.5 * (1 - b1) * grads[key]"),             # halved first moment
+    ("np.sqrt(vh) + eps", "vh + eps"),                               # missing square root
+    ('state["t"] = state.get("t", 0) + 1', 'state["t"] = 1'),        # step count stuck
+])
+def test_mutant_adam_fails_hand_pin(old, new):
+    """Planted mistakes in a copy of the oracle's Adam step fail the pin."""
+    import types
+    src = open(PC.__file__).read()
+    assert old in src
+    m = types.ModuleType("precond_mutant")
+    exec(compile(src.replace(old, new), "precond_mutant", "exec"), m.__dict__)
+    g = globals()
+    saved = g["PC"]
+    g["PC"] = m
+    try:
+        with pytest.raises(AssertionError):
+            test_adam_step_by_hand()
+    finally:
+        g["PC"] = saved

@@ -304,6 +304,25 @@ def start_block(n: int, k: int, seed: int = 12) -> np.ndarray:
     return np.asfortranarray(X)
 
 
+def splitmix64_block(n: int, k: int, seed: int = 12) -> np.ndarray:
+    """n x k uniform[-1, 1) block (Fortran order) from the counter-based
+    SplitMix64 generator (Steele, Lea and Flood, OOPSLA 2014): entry
+    e = column * n + row is b * 2^-52 - 1, b the top 53 bits of
+    mix(seed + (e + 1) * 0x9e3779b97f4a7c15), mix the generator's 64-bit
+    finaliser.  The GPU library draws its default start block (x0 = NULL) by
+    the same definition, so the two blocks are identical."""
+    X = np.empty((n, k), order="F")
+    s = np.uint64(seed % (1 << 64))
+    for c in range(k):   # one column at a time keeps the temporaries at n words
+        e = np.arange(c * n, (c + 1) * n, dtype=np.uint64)
+        z = s + (e + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+        X[:, c] = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+    return X
+
+
 def lap2d_island(N: int, s: int, diag: float = 2.5) -> CSR:
     """lap2d(N) with a disconnected path of s extra nodes appended: the
     block-diagonal matrix diag(lap2d(N), tridiag(-1, diag, -1) of order s).
