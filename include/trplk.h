@@ -363,6 +363,20 @@ int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const f
 int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v,
                  double* h, void* stream);
 
+/* trplk_gemv_t for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same h = U^T v with the same kernels and summation order, but the
+ * per-workgroup partial sums go to a static device array of the library
+ * (256 workgroups x 384 doubles = 768 KiB per device, held until the
+ * process ends; its address is looked up once per device) instead of
+ * memory the library allocates.  No hipMalloc, hipFree or allocating
+ * library call is made.  Same arguments, layout and alignment rules as
+ * trplk_gemv_t; TRPLK_EINVAL when the pass would need more partial rows
+ * than the array holds.  Every call on one device shares that array: calls
+ * that overlap on one GPU (several streams or host threads) race. */
+int trplk_gemv_t_noalloc(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v,
+                         double* h, void* stream);
+
 /* w <- w - U h followed by h2 = U^T w (one read of U): the fused second
  * pass of classical Gram-Schmidt applied twice.  Same layout and alignment
  * rules as trplk_gemv_t (U and w 16-byte aligned, ldu even). */

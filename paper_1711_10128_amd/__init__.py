@@ -91,7 +91,7 @@ EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_workspace_size", "trplk_
            "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
            "trplk_rotate", "trplk_learned_factor", "trplk_factor_nnz", "trplk_factor_values",
            "trplk_factor_loss_grad", "trplk_train_step", "trplk_get_factor",
-           "trplk_get_history"]
+           "trplk_gemv_t_noalloc", "trplk_get_history"]
 MLP_NPARAM = 1217
 MLP_NF, MLP_NIN, MLP_NH = 8, 17, 64
 
@@ -131,10 +131,12 @@ def lib():
     L.trplk_spmv.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
     L.trplk_spmv_f32.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
     L.trplk_gemv_t.argtypes = [i32, i32, vp, i64, vp, vp, vp]
+    L.trplk_gemv_t_noalloc.argtypes = [i32, i32, vp, i64, vp, vp, vp]
     L.trplk_cgs_update_dot.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp]
     L.trplk_syev.argtypes = [i32, vp, vp, vp, vp]
     L.trplk_rotate.argtypes = [i32, i32, i32, vp, i64, vp, i32, vp]
-    for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot",
+    for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_gemv_t_noalloc",
+              "trplk_cgs_update_dot",
               "trplk_syev", "trplk_rotate"):
         getattr(L, f).restype = ctypes.c_int
     L.trplk_learned_factor.argtypes = [vp, vp]
@@ -389,6 +391,14 @@ def gemv_t(U, v, h, n=None):
     c, ld = U.shape
     n = ld if n is None else n
     _check(lib().trplk_gemv_t(n, c, _ptr(U), ld, _ptr(v), _ptr(h), _stream()))
+    return h
+
+
+def gemv_t_noalloc(U, v, h, n=None):
+    """gemv_t through the entry point that allocates nothing (static scratch)."""
+    c, ld = U.shape
+    n = ld if n is None else n
+    _check(lib().trplk_gemv_t_noalloc(n, c, _ptr(U), ld, _ptr(v), _ptr(h), _stream()))
     return h
 
 

@@ -26,6 +26,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2115,6 +2116,42 @@ int kernel_err(hipError_t e) {
   return TRPLK_EDEVICE;
 }
 
+// Reduction scratch of trplk_gemv_t_noalloc: one row of partial sums per
+// workgroup of the dot pass (at most NOALLOC_BLOCKS workgroups of
+// 3 * ORTH_MAXCOL doubles).  Each device holds its own copy for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device.
+constexpr int NOALLOC_BLOCKS = 256;
+constexpr int64_t NOALLOC_DOUBLES = int64_t(NOALLOC_BLOCKS) * 3 * ORTH_MAXCOL;
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAXDEV = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAXDEV] = {};
+
+// Address of this device's scratch (looked up once per device, with the
+// device current); nullptr with *err set on failure.
+double* noalloc_scratch(hipError_t* err) {
+  int dev = -1;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= NOALLOC_MAXDEV) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess || !p) {
+      if (*err == hipSuccess) *err = hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_noalloc_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -2174,6 +2211,33 @@ int trplk_gemv_t(int32_t n, int32_t c, const double* U, int64_t ldu, const doubl
   a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Md0 = U; a.vec0 = v; a.nvec = 1;
   a.partial = part;
   hipError_t e = orth_pass(ORTH_DOT, a, nblk, s);
+  FinishArgs f;
+  f.mode = FIN_SUM; f.partial = part; f.nblk = nblk; f.stride = orth_stride(); f.out = h; f.cnt = c;
+  if (e == hipSuccess) e = finish(f, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_gemv_t_noalloc(int32_t n, int32_t c, const double* U, int64_t ldu, const double* v,
+                         double* h, void* stream) {
+  if (n < 1 || c < 1 || c > ORTH_MAXCOL || ldu < n || !U || !v || !h) return TRPLK_EINVAL;
+  if (ldu % 2 != 0 || !aligned16(U) || !aligned16(v)) return TRPLK_EINVAL;
+  const int nblk = orth_blocks(n, ORTH_DOT);
+  if (static_cast<int64_t>(nblk) * orth_stride() > NOALLOC_DOUBLES) {
+    g_create_err = "trplk_gemv_t_noalloc: the dot pass needs more partial rows than the static "
+                   "scratch holds";
+    return TRPLK_EINVAL;
+  }
+  hipError_t e = hipSuccess;
+  double* part = noalloc_scratch(&e);
+  if (!part) return kernel_err(e);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every workgroup writes its whole row of partials before the finish reads
+  // it, so nothing left by an earlier call is read
+  OrthArgs a;
+  a.n = n; a.ld = ldu; a.ncol_fixed = c; a.ncol_max = c; a.Md0 = U; a.vec0 = v; a.nvec = 1;
+  a.partial = part;
+  e = orth_pass(ORTH_DOT, a, nblk, s);
   FinishArgs f;
   f.mode = FIN_SUM; f.partial = part; f.nblk = nblk; f.stride = orth_stride(); f.out = h; f.cnt = c;
   if (e == hipSuccess) e = finish(f, s);
