@@ -108,6 +108,9 @@ def parse():
                     help="restart cycles per step (0 = a complete solve; default per workload)")
     ap.add_argument("--converged", action="store_true",
                     help="also run one complete solve of the timed form and of float64 Jacobi")
+    ap.add_argument("--converged-forms", default="",
+                    help="comma-separated forms (precond-precision) of the complete solves "
+                         "(default: the timed form and jacobi-fp64)")
     ap.add_argument("--precond", default="", help="timed form's preconditioner (default per workload)")
     ap.add_argument("--precision", default="", choices=["", "fp64", "mixed"])
     ap.add_argument("--variants", type=int, default=1, help="also time the other forms once")
@@ -127,6 +130,9 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=5000, help="cap of a complete solve")
     ap.add_argument("--progress", type=int, default=0,
                     help="complete solves print a line every this many cycles (0 = silent)")
+    ap.add_argument("--protocol", action="store_true",
+                    help="the power-law learned-factor protocol (24 train / 8 held-out graphs, "
+                         "n = 1e6) instead of the timed run")
     ap.add_argument("--summarize", default="",
                     help="summarize rocprofv3 output in this directory (kernel stats or counters) "
                          "instead of running anything on the GPU")
@@ -172,6 +178,90 @@ def train_factor(T, name, args, log):
         f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
     return params, {"train_instances": args.train_count, "train_size": size,
                     "epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1]}
+
+
+def _gen_powerlaw(seed):
+    P = make_workload("powerlaw", 0, seed=seed)
+    return seed, P
+
+
+def run_protocol(args, T, log):
+    """The learned-preconditioner protocol of the power-law workload: 32
+    seeded graphs at n = 1e6 (seeds 12..43), the factor's network trained on
+    the first 24 (pairs harvested from GPU Jacobi solves of each), then each
+    of the 8 held-out graphs solved to tol 1e-8 in every form; one JSON line
+    with the per-form mean time, products and cycles."""
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from workloads import start_block
+    seeds = list(range(12, 44))
+    t0 = time.time()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        probs = dict(ex.map(_gen_powerlaw, seeds))
+    log(f"# generated {len(seeds)} power-law graphs (n = 1e6) in {time.time() - t0:.1f}s")
+    train_seeds, test_seeds = seeds[:24], seeds[24:]
+    solvers, X0s, dev = [], [], []
+    for sd in train_seeds:
+        P = probs[sd]
+        Ad = T.DeviceCSR(P.A)
+        dev.append(Ad)
+        for cycles in (300, 1, 3):
+            solvers.append(T.Solver(Ad, None, p=min(P.p, P.k), m=P.m, k=P.k, l=1, tol=1e-6,
+                                    precond="jacobi", max_cycles=cycles))
+            X0s.append(start_block(P.A.n, P.k, sd))
+    t1 = time.time()
+    params, hist = T.train(solvers, X0s, epochs=args.epochs, lr=1e-3, S=min(64, P.m))
+    t2 = time.time()
+    for s in solvers:
+        s.close()
+    del solvers, dev
+    torch.cuda.synchronize()
+    log(f"# trained on {len(train_seeds)} graphs in {t2 - t1:.1f}s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    forms = [("jacobi", "fp64"), ("jacobi", "mixed"), ("fsai", "fp64"), ("fsai", "mixed"),
+             ("learned", "fp64"), ("learned", "mixed")]
+    rows = {f"{a}-{b}": [] for a, b in forms}
+    for sd in test_seeds:
+        P = probs[sd]
+        Ad = T.DeviceCSR(P.A)
+        Xd = torch.from_numpy(np.ascontiguousarray(start_block(P.A.n, P.k, sd).T)).cuda()
+        ev0 = None
+        for pc, pr in forms:
+            S = T.Solver(Ad, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol,
+                         precond="jacobi" if pc == "learned" else pc, precision=pr,
+                         mixed_switch=WORKLOADS["powerlaw"].get("mixed_switch", 0.0))
+            if pc == "learned":
+                S.learned_factor(params)
+            S.solve(Xd)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = S.solve(Xd)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            ev, _, res, conv = S.eigpairs(vectors=False)
+            S.close()
+            if ev0 is None:
+                ev0 = ev
+            rows[f"{pc}-{pr}"].append({"seed": sd, "s": round(b - a, 4), "matvecs": st["matvecs"],
+                                       "cycles": st["cycles"], "converged": bool(conv.all()),
+                                       "max_resid_rel": float(np.max(res) / st["normA"]),
+                                       "max_rel_eig_diff_vs_jacobi_fp64":
+                                           float(np.max(np.abs(ev - ev0) / np.abs(ev0)))})
+        log(f"# held-out graph seed {sd}: " + ", ".join(
+            f"{k} {v[-1]['cycles']} cyc {v[-1]['s']:.3f}s" for k, v in rows.items()))
+        del Ad, Xd
+    summary = {k: {"mean_s": round(float(np.mean([r["s"] for r in v])), 4),
+                   "mean_matvecs": float(np.mean([r["matvecs"] for r in v])),
+                   "mean_cycles": float(np.mean([r["cycles"] for r in v])),
+                   "all_converged": all(r["converged"] for r in v)} for k, v in rows.items()}
+    base = summary["jacobi-fp64"]["mean_s"]
+    for k in summary:
+        summary[k]["speedup_vs_jacobi_fp64"] = round(base / summary[k]["mean_s"], 3)
+    print(json.dumps({"protocol": "power-law learned factor: 24 train / 8 held-out at n = 1e6",
+                      "train_seeds": train_seeds, "test_seeds": test_seeds,
+                      "train": {"epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1],
+                                "seconds": round(t2 - t1, 1)},
+                      "summary": summary, "per_graph": rows}))
 
 
 def run_sweep(args, T, P, Ad, Bd, Xd, precond, precision, log):
@@ -322,6 +412,8 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.protocol:
+        return run_protocol(args, T, log)
     W = WORKLOADS[args.workload]
     precond = args.precond or W["form"][0]
     precision = args.precision or W["form"][1]
@@ -349,8 +441,9 @@ def main():
 
     learned = None
     learn_info = None
-    need_learned = precond == "learned" or (args.variants and not args.profile_only and
-                                             args.workload in ("powerlaw", "aniso3d", "lap3d"))
+    cf = args.converged_forms if (args.converged and C) else ""
+    need_learned = precond == "learned" or "learned" in cf or (
+        args.variants and not args.profile_only and args.workload in ("powerlaw", "aniso3d", "lap3d"))
     if need_learned:
         learned, learn_info = train_factor(T, args.workload, args, log)
 
@@ -470,7 +563,7 @@ def main():
         b = time.perf_counter()
         evv, _, rv, cv = V.eigpairs(vectors=False)
         V.close()
-        ok = np.isfinite(evv) & np.isfinite(ev)
+        ok = np.isfinite(evv) & np.isfinite(ev) & cv.astype(bool) & conv.astype(bool)
         return {"s": round(b - a, 4), "matvecs": sv["matvecs"], "cycles": sv["cycles"],
                 "fp32_cycles": sv["fp32_cycles"], "converged_pairs": int(cv.sum()),
                 "setup_ms": round(sv["setup_ms"], 2), "converged": bool(cv.all()),
@@ -499,7 +592,9 @@ def main():
     solutions = None
     if args.converged and C:
         solutions = {}
-        for pc, pr in [(precond, precision), ("jacobi", "fp64")]:
+        cforms = ([tuple(f.split("-")) for f in args.converged_forms.split(",")]
+                  if args.converged_forms else [(precond, precision), ("jacobi", "fp64")])
+        for pc, pr in cforms:
             label = f"{pc}-{pr}"
             log(f"# complete solve {label} (max {args.max_cycles} cycles)")
             solutions[label] = one(pc, pr, cycles=args.max_cycles, warm=False)
