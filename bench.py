@@ -362,36 +362,54 @@ def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log):
                        f"= that x the {gpu_cycles} cycles of the timed GPU form (extrapolated)")
 
 
-def summarize(d):
-    """Text summary of rocprofv3 CSV output under d: kernel statistics
-    (*kernel_stats.csv) or per-class HBM counters (*counter_collection.csv)."""
+def summarize(spec):
+    """Text summary of rocprofv3 CSV output: kernel statistics
+    (*kernel_stats.csv) and per-class HBM counters (*counter_collection.csv)
+    under the comma-separated directories in spec.  With FETCH_SIZE and
+    WRITE_SIZE both present, each class's HBM bytes per launch are printed as
+    TRAFFIC lines, the counters scaled by what they read for the 256 MiB
+    calibration copies bench.py --profile-only runs (copyBuffer dispatches)."""
     import csv
     import glob
     out = []
-    ks = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
-    cc = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    if ks:
-        rows = list(csv.DictReader(open(ks[0])))
-        tot = sum(float(r["TotalDurationNs"]) for r in rows)
-        out.append(f"# source: {os.path.relpath(ks[0], d)}")
-        out.append(f"# {'rocprofv3 kernel':<92} {'calls':>6} {'total ms':>9} {'avg us':>9} {'%':>6}")
-        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-            out.append(f"{r['Name'][:92]:<92} {int(r['Calls']):>6} "
-                       f"{float(r['TotalDurationNs']) / 1e6:>9.2f} {float(r['AverageNs']) / 1e3:>9.2f} "
-                       f"{100 * float(r['TotalDurationNs']) / tot:>6.2f}")
-    for f in cc:
-        rows = list(csv.DictReader(open(f)))
-        agg = {}
-        for r in rows:
-            name = r["Kernel_Name"]
-            cls = next((c for key, c in PROF_CLASSES if key in name), "other")
-            a = agg.setdefault((cls, r["Counter_Name"]), [0, 0.0])
-            a[0] += 1
-            a[1] += float(r["Counter_Value"])
-        out.append(f"# source: {os.path.relpath(f, d)}")
-        out.append(f"{'class':<14} {'counter':<12} {'dispatches':>10} {'mean KiB':>14}")
+    agg = {}
+    for d in spec.split(","):
+        ks = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+        cc = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+        if ks:
+            rows = list(csv.DictReader(open(ks[0])))
+            tot = sum(float(r["TotalDurationNs"]) for r in rows)
+            out.append(f"# kernel statistics: {os.path.basename(ks[0])}")
+            out.append(f"# {'rocprofv3 kernel':<92} {'calls':>6} {'total ms':>9} {'avg us':>9} {'%':>6}")
+            for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+                out.append(f"{r['Name'][:92]:<92} {int(r['Calls']):>6} "
+                           f"{float(r['TotalDurationNs']) / 1e6:>9.2f} "
+                           f"{float(r['AverageNs']) / 1e3:>9.2f} "
+                           f"{100 * float(r['TotalDurationNs']) / tot:>6.2f}")
+        for f in cc:
+            for r in csv.DictReader(open(f)):
+                name = r["Kernel_Name"]
+                cls = next((c for key, c in PROF_CLASSES if key in name), "other")
+                a = agg.setdefault((cls, r["Counter_Name"]), [0, 0.0])
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+    if agg:
+        out.append(f"# counters: {'class':<14} {'counter':<12} {'dispatches':>10} {'mean KiB':>14}")
         for (cls, cn), (cnt, tot) in sorted(agg.items()):
             out.append(f"{cls:<14} {cn:<12} {cnt:>10} {tot / cnt:>14.1f}")
+        f_copy = agg.get(("copy", "FETCH_SIZE"))
+        w_copy = agg.get(("copy", "WRITE_SIZE"))
+        if f_copy and w_copy:
+            want = (256 << 20) / 1024.0
+            rs = want / (f_copy[1] / f_copy[0])
+            ws = want / (w_copy[1] / w_copy[0])
+            out.append(f"calibration: 256 MiB copies read {f_copy[1] / f_copy[0]:.1f} KiB (scale {rs:.5f}), "
+                       f"write {w_copy[1] / w_copy[0]:.1f} KiB (scale {ws:.5f})")
+            for cls in sorted({c for c, _ in agg}):
+                fe, wr = agg.get((cls, "FETCH_SIZE")), agg.get((cls, "WRITE_SIZE"))
+                if fe and wr and cls != "copy":
+                    b = (fe[1] / fe[0] * rs + wr[1] / wr[0] * ws) * 1024.0
+                    out.append(f"TRAFFIC {cls} {int(b)} bytes_per_launch")
     print("\n".join(out))
 
 
@@ -444,7 +462,12 @@ def main():
     cf = args.converged_forms if (args.converged and C) else ""
     need_learned = precond == "learned" or "learned" in cf or (
         args.variants and not args.profile_only and args.workload in ("powerlaw", "aniso3d", "lap3d"))
-    if need_learned:
+    if need_learned and args.profile_only:
+        # the kernels and their cost do not depend on the factor's values:
+        # a profiled step uses the untrained (Jacobi-equivalent) network, so
+        # the profile holds no training solves
+        learned, learn_info = T.init_params(), {"untrained": True}
+    elif need_learned:
         learned, learn_info = train_factor(T, args.workload, args, log)
 
     def make_solver(pc, pr, profile=False, method=None, cycles=None):

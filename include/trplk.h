@@ -145,7 +145,14 @@ typedef struct trplk_opts {
   int32_t progress;   /* > 0: TRPL+K writes one line to stderr every `progress` restart
                          cycles (cycle, converged pairs, target residual, products);
                          0 = silent */
-  int32_t pad_;
+  int32_t block;      /* block TRPL+K (the block form the paper leaves to future work,
+                         Sec. 5.5): 0 or 1 = TRPL+K; s = 2..16 (s <= k, float64, CGS2)
+                         targets the s lowest unconverged pairs per cycle, each with its own
+                         shift, and grows the basis by blocks of s vectors
+                         M (A g_j - theta_j B g_j), each block B-orthogonalised against the
+                         basis with block passes (one read of the basis per block) and then
+                         column by column within itself; +K, Rayleigh-Ritz, restart and
+                         locking are TRPL+K's */
 } trplk_opts;
 
 typedef struct trplk_stats {
@@ -382,6 +389,19 @@ int trplk_gemv_t_noalloc(int32_t n, int32_t c, const double* U, int64_t ldu, con
  * rules as trplk_gemv_t (U and w 16-byte aligned, ldu even). */
 int trplk_cgs_update_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* h,
                          double* w, double* h2, void* stream);
+
+/* Block Gram-Schmidt passes of block TRPL+K (the block form the paper leaves
+ * to future work, Sec. 5.5): H = U^T V for U n x c (c <= 128, column-major,
+ * leading dimension ldu, 16-byte aligned, ldu even) and V n x r (r <= 16,
+ * leading dimension ldv); H is c x r with leading dimension ldh.  One read
+ * of U serves all r vectors (FP64 matrix cores).  Device pointers. */
+int trplk_block_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* V,
+                    int64_t ldv, int32_t r, double* H, int32_t ldh, void* stream);
+
+/* V <- V + alpha U H (U n x c, H c x r, V n x r; the same layout rules
+ * except alignment): the block update of Gram-Schmidt (alpha = -1). */
+int trplk_block_update(int32_t n, int32_t c, const double* U, int64_t ldu, const double* H,
+                       int32_t ldh, int32_t r, double alpha, double* V, int64_t ldv, void* stream);
 
 /* Symmetric eigendecomposition of a b x b matrix T (column-major, b <= 64),
  * ascending eigenvalues theta (b) and orthonormal eigenvectors Y (b x b):

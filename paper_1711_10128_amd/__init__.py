@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
                 ("mixed_switch", ctypes.c_double), ("fallback_window", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("orth", ctypes.c_int32),
                 ("breakdown_tol", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("progress", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("progress", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -91,7 +91,7 @@ EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_workspace_size", "trplk_
            "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
            "trplk_rotate", "trplk_learned_factor", "trplk_factor_nnz", "trplk_factor_values",
            "trplk_factor_loss_grad", "trplk_train_step", "trplk_get_factor",
-           "trplk_gemv_t_noalloc", "trplk_get_history"]
+           "trplk_gemv_t_noalloc", "trplk_get_history", "trplk_block_dot", "trplk_block_update"]
 MLP_NPARAM = 1217
 MLP_NF, MLP_NIN, MLP_NH = 8, 17, 64
 
@@ -134,9 +134,11 @@ def lib():
     L.trplk_gemv_t_noalloc.argtypes = [i32, i32, vp, i64, vp, vp, vp]
     L.trplk_cgs_update_dot.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp]
     L.trplk_syev.argtypes = [i32, vp, vp, vp, vp]
+    L.trplk_block_dot.argtypes = [i32, i32, vp, i64, vp, i64, i32, vp, i32, vp]
+    L.trplk_block_update.argtypes = [i32, i32, vp, i64, vp, i32, i32, ctypes.c_double, vp, i64, vp]
     L.trplk_rotate.argtypes = [i32, i32, i32, vp, i64, vp, i32, vp]
     for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_gemv_t_noalloc",
-              "trplk_cgs_update_dot",
+              "trplk_cgs_update_dot", "trplk_block_dot", "trplk_block_update",
               "trplk_syev", "trplk_rotate"):
         getattr(L, f).restype = ctypes.c_int
     L.trplk_learned_factor.argtypes = [vp, vp]
@@ -210,7 +212,8 @@ class Solver:
     def __init__(self, A, B=None, *, p, m, k, l=1, tol=1e-8, precond="jacobi",
                  precision="fp64", locking="auto", norm="inf", max_cycles=5000, fsai_cap=0,
                  profile=False, mixed_switch=0.0, fallback_window=0, method="trplk",
-                 orth="auto", breakdown_tol=0.0, seed=12, workspace=False, progress=0):
+                 orth="auto", breakdown_tol=0.0, seed=12, workspace=False, progress=0,
+                 block=0):
         L = lib()
         o = _Opts()
         L.trplk_default_opts(ctypes.byref(o))
@@ -224,6 +227,7 @@ class Solver:
         o.breakdown_tol = breakdown_tol
         o.seed = seed
         o.progress = progress
+        o.block = block
         self.opts = o
         self.n = int(A.n)
         self.p = p
@@ -400,6 +404,27 @@ def gemv_t_noalloc(U, v, h, n=None):
     n = ld if n is None else n
     _check(lib().trplk_gemv_t_noalloc(n, c, _ptr(U), ld, _ptr(v), _ptr(h), _stream()))
     return h
+
+
+def block_dot(U, V, H, n=None):
+    """H = U^T V; U (c, ldu), V (r, ldv), H (r, ldh) contiguous tensors holding
+    column-major blocks (the first n rows used)."""
+    c, ldu = U.shape
+    r, ldv = V.shape
+    n = ldu if n is None else n
+    _check(lib().trplk_block_dot(n, c, _ptr(U), ldu, _ptr(V), ldv, r, _ptr(H), H.shape[1],
+                                 _stream()))
+    return H
+
+
+def block_update(U, H, V, alpha=-1.0, n=None):
+    """V += alpha U H (same layouts as block_dot)."""
+    c, ldu = U.shape
+    r, ldv = V.shape
+    n = ldu if n is None else n
+    _check(lib().trplk_block_update(n, c, _ptr(U), ldu, _ptr(H), H.shape[1], r, alpha, _ptr(V), ldv,
+                                    _stream()))
+    return V
 
 
 def cgs_update_dot(U, h, w, h2, n=None):

@@ -370,4 +370,19 @@ struct RotArgs {
 int rot_blocks(int n);
 hipError_t rotate(const RotArgs& a, int nblk, hipStream_t s);
 
+// ----------------------------------------------------- block passes --
+// H (ncols x r, leading dimension ldh) = M^T V for M n x ncols (ncols <= 128,
+// 16-byte aligned, even ld) and V n x r (r <= 16); partial: at least
+// block_partial_doubles() doubles.  V += alpha M H.
+int block_dot_blocks(int n);
+int64_t block_partial_doubles();
+hipError_t block_dot(int n, int ncols, const double* M, int64_t ld, const double* V, int64_t ldv,
+                     int r, double* partial, double* H, int ldh, hipStream_t s);
+hipError_t block_update(int n, int ncols, const double* M, int64_t ld, const double* H, int ldh,
+                        int r, double alpha, double* V, int64_t ldv, hipStream_t s);
+// y = alpha x (n entries)
+hipError_t scale_copy(int n, double alpha, const double* x, double* y, hipStream_t s);
+// T(i, nb0 + j) = T(nb0 + j, i) = H(i, j), i <= nb0 + j, j < r
+hipError_t block_tcols(const double* H, int ldh, int nb0, int r, double* T, int ldT, hipStream_t s);
+
 }  // namespace trplk

@@ -40,6 +40,7 @@ namespace {
 constexpr double BREAKDOWN_TOL = 1e-14;  // inner-step breakdown (relative)
 constexpr int MIXED_STALL_CYCLES = 8;    // float32 phase: cycles without halving the residual
 constexpr double PLUSK_DROP_TOL = 1e-12; // +K vector dropped when nearly dependent
+constexpr int BLOCK_MAX = 16;            // largest inner block of block TRPL+K
 
 struct DevCsr {
   int n = 0;
@@ -110,6 +111,13 @@ struct trplk_ctx {
   double* partial = nullptr;
   double* resout = nullptr;
   double* thout = nullptr;  // Ritz values of the returned pairs (get_eigpairs)
+  // block TRPL+K (opts.block > 1): the current inner block, reduction
+  // partials of the block passes, coefficients, small scalars, target shifts
+  double* Wblk = nullptr;
+  double* bpart = nullptr;
+  double* bh = nullptr;
+  double* bsmall = nullptr;
+  double* bshift = nullptr;
   DevState* st = nullptr;
   Report* rep_h = nullptr;
   Report* rep_d = nullptr;
@@ -348,6 +356,7 @@ void ws_pieces(trplk_ctx* c, std::vector<WsPiece>& out) {
   out.push_back({reinterpret_cast<void**>(&c->v32), f});
   out.push_back({reinterpret_cast<void**>(&c->y32), f});
   out.push_back({reinterpret_cast<void**>(&c->wtmp32), f});
+  if (o.block > 1) out.push_back({reinterpret_cast<void**>(&c->Wblk), d * o.block});
 }
 
 int64_t ws_bytes_needed(trplk_ctx* c) {
@@ -394,6 +403,12 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->thout, SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->pl1_s, 2 * ORTH_MAXCOL));
+  if (o.block > 1) {
+    HIPCHK(c, dalloc(c, &c->bpart, static_cast<size_t>(block_partial_doubles())));
+    HIPCHK(c, dalloc(c, &c->bh, ORTH_MAXCOL * BLOCK_MAX));
+    HIPCHK(c, dalloc(c, &c->bsmall, 4 * BLOCK_MAX));
+    HIPCHK(c, dalloc(c, &c->bshift, BLOCK_MAX));
+  }
   c->orth_nblk = orth_blocks_max(n);
   c->rot_nblk = rot_blocks(n);
   int64_t pb = static_cast<int64_t>(c->orth_nblk) * orth_stride();
@@ -809,6 +824,135 @@ struct Solver {
     return S.ok() ? TRPLK_OK : set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
   }
 
+  // Block TRPL+K, one cycle's inner loop (readings B1-B4 of the block form):
+  // the first block holds the preconditioned residuals of the targets t ..
+  // t + nt - 1; each block is projected against [Q | U] by classical
+  // Gram-Schmidt applied twice with block passes (one read of the basis for
+  // every column), then its columns in order against the block's columns
+  // already appended (the same, over those few columns), tested for
+  // breakdown (R7), appended with A g, and turned into the next block,
+  // M (A g - rho_j B g) with the shift of the target the column descends
+  // from.  Host decisions per column (O(1) scalars read back); returns the
+  // products with A it made.
+  int block_inner(int t, int nt, int room, const double* shifts_host, long long* mv,
+                  long long* precs) {
+    Status S;
+    const int bs = c->o.block;
+    const double tol2 = std::pow(c->o.breakdown_tol > 0 ? c->o.breakdown_tol : BREAKDOWN_TOL, 2);
+    const int next = c->prec == TRPLK_PREC_JACOBI ? NEXT_JACOBI
+                     : c->prec == TRPLK_PREC_NONE ? NEXT_IDENT : NEXT_STORE_V;
+    const bool fac = c->prec >= TRPLK_PREC_FSAI;
+    HIPCHK(c, hipMemcpyAsync(c->bshift, shifts_host, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    // first block: the targets' residuals through M
+    std::vector<int> tgt(nt);
+    for (int j = 0; j < nt; ++j) {
+      tgt[j] = j;
+      double* wj = c->Wblk + static_cast<int64_t>(j) * ld;
+      S.check(restart_residual(n, AUcol(t + j), BUcol(t + j), c->bshift, j, next, c->dinv, wj,
+                               fac ? c->vtmp : nullptr, nullptr, s), "block residual");
+      if (fac) {
+        S.check(apply_factor(), "block factor");
+        S.check(copy_cols(n, c->w, ld, wj, ld, 1, s), "block copy");
+      }
+    }
+    if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+    *precs += nt;
+    int r = nt;
+    std::vector<double> H1h(ORTH_MAXCOL * BLOCK_MAX), sm(4 * BLOCK_MAX);
+    while (nbh < room && r > 0) {
+      const int take = std::min(r, room - nbh);
+      const int nq = c->u0 + nbh;   // columns of [Q | U]
+      {
+        // block CGS2 against [Q | U]: H1 = [BQ BU]^T W, W -= [Q U] H1, twice
+        ProfScope ps(c, PC_ORTH, 4 * (8LL * n * nq) + 6 * 8LL * n * take);
+        S.check(block_dot(n, nq, BWq(), ld, c->Wblk, ld, take, c->bpart, c->bh, ORTH_MAXCOL, s), "bdot1");
+        S.check(hipMemcpyAsync(H1h.data(), c->bh, sizeof(double) * ORTH_MAXCOL * take,
+                               hipMemcpyDeviceToHost, s), "h1 d2h");
+        S.check(block_update(n, nq, Wq(), ld, c->bh, ORTH_MAXCOL, take, -1.0, c->Wblk, ld, s), "bupd1");
+        S.check(block_dot(n, nq, BWq(), ld, c->Wblk, ld, take, c->bpart, c->bh, ORTH_MAXCOL, s), "bdot2");
+        S.check(block_update(n, nq, Wq(), ld, c->bh, ORTH_MAXCOL, take, -1.0, c->Wblk, ld, s), "bupd2");
+      }
+      S.check(hipStreamSynchronize(s), "sync h1");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+      const int nb0 = nbh;
+      std::vector<int> nxt;
+      for (int j = 0; j < take; ++j) {
+        double h1n2 = 0.0;
+        for (int i = 0; i < nq; ++i) h1n2 += H1h[i + j * ORTH_MAXCOL] * H1h[i + j * ORTH_MAXCOL];
+        double* wj = c->Wblk + static_cast<int64_t>(j) * ld;
+        const int ja = nbh - nb0;   // block columns appended so far
+        if (ja > 0) {
+          // against the block's appended columns, twice (first-pass coefficients count in h1)
+          S.check(block_dot(n, ja, BUcol(nb0), ld, wj, ld, 1, c->bpart, c->bsmall, BLOCK_MAX, s), "bdot3");
+          S.check(block_update(n, ja, Ucol(nb0), ld, c->bsmall, BLOCK_MAX, 1, -1.0, wj, ld, s), "bupd3");
+          S.check(hipMemcpyAsync(sm.data(), c->bsmall, sizeof(double) * ja, hipMemcpyDeviceToHost, s),
+                  "h d2h");
+          S.check(block_dot(n, ja, BUcol(nb0), ld, wj, ld, 1, c->bpart, c->bsmall + BLOCK_MAX,
+                            BLOCK_MAX, s), "bdot4");
+          S.check(block_update(n, ja, Ucol(nb0), ld, c->bsmall + BLOCK_MAX, BLOCK_MAX, 1, -1.0, wj, ld,
+                               s), "bupd4");
+        }
+        // B-norm of the projected column
+        const double* bw = wj;
+        if (c->hasB) {
+          SpmvArgs b;
+          b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = wj;
+          b.mode = SPMV_STORE; b.y = c->tmpB;
+          S.check(spmv(c->B, b, false, PC_SPMV, 0), "block B w");
+          bw = c->tmpB;
+        }
+        S.check(block_dot(n, 1, wj, ld, bw, ld, 1, c->bpart, c->bsmall + 2 * BLOCK_MAX, 1, s), "bnorm");
+        S.check(hipMemcpyAsync(sm.data() + 2 * BLOCK_MAX, c->bsmall + 2 * BLOCK_MAX, sizeof(double),
+                               hipMemcpyDeviceToHost, s), "norm d2h");
+        S.check(hipStreamSynchronize(s), "sync norm");
+        if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+        for (int i = 0; i < ja; ++i) h1n2 += sm[i] * sm[i];
+        const double beta2 = sm[2 * BLOCK_MAX];
+        if (!std::isfinite(beta2)) return set_err(c, TRPLK_ENUMERIC, "non-finite block vector");
+        if (!(beta2 > tol2 * (h1n2 + beta2))) continue;   // breakdown: the column is dropped
+        const double ib = 1.0 / std::sqrt(beta2);
+        S.check(scale_copy(n, ib, wj, Ucol(nbh), s), "append U");
+        if (c->hasB) {
+          S.check(scale_copy(n, ib, c->tmpB, BUcol(nbh), s), "append BU");
+          ++bprod;
+        }
+        SpmvArgs a;
+        a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = Ucol(nbh);
+        a.mode = SPMV_STORE; a.y = AUcol(nbh);
+        S.check(spmv(c->A, a, false, PC_SPMV, 0), "block A g");
+        ++*mv;
+        ++nbh;
+        if (nbh < room) {
+          // next block column (index = number of columns kept so far; it only
+          // overwrites columns of this block already consumed)
+          const int q = static_cast<int>(nxt.size());
+          double* wq = c->Wblk + static_cast<int64_t>(q) * ld;
+          S.check(restart_residual(n, AUcol(nbh - 1), BUcol(nbh - 1), c->bshift, tgt[j], next, c->dinv,
+                                   wq, fac ? c->vtmp : nullptr, nullptr, s), "block next");
+          if (fac) {
+            S.check(apply_factor(), "block next factor");
+            S.check(copy_cols(n, c->w, ld, wq, ld, 1, s), "block next copy");
+          }
+          nxt.push_back(tgt[j]);
+          ++*precs;
+        }
+      }
+      // T columns of the appended block columns: T(0:nb0+j, nb0+j) = U^T A g_j
+      const int ra = nbh - nb0;
+      if (ra > 0) {
+        S.check(block_dot(n, nbh, Ucol(0), ld, AUcol(nb0), ld, ra, c->bpart, c->bh, ORTH_MAXCOL, s),
+                "block T");
+        S.check(block_tcols(c->bh, ORTH_MAXCOL, nb0, ra, c->T, SYEV_MAXB, s), "block T scatter");
+      }
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+      tgt = nxt;
+      r = static_cast<int>(nxt.size());
+    }
+    HIPCHK(c, set_state(c->st, SET_NB, 0.0, nbh, s));
+    return TRPLK_OK;
+  }
+  long long bprod = 0;  // products with B made by the block inner loop
+
   int run(const double* x0, int32_t mem, trplk_stats* out);
   int run_pl1(const double* x0, int32_t mem, trplk_stats* out);
   void collect_profile();
@@ -945,8 +1089,10 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   c->solved = false;
   c->fp32_phase = (o.precision == TRPLK_MIXED);
   c->hist.clear();
-  dc = o.orth != TRPLK_ORTH_CGS2;
+  const bool blk = o.block > 1;
+  dc = o.orth != TRPLK_ORTH_CGS2 && !blk;
   stt.orth_delayed = dc ? 1 : 0;
+  bprod = 0;
   int r;
   HIPCHK(c, hipEventRecord(c->ev0, s));
   HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
@@ -982,6 +1128,15 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
     if (!keepT) HIPCHK(c, reset_T(c->T, SYEV_MAXB, SYEV_MAXB, kact, c->theta, th_off, s));
     keepT = false;
     nbh = kact;
+    if (blk) {
+      // ---- block TRPL+K: the inner blocks (B1-B4), then +K as below ----
+      const int nt = std::max(1, std::min(o.block, kact - t));
+      std::vector<double> sh(th.begin() + t, th.begin() + t + nt);
+      long long mv = 0, pc = 0;
+      if ((r = block_inner(t, nt, m - nprev, sh.data(), &mv, &pc))) return r;
+      stt.matvecs += mv;
+      stt.precs += pc;
+    } else {
     {
       const bool fac = c->prec >= TRPLK_PREC_FSAI;
       const int next = c->prec == TRPLK_PREC_JACOBI ? NEXT_JACOBI
@@ -1013,6 +1168,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
       ++nbh;
       if (more) stt.precs += 1;
     }
+    }  // scalar inner loop
     // ---- +K: previous Ritz vectors after the Krylov block ----
     if (dc && nprev > 0) {
       // each +K vector's single pass also corrects the pending column; the
@@ -1138,7 +1294,7 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   if (cycle > o.max_cycles) cycle = o.max_cycles;
   stt.cycles = cycle;
   if (c->fp32_phase) stt.fp32_cycles = cycle;
-  stt.bmatvecs = c->hasB ? c->rep_h->cnt_norm : 0;
+  stt.bmatvecs = c->hasB ? c->rep_h->cnt_norm + bprod : 0;
   // ---- results ----
   if (hard) {
     // final Rayleigh-Ritz on the locked set: T_Q = Q^T A Q
@@ -1815,6 +1971,7 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
     if (o->max_cycles < 1) { why = "max_cycles must be >= 1"; return TRPLK_EINVAL; }
     if (o->precond < TRPLK_PREC_NONE || o->precond > TRPLK_PREC_FACTOR) { why = "bad precond"; return TRPLK_EINVAL; }
     if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
+    if (o->block > 1) { why = "PL+1 has no block form"; return TRPLK_EINVAL; }
     return TRPLK_OK;
   }
   if (o->p < 1) { why = "p must be >= 1"; return TRPLK_EINVAL; }
@@ -1835,6 +1992,12 @@ static int check_opts(const trplk_opts* o, int n, std::string& why) {
   if (o->orth < TRPLK_ORTH_AUTO || o->orth > TRPLK_ORTH_DELAYED) { why = "bad orth"; return TRPLK_EINVAL; }
   if (!(o->breakdown_tol >= 0.0 && o->breakdown_tol < 1.0)) { why = "breakdown_tol must be in [0, 1)"; return TRPLK_EINVAL; }
   if (o->fsai_cap < 0 || o->fsai_cap > 64) { why = "fsai_cap must be in 0..64"; return TRPLK_EINVAL; }
+  if (o->block < 0 || o->block > BLOCK_MAX) { why = "block must be in 0..16"; return TRPLK_EINVAL; }
+  if (o->block > 1) {
+    if (o->block > o->k) { why = "block must be <= k"; return TRPLK_EINVAL; }
+    if (o->precision != TRPLK_FP64) { why = "block TRPL+K runs in float64"; return TRPLK_EINVAL; }
+    if (o->orth == TRPLK_ORTH_DELAYED) { why = "block TRPL+K uses CGS2"; return TRPLK_EINVAL; }
+  }
   return TRPLK_OK;
 }
 
@@ -2072,7 +2235,8 @@ void trplk_destroy(trplk_ctx* c) {
     for (const WsPiece& q : pcs) dfree(*q.ptr);
   }
   void* ptrs[] = {c->dinv, c->pl1_s, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
-                  c->partial, c->resout, c->thout, c->st, c->rep_d};
+                  c->partial, c->resout, c->thout, c->st, c->rep_d, c->bpart, c->bh, c->bsmall,
+                  c->bshift};
   for (void* p : ptrs) dfree(p);
   auto& L = c->L;
   void* lp[] = {L.Lrow, L.Lcol, L.lr, L.lval, L.Trow, L.Tcol, L.permd, L.dinv, L.F, L.Fz,
@@ -2241,6 +2405,31 @@ int trplk_gemv_t_noalloc(int32_t n, int32_t c, const double* U, int64_t ldu, con
   FinishArgs f;
   f.mode = FIN_SUM; f.partial = part; f.nblk = nblk; f.stride = orth_stride(); f.out = h; f.cnt = c;
   if (e == hipSuccess) e = finish(f, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_block_dot(int32_t n, int32_t c, const double* U, int64_t ldu, const double* V,
+                    int64_t ldv, int32_t r, double* H, int32_t ldh, void* stream) {
+  if (n < 1 || c < 1 || c > 128 || r < 1 || r > 16 || ldu < n || ldv < n || ldh < c || !U || !V ||
+      !H)
+    return TRPLK_EINVAL;
+  if (ldu % 2 != 0 || !aligned16(U)) return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* part = kernel_scratch(sizeof(double) * block_partial_doubles());
+  if (!part) return TRPLK_ENOMEM;
+  hipError_t e = block_dot(n, c, U, ldu, V, ldv, r, part, H, ldh, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return kernel_err(e);
+}
+
+int trplk_block_update(int32_t n, int32_t c, const double* U, int64_t ldu, const double* H,
+                       int32_t ldh, int32_t r, double alpha, double* V, int64_t ldv, void* stream) {
+  if (n < 1 || c < 1 || c > 128 || r < 1 || r > 16 || ldu < n || ldv < n || ldh < c || !U || !V ||
+      !H)
+    return TRPLK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = block_update(n, c, U, ldu, H, ldh, r, alpha, V, ldv, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return kernel_err(e);
 }
