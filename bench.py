@@ -48,7 +48,9 @@ WORKLOADS = {
                      desc="shifted Laplacian of a Chung-Lu power-law graph, n=1e6",
                      # gather-bound SpMV and well-separated wanted eigenvalues: a long
                      # float32 phase pays here (measured), unlike on the grids
-                     mixed_switch=1e-5),
+                     mixed_switch=1e-5,
+                     # hub rows: FSAI keeps the 63 largest lower entries and the diagonal
+                     fsai_cap=64),
     "aniso3d": dict(gen=dict(N=256, sigma=1.0), p=50, m=64, k=32, form=("learned", "mixed"),
                     cycles=10,
                     desc="anisotropic 7-point diffusion 256^3 (axis weights 1, 1e-2, 1e-4 x "
@@ -128,6 +130,8 @@ def parse():
                          "thick-restart Lanczos) and print one JSON line with every setting")
     ap.add_argument("--sweep-values", default="", help="comma-separated values (default per sweep)")
     ap.add_argument("--max-cycles", type=int, default=5000, help="cap of a complete solve")
+    ap.add_argument("--block", type=int, default=0,
+                    help="block TRPL+K with this block size (2..16, float64) for the timed form")
     ap.add_argument("--progress", type=int, default=0,
                     help="complete solves print a line every this many cycles (0 = silent)")
     ap.add_argument("--protocol", action="store_true",
@@ -206,12 +210,14 @@ def run_protocol(args, T, log):
         P = probs[sd]
         Ad = T.DeviceCSR(P.A)
         dev.append(Ad)
-        for cycles in (300, 1, 3):
+        # two harvest solves per graph (to tol 1e-6 and stopped after 3
+        # cycles) and 32 pairs each keep the 48 training contexts in memory
+        for cycles in (300, 3):
             solvers.append(T.Solver(Ad, None, p=min(P.p, P.k), m=P.m, k=P.k, l=1, tol=1e-6,
                                     precond="jacobi", max_cycles=cycles))
             X0s.append(start_block(P.A.n, P.k, sd))
     t1 = time.time()
-    params, hist = T.train(solvers, X0s, epochs=args.epochs, lr=1e-3, S=min(64, P.m))
+    params, hist = T.train(solvers, X0s, epochs=args.epochs, lr=1e-3, S=32)
     t2 = time.time()
     for s in solvers:
         s.close()
@@ -229,7 +235,8 @@ def run_protocol(args, T, log):
         for pc, pr in forms:
             S = T.Solver(Ad, None, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol,
                          precond="jacobi" if pc == "learned" else pc, precision=pr,
-                         mixed_switch=WORKLOADS["powerlaw"].get("mixed_switch", 0.0))
+                         mixed_switch=WORKLOADS["powerlaw"].get("mixed_switch", 0.0),
+                         fsai_cap=WORKLOADS["powerlaw"]["fsai_cap"])
             if pc == "learned":
                 S.learned_factor(params)
             S.solve(Xd)
@@ -259,7 +266,9 @@ def run_protocol(args, T, log):
         summary[k]["speedup_vs_jacobi_fp64"] = round(base / summary[k]["mean_s"], 3)
     print(json.dumps({"protocol": "power-law learned factor: 24 train / 8 held-out at n = 1e6",
                       "train_seeds": train_seeds, "test_seeds": test_seeds,
-                      "train": {"epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1],
+                      "train": {"epochs": args.epochs, "pairs_per_solve": 32,
+                                "harvest_solves_per_graph": 2,
+                                "loss_first": hist[0], "loss_last": hist[-1],
                                 "seconds": round(t2 - t1, 1)},
                       "summary": summary, "per_graph": rows}))
 
@@ -473,10 +482,12 @@ def main():
     def make_solver(pc, pr, profile=False, method=None, cycles=None):
         base = "jacobi" if pc == "learned" else pc
         cap = (C or args.max_cycles) if cycles is None else cycles
+        blk = args.block if (pc, pr) == (precond, precision) and not method else 0
         s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=base,
                      precision=pr, profile=profile, max_cycles=cap, seed=P.seed,
                      method=method or args.method, mixed_switch=W.get("mixed_switch", 0.0),
-                     progress=args.progress if cap > 100 else 0)
+                     progress=args.progress if cap > 100 else 0, block=blk,
+                     fsai_cap=W.get("fsai_cap", 0))
         if pc == "learned":
             s.learned_factor(learned)
         return s
@@ -653,6 +664,7 @@ def main():
         "config": {"workload": f"{W['desc']}, p={P.p} m={P.m} k={P.k} l={P.l} tol=1e-8*||A||_inf, "
                                f"{'hard' if P.p > P.k else 'soft'} locking, {precond} {precision}"
                                + ("" if args.method == "trplk" else f", {args.method}")
+                               + (f", block size {args.block}" if args.block > 1 else "")
                                + f"; {step_desc}",
                    "name": args.workload, "n": P.A.n, "nnz": P.A.nnz,
                    "generalized": P.B is not None, "cycles_per_step": C or None},

@@ -148,6 +148,7 @@ struct trplk_ctx {
     bool ready = false;
     bool pairs = false;
     int S = 0;
+    int pair_cap = 0;   // pairs the pair buffers hold
     int64_t nnz = 0;
     int* Lrow = nullptr;
     int* Lcol = nullptr;
@@ -1777,10 +1778,20 @@ int learn_prepare(trplk_ctx* c) {
   return TRPLK_OK;
 }
 
-int learn_alloc_pairs(trplk_ctx* c) {
+// Pair buffers sized for S pairs (grown when a later call asks for more): six
+// n x S blocks, so a context trained on few pairs holds little memory.
+int learn_alloc_pairs(trplk_ctx* c, int S) {
   auto& L = c->L;
-  if (L.Er) return TRPLK_OK;
-  const int64_t nS = static_cast<int64_t>(c->n) * LEARN_MAXS;
+  if (L.Er && L.pair_cap >= S) return TRPLK_OK;
+  if (L.Er) {
+    void* lp[] = {L.Er, L.Rr, L.Y, L.D, L.Uu, L.Z, L.coef, L.w, L.dout};
+    for (void* q : lp) dfree(q);
+    L.Er = L.Rr = L.Y = L.D = L.Uu = L.Z = L.coef = L.w = nullptr;
+    L.dout = nullptr;
+    L.pairs = false;
+  }
+  L.pair_cap = S;
+  const int64_t nS = static_cast<int64_t>(c->n) * S;
   HIPCHK(c, dalloc(c, &L.Er, nS));
   HIPCHK(c, dalloc(c, &L.Rr, nS));
   HIPCHK(c, dalloc(c, &L.Y, nS));
@@ -1881,7 +1892,7 @@ int trplk_factor_loss_grad(trplk_ctx* c, const float* params, int32_t S, const d
   if (!c || !params || !E || !R || !loss || !grad) return set_err(c, TRPLK_EINVAL, "null argument");
   if (S < 1 || S > LEARN_MAXS) return set_err(c, TRPLK_EINVAL, "S must be in 1..64");
   int r;
-  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
+  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c, S))) return r;
   auto& L = c->L;
   const int n = c->n;
   const int64_t nS = static_cast<int64_t>(n) * S;
@@ -1908,7 +1919,7 @@ int trplk_train_step(trplk_ctx* c, float* params, float* adam_m, float* adam_v, 
   if (step < 1) return set_err(c, TRPLK_EINVAL, "step counts from 1");
   if (S < 1 || S > LEARN_MAXS || S > c->m) return set_err(c, TRPLK_EINVAL, "S must be in 1..min(64, m)");
   int r;
-  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c))) return r;
+  if ((r = learn_prepare(c)) || (r = learn_alloc_pairs(c, S))) return r;
   auto& L = c->L;
   const int n = c->n;
   if (!L.pairs || L.S != S) {
