@@ -128,6 +128,10 @@ def parse():
     ap.add_argument("--precision", default="", choices=["", "fp64", "mixed"])
     ap.add_argument("--variants", type=int, default=1, help="also time the other forms once")
     ap.add_argument("--cpu", type=int, default=1, help="time the CPU oracle on the same input")
+    ap.add_argument("--cpu-size", type=int, default=-1,
+                    help="grid edge of the instance the CPU oracle is timed on when a step is a "
+                         "number of cycles (default 96 for the 256^3 workload: one oracle cycle "
+                         "at full size takes minutes; 0 = the full size)")
     ap.add_argument("--train-count", type=int, default=6, help="learned factor: training instances")
     ap.add_argument("--train-size", type=int, default=0, help="learned factor: training instance size")
     ap.add_argument("--epochs", type=int, default=120)
@@ -375,15 +379,17 @@ def kernel_profile(sp, st, log):
     return classes
 
 
-def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log):
-    """The FP64 NumPy/SciPy oracle on the same input, on this host's cores.
+def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log, n_full=None):
+    """The FP64 NumPy/SciPy oracle on this host's cores.
 
     Per-cycle time: from the oracle's hook before the Rayleigh-Ritz of cycle 1
     to the same point of cycle 2, i.e. exactly one full restart cycle (its
     start-block phase excluded).  A step of C cycles is priced at C times
-    that; a complete-solve step at the oracle's own cycle count when the
-    full-size reference run (tests/golden) records one, else the sample's
-    per-cycle time times the GPU's cycles (labelled)."""
+    that (times n_full / n when the oracle ran on a smaller instance of the
+    same generator: at fixed p, m, k a cycle's work is linear in n); a
+    complete-solve step at the oracle's own cycle count when the full-size
+    reference run (tests/golden) records one, else the sample's per-cycle
+    time times the GPU's cycles (labelled)."""
     from oracle import trplk as O
     A = P.A.to_scipy()
     B = None if P.B is None else P.B.to_scipy()
@@ -399,11 +405,19 @@ def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log):
             "threads_note": f"NumPy BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}; "
                             "SciPy SpMV single-threaded"}
     if cycles_per_step:
-        return dict(base, value=round(per_cycle * cycles_per_step, 3),
-                    sample=f"FP64 oracle (Jacobi) on the same full-size input and start block: one "
-                           f"complete restart cycle (cycle 1 -> 2, hook to hook) took "
-                           f"{per_cycle:.2f} s of {c1 - c0:.1f} s (start block + 2 cycles); value "
-                           f"= {cycles_per_step} cycles, the GPU step's unit")
+        n = P.A.n
+        scale = (n_full or n) / n
+        where = ("the same full-size input and start block" if scale == 1 else
+                 f"the n = {n:,} instance of the same generator (same p, m, k, seed, start-block "
+                 f"definition)")
+        return dict(base, value=round(per_cycle * scale * cycles_per_step, 3),
+                    sample=f"FP64 oracle (Jacobi) on {where}: one complete restart cycle (cycle "
+                           f"1 -> 2, hook to hook) took {per_cycle:.2f} s of {c1 - c0:.1f} s (start "
+                           f"block + 2 cycles); value = that"
+                           + (f" x {scale:.2f} (n_full / n: a cycle's work is linear in n at fixed "
+                              f"p, m, k; extrapolated in n)" if scale != 1 else "")
+                           + f" x {cycles_per_step} cycles, the GPU step's unit",
+                    n_sample=n)
     gold = None
     try:
         sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
@@ -700,8 +714,13 @@ def main():
     # ---- CPU oracle on the same input ----
     cpu = None
     if args.cpu and args.method == "trplk":
-        X0h = splitmix64_block(P.A.n, P.k, P.seed) if C else start_block(P.A.n, P.k, P.seed)
-        cpu = cpu_oracle(P, X0h, C, st["cycles"], log)
+        Pc = P
+        if C:
+            csize = args.cpu_size if args.cpu_size >= 0 else (96 if args.workload == "aniso3d" else 0)
+            if csize and csize < (args.size or list(W["gen"].values())[0]):
+                Pc = make_workload(args.workload, csize)
+        X0h = splitmix64_block(Pc.A.n, Pc.k, Pc.seed) if C else start_block(Pc.A.n, Pc.k, Pc.seed)
+        cpu = cpu_oracle(Pc, X0h, C, st["cycles"], log, n_full=P.A.n)
         del X0h
 
     if C:

@@ -197,3 +197,27 @@ def test_full_size_eigenvalues_match_oracle(T, case, name, prec, precision, same
             cert = np.full_like(th, np.inf)
         allow = np.maximum(floor, np.minimum(cert, 1e-8 * np.abs(th)))
         assert np.all(np.abs(ev - th) <= allow)
+
+
+def test_anisotropic_constant_field_closed_form(T):
+    """The anisotropic operator with a constant coefficient field (sigma = 0)
+    on 64^3: its eigenvalues are a_x 4 s_i + a_y 4 s_j + a_z 4 s_k with
+    s_x = sin^2(x pi / (2 (N + 1))) and axis weights (1, 1e-2, 1e-4); the 50
+    smallest (all with i = j = 1, a cluster 7% wide) from the p50 m64 k32
+    hard-locking solve in the workload's configuration, to 1e-10 relative."""
+    from workloads import aniso3d
+    N = 64
+    A = aniso3d(N, sigma=0.0, seed=12)
+    s1 = 4 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    lam = np.sort((s1[:, None, None] + 1e-2 * s1[None, :, None]
+                   + 1e-4 * s1[None, None, :]).ravel())[:50]
+    print(f"aniso sigma=0 N={N}", flush=True)
+    S = T.Solver(T.DeviceCSR(A), None, p=50, m=64, k=32, l=1, tol=1e-8, precond="jacobi")
+    st = S.solve(None)
+    ev, X, res, conv = S.eigpairs()
+    S.close()
+    print(f"  cycles={st['cycles']} mv={st['matvecs']} max rel err "
+          f"{np.max(np.abs(ev - lam) / lam):.2e}", flush=True)
+    assert conv.all() and np.all(res <= 1e-8 * st["normA"] * 1.001)
+    assert abs(st["normA"] - 4 * (1 + 1e-2 + 1e-4)) < 1e-12
+    assert np.all(np.abs(ev - lam) <= 1e-10 * lam)
