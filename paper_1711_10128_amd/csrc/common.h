@@ -129,6 +129,15 @@ struct SpmvPlan {
   int* dia_off = nullptr;       // device, ndiag column offsets (col - row)
   double* dia_val = nullptr;    // device, ndiag * n (float64 products)
   float* dia_val32 = nullptr;   // device, ndiag * n (float32 products)
+  // x staged in LDS per 256-row chunk: the offsets fall into ncl clusters
+  // (windows of 256 + span rows); diagonal d reads window entry doff[d] + row
+  // - chunk start.  ncl = 0: no staging (the windows would not fit).
+  int ncl = 0;
+  int cl_lo[8] = {};
+  int cl_len[8] = {};
+  int cl_base[8] = {};
+  int doff[32] = {};
+  int lds_elems = 0;
   int nblk_dia = 0;             // grid of the diagonal kernel
 };
 constexpr int DIA_MAXD = 32;
