@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libtrplk.so")
-SOURCES = ["spmv.hip", "orth.hip", "syev.hip", "rotate.hip", "block.hip", "fsai.hip", "learn.hip",
+SOURCES = ["spmv.hip", "orth.hip", "syev.hip", "rotate.hip", "block.hip", "pencil.hip", "fsai.hip", "learn.hip",
            "solver.hip"]
 
 HIPCC_FLAGS = [

@@ -28,6 +28,7 @@ struct DevState {
   long long cnt_append;  // vectors appended to the basis (one A product each)
   long long cnt_norm;    // B-norm evaluations (one B product each when B != I)
   double inv_gamma;      // delayed correction: 1 / ||u' - U c|| of the column being corrected
+  int pl1_err;           // PL+1 projected pencil: 0 ok, 1 not positive definite, 2 non-finite, 3 zero direction
 };
 
 // Launch-error helper: records the first failing call.
@@ -359,6 +360,17 @@ constexpr int SYEV_MAXB = 64;
 // null), column-major with leading dimension ldT.
 hipError_t syev(const double* T, int ldT, int b_fixed, const int* nb_dev, int nb_offset,
                 double* theta, double* Y, int ldY, hipStream_t s);
+
+// PL+1's projected pencil (pencil.hip): the lowest pair of (Q^T A Q, Q^T B Q)
+// for Q = [x_k, G_k, p_{k-1}] (q = nq columns, p_{k-1} last when use_p; S: B
+// inner products of x_k at S[0..nq) and of p_{k-1} at S[sp..sp+nq)), turned
+// into the two rotation columns for x_{k+1} and p_k (Y, ld ldY), theta[0] =
+// the Ritz value, st->nb = the columns used; failures in st->pl1_err.
+// work: pl1_work_doubles() doubles, qdev: 2 ints (device).
+int64_t pl1_work_doubles();
+hipError_t pl1_pencil(const double* T, int ldT, const double* S, int sp, int nq, bool use_p, bool conj,
+                      double rho_prev, double* work, int* qdev, double* Y, int ldY, double* theta,
+                      DevState* st, hipStream_t s);
 
 struct RotArgs {
   int n = 0;

@@ -56,7 +56,8 @@ struct DevCsr {
 struct Report {
   int nb;
   int bad;
-  int pad[2];
+  int pl1_err;
+  int pad;
   long long cnt_append;
   long long cnt_norm;
   double theta[SYEV_MAXB];
@@ -101,6 +102,8 @@ struct trplk_ctx {
   double* pl1_Ap = nullptr;  // PL+1: A p and B p of the search direction (p itself in Xprev)
   double* pl1_Bp = nullptr;
   double* pl1_s = nullptr;   // PL+1: border of Q^T B Q (2 * ORTH_MAXCOL)
+  double* pl1_work = nullptr;  // PL+1: the projected pencil's matrices (pl1_work_doubles())
+  int* pl1_q = nullptr;        // PL+1: columns of the pencil used, p_{k-1} kept
   double* T = nullptr;
   double* theta = nullptr;
   double* Y = nullptr;
@@ -404,6 +407,10 @@ int ensure_workspace(trplk_ctx* c) {
   HIPCHK(c, dalloc(c, &c->resout, 2 * SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->thout, SYEV_MAXB));
   HIPCHK(c, dalloc(c, &c->pl1_s, 2 * ORTH_MAXCOL));
+  if (o.method != TRPLK_METHOD_TRPLK) {
+    HIPCHK(c, dalloc(c, &c->pl1_work, static_cast<size_t>(pl1_work_doubles())));
+    HIPCHK(c, dalloc(c, &c->pl1_q, 2));
+  }
   if (o.block > 1) {
     HIPCHK(c, dalloc(c, &c->bpart, static_cast<size_t>(block_partial_doubles())));
     HIPCHK(c, dalloc(c, &c->bh, ORTH_MAXCOL * BLOCK_MAX));
@@ -460,6 +467,7 @@ __global__ void k_report(const DevState* st, const double* theta, const double* 
   if (t == 0) {
     rep->nb = st->nb;
     rep->bad = st->bad;
+    rep->pl1_err = st->pl1_err;
     rep->cnt_append = st->cnt_append;
     rep->cnt_norm = st->cnt_norm;
   }
@@ -959,114 +967,6 @@ struct Solver {
   void collect_profile();
 };
 
-// ---------------------------------------------------------- PL+1 helpers --
-// Small dense symmetric algebra on the host for the (<= 64) projected pencil.
-
-// Cholesky T = L L^T of an n x n row-major matrix; false if not positive
-// definite (a pivot <= eps_rel * the largest diagonal).
-bool host_cholesky(const std::vector<double>& T, int n, std::vector<double>& L) {
-  L.assign(static_cast<size_t>(n) * n, 0.0);
-  double dmax = 0.0;
-  for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(T[i * n + i]));
-  for (int j = 0; j < n; ++j) {
-    double d = T[j * n + j];
-    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
-    if (!(d > 1e-12 * dmax)) return false;
-    const double ljj = std::sqrt(d);
-    L[j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      double v = T[i * n + j];
-      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
-      L[i * n + j] = v / ljj;
-    }
-  }
-  return true;
-}
-
-// Cyclic Jacobi eigenvalue iteration (row-major, symmetric); on return the
-// eigenvalues are in `lam` and the eigenvectors in the columns of V.
-void host_jacobi_eig(std::vector<double> C, int n, std::vector<double>& lam,
-                     std::vector<double>& V) {
-  V.assign(static_cast<size_t>(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, fro = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        fro += C[i * n + j] * C[i * n + j];
-        if (i != j) off += C[i * n + j] * C[i * n + j];
-      }
-    if (off <= 1e-30 * fro) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = C[p * n + q];
-        if (apq == 0.0) continue;
-        const double tau = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double ckp = C[k * n + p], ckq = C[k * n + q];
-          C[k * n + p] = cs * ckp - sn * ckq;
-          C[k * n + q] = sn * ckp + cs * ckq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double cpk = C[p * n + k], cqk = C[q * n + k];
-          C[p * n + k] = cs * cpk - sn * cqk;
-          C[q * n + k] = sn * cpk + cs * cqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[k * n + p], vkq = V[k * n + q];
-          V[k * n + p] = cs * vkp - sn * vkq;
-          V[k * n + q] = sn * vkp + cs * vkq;
-        }
-      }
-  }
-  lam.resize(n);
-  for (int i = 0; i < n; ++i) lam[i] = C[i * n + i];
-}
-
-// Lowest eigenpair of the pencil (TA, TB), TB = L L^T: w = L^{-T} y with
-// (L^{-1} TA L^{-T}) y = lambda y.  Row-major n x n inputs.
-void host_lowest_pair(const std::vector<double>& TA, const std::vector<double>& L, int n,
-                      double& lambda, std::vector<double>& w) {
-  // X = L^{-1} TA (forward substitution per column), C = X L^{-T}
-  std::vector<double> X(static_cast<size_t>(n) * n), C(static_cast<size_t>(n) * n);
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) {
-      double v = TA[i * n + j];
-      for (int k = 0; k < i; ++k) v -= L[i * n + k] * X[k * n + j];
-      X[i * n + j] = v / L[i * n + i];
-    }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double v = X[i * n + j];
-      for (int k = 0; k < j; ++k) v -= C[i * n + k] * L[j * n + k];
-      C[i * n + j] = v / L[j * n + j];
-    }
-  for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) C[i * n + j] = C[j * n + i] = 0.5 * (C[i * n + j] + C[j * n + i]);
-  std::vector<double> lam, V;
-  host_jacobi_eig(C, n, lam, V);
-  int imin = 0;
-  for (int i = 1; i < n; ++i)
-    if (lam[i] < lam[imin]) imin = i;
-  lambda = lam[imin];
-  w.assign(n, 0.0);
-  for (int i = n - 1; i >= 0; --i) {  // L^T w = y
-    double v = V[i * n + imin];
-    for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * w[k];
-    w[i] = v / L[i * n + i];
-  }
-}
-
-double quad(const std::vector<double>& M, int n, const std::vector<double>& a,
-            const std::vector<double>& b) {
-  double s = 0.0;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) s += a[i] * M[i * n + j] * b[j];
-  return s;
-}
-
 int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   const trplk_opts& o = c->o;
   const int p = o.p, m = o.m, k = o.k, l = o.l;
@@ -1421,8 +1321,6 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
   double rho = c->rep_h->theta[0], res = c->rep_h->res[0], rho_prev = 0.0;
   bool have_p = false;
   bool done = res <= thr;
-  std::vector<double> Th(static_cast<size_t>(SYEV_MAXB) * SYEV_MAXB), Sh(2 * ORTH_MAXCOL);
-  std::vector<double> Yh(static_cast<size_t>(SYEV_MAXB) * 2), th2(2);
   int cycle = 0;
   skip0 = 1;
   while (!done && cycle < o.max_cycles) {
@@ -1471,8 +1369,9 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
       if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where);
       ++nq;
     }
-    {  // border of S = Q^T B Q: rows of B x_k and B p_{k-1}
+    {
       Status S;
+      // border of S = Q^T B Q: rows of B x_k and B p_{k-1}
       OrthArgs a;
       a.n = n; a.ld = ld; a.ncol_fixed = nq; a.ncol_max = nq; a.Md0 = Ucol(0); a.Md1 = Ucol(0);
       a.vec0 = BUcol(0); a.vec1 = BUcol(nq - 1); a.nvec = 2; a.partial = c->partial;
@@ -1481,82 +1380,20 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
       f.mode = FIN_SUM; f.partial = c->partial; f.nblk = nblk(ORTH_DOT); f.stride = orth_stride();
       f.out = c->pl1_s; f.cnt = ORTH_MAXCOL + nq;
       S.check(fin(f), "fin S border");
-      S.check(hipMemcpyAsync(Th.data(), c->T, sizeof(double) * Th.size(), hipMemcpyDeviceToHost, s), "T d2h");
-      S.check(hipMemcpyAsync(Sh.data(), c->pl1_s, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, s), "S d2h");
-      S.check(hipStreamSynchronize(s), "sync");
-      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where);
-    }
-    // ---- lowest pair of Q^T A Q w = rho Q^T B Q w (steps 5-6) ----
-    bool use_p = have_p;
-    int nqq = nq;
-    std::vector<double> TA, TB, L;
-    auto build = [&](int q) {
-      TA.assign(static_cast<size_t>(q) * q, 0.0);
-      TB.assign(static_cast<size_t>(q) * q, 0.0);
-      for (int i = 0; i < q; ++i)
-        for (int j = 0; j < q; ++j) TA[i * q + j] = 0.5 * (Th[i + j * SYEV_MAXB] + Th[j + i * SYEV_MAXB]);
-      for (int i = 0; i < q; ++i) TB[i * q + i] = 1.0;  // G_k is B-orthonormal
-      for (int j = 0; j < q; ++j) TB[j] = TB[j * q] = Sh[j];
-      if (use_p) {
-        const int e = q - 1;
-        for (int j = 0; j < q; ++j) TB[e * q + j] = TB[j * q + e] = Sh[ORTH_MAXCOL + j];
-        TB[0 * q + e] = TB[e * q + 0] = 0.5 * (Sh[e] + Sh[ORTH_MAXCOL]);
-      }
-    };
-    build(nqq);
-    if (!host_cholesky(TB, nqq, L)) {
-      if (!use_p) return set_err(c, TRPLK_ENOTSPD, "PL+1: projected B not positive definite");
-      use_p = false;  // p_{k-1} numerically inside span{x_k, G_k}
-      --nqq;
-      build(nqq);
-      if (!host_cholesky(TB, nqq, L)) return set_err(c, TRPLK_ENOTSPD, "PL+1: projected B not positive definite");
-    }
-    double lambda;
-    std::vector<double> wv;
-    host_lowest_pair(TA, L, nqq, lambda, wv);
-    if (!std::isfinite(lambda)) return set_err(c, TRPLK_ENUMERIC, "non-finite Ritz value");
-    // g_k coordinates, then the search direction p_k (step 7 or the practical one)
-    std::vector<double> zg(wv), zp;
-    zg[0] = 0.0;
-    if (use_p) zg[nqq - 1] = 0.0;
-    zp = zg;
-    if (use_p) {
-      const int e = nqq - 1;
-      if (conj) {
-        std::vector<double> K(TA);
-        for (size_t i = 0; i < K.size(); ++i) K[i] -= rho_prev * TB[i];
-        std::vector<double> ee(nqq, 0.0);
-        ee[e] = 1.0;
-        const double cc = quad(K, nqq, ee, zg) / quad(K, nqq, ee, ee);
-        zp[e] = -cc;
-      } else {
-        zp[e] = wv[e];
-      }
-    }
-    const double nw = std::sqrt(quad(TB, nqq, wv, wv)), np = std::sqrt(quad(TB, nqq, zp, zp));
-    if (!(np > 0.0) || !(nw > 0.0)) return set_err(c, TRPLK_ENUMERIC, "PL+1: zero direction");
-    std::fill(Yh.begin(), Yh.end(), 0.0);
-    for (int i = 0; i < nqq; ++i) {
-      Yh[i] = wv[i] / nw;
-      Yh[SYEV_MAXB + i] = zp[i] / np;
-    }
-    th2[0] = lambda;
-    th2[1] = 0.0;
-    {
-      Status S;
-      S.check(hipMemcpyAsync(c->Y, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice, s), "Y h2d");
-      S.check(hipMemcpyAsync(c->theta, th2.data(), sizeof(double) * 2, hipMemcpyHostToDevice, s), "theta h2d");
-      S.check(set_state(c->st, SET_NB, 0.0, nqq, s), "nb");
+      // ---- lowest pair of Q^T A Q w = rho Q^T B Q w and the two rotation
+      // columns (steps 5-7), on the device ----
+      S.check(pl1_pencil(c->T, SYEV_MAXB, c->pl1_s, ORTH_MAXCOL, nq, have_p, conj, rho_prev, c->pl1_work,
+                         c->pl1_q, c->Y, SYEV_MAXB, c->theta, c->st, s), "pencil");
       RotArgs ra;
       ra.n = n; ra.kout = 2; ra.state = c->st; ra.Y = c->Y; ra.ldY = SYEV_MAXB; ra.b_max = m;
       ra.U = Ucol(0); ra.AU = AUcol(0); ra.BU = c->hasB ? BUcol(0) : nullptr; ra.ld = ld;
       ra.theta = c->theta; ra.partial = c->partial;
       {
         const int64_t mats = c->hasB ? 3 : 2;
-        ProfScope ps(c, PC_ROT, 8LL * n * (nqq + 2) * mats);
+        ProfScope ps(c, PC_ROT, 8LL * n * (nq + 2) * mats);
         S.check(rotate(ra, c->rot_nblk, s), "rotate");
       }
-      FinishArgs f;
+      f = FinishArgs{};
       f.mode = FIN_RES; f.partial = c->partial; f.nblk = c->rot_nblk; f.stride = 128;
       f.out = c->resout; f.cnt = 1;
       S.check(fin(f), "fin res");
@@ -1571,6 +1408,13 @@ int Solver::run_pl1(const double* x0, int32_t mem, trplk_stats* out) {
       S.check(hipStreamSynchronize(s), "sync");
       if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
     }
+    switch (c->rep_h->pl1_err) {
+      case 0: break;
+      case 1: return set_err(c, TRPLK_ENOTSPD, "PL+1: projected B not positive definite");
+      case 2: return set_err(c, TRPLK_ENUMERIC, "non-finite Ritz value");
+      default: return set_err(c, TRPLK_ENUMERIC, "PL+1: zero direction");
+    }
+    const double lambda = c->rep_h->theta[0];
     if (c->rep_h->bad) return set_err(c, TRPLK_ENOTSPD, "B-norm squared not positive or not finite");
     stt.matvecs += c->rep_h->cnt_append - prev_app;
     prev_app = c->rep_h->cnt_append;
@@ -2245,7 +2089,7 @@ void trplk_destroy(trplk_ctx* c) {
     ws_pieces(c, pcs);
     for (const WsPiece& q : pcs) dfree(*q.ptr);
   }
-  void* ptrs[] = {c->dinv, c->pl1_s, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
+  void* ptrs[] = {c->dinv, c->pl1_s, c->pl1_work, c->pl1_q, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
                   c->partial, c->resout, c->thout, c->st, c->rep_d, c->bpart, c->bh, c->bsmall,
                   c->bshift};
   for (void* p : ptrs) dfree(p);
