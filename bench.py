@@ -78,7 +78,8 @@ def prof_class(name):
         return "orth_upd_dot"
     for key, cls in (("k_upd2", "orth_dc_upd"), ("k_upd<", "orth_upd"),
                      ("k_spmv_dia<8, double", "spmv_f64"), ("k_spmv", "spmv_f32_or_factor"),
-                     ("k_rotate", "rot"), ("k_block_dot", "block_dot"),
+                     ("k_rotate", "rot"), ("k_block_dot_finish", "block_finish"),
+                     ("k_block_dot", "block_dot"), ("k_dot_small", "block_dot_small"),
                      ("k_block_update", "block_update"), ("k_finish", "finish"),
                      ("k_syev", "syev"), ("copyBuffer", "copy")):
         if key in name:

@@ -24,14 +24,19 @@ def T():
     return T
 
 
+@pytest.mark.parametrize("vpad", [3, 4], ids=["V-odd-ld", "V-even-ld"])
 @pytest.mark.parametrize("n,c,r", [(1, 1, 1), (37, 5, 3), (1000, 17, 16), (12345, 64, 4),
-                                   (100_003, 128, 7), (300_001, 40, 1)])
-def test_block_passes_against_numpy(T, n, c, r):
-    print(f"block passes n={n} c={c} r={r}", flush=True)
+                                   (100_003, 128, 7), (300_001, 40, 1), (70_001, 100, 16),
+                                   (50_001, 3, 1), (99_999, 13, 1), (4_097, 16, 1)])
+def test_block_passes_against_numpy(T, n, c, r, vpad):
+    """An odd leading dimension of V takes the scalar-load form of the dot
+    pass, an even one the 16-byte-load form the solver uses; one vector
+    against at most 16 columns takes the row-pair pass."""
+    print(f"block passes n={n} c={c} r={r} ldv=ld+{vpad}", flush=True)
     rng = np.random.default_rng(n + c + r)
     ld = n + (n % 2)
     U = rng.standard_normal((c, ld))
-    V = rng.standard_normal((r, ld + 3))
+    V = rng.standard_normal((r, ld + vpad))
     H0 = rng.standard_normal((r, c + 2))
     Ud, Vd = torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda()
     Hd = torch.full((r, c + 2), float("nan"), dtype=torch.float64, device="cuda")
