@@ -77,6 +77,7 @@ def prof_class(name):
             return "orth_dc_dot" if nvec == "3" else "orth_dot"
         return "orth_upd_dot"
     for key, cls in (("k_upd2", "orth_dc_upd"), ("k_upd<", "orth_upd"),
+                     ("k_spmv_dia_lds", "spmv_staged"),
                      ("k_spmv_dia<8, double", "spmv_f64"), ("k_spmv", "spmv_f32_or_factor"),
                      ("k_rotate", "rot"), ("k_block_dot_finish", "block_finish"),
                      ("k_block_dot", "block_dot"), ("k_dot_small", "block_dot_small"),
@@ -397,8 +398,12 @@ def cpu_oracle(P, X0, cycles_per_step, gpu_cycles, log, n_full=None):
     cores = len(os.sched_getaffinity(0))
     stamps = []
     c0 = time.perf_counter()
-    r = O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=O.jacobi(A), max_cycles=2,
-                trace=lambda c, *a: stamps.append(time.perf_counter()))
+
+    def hook(c, *a):
+        stamps.append(time.perf_counter())
+        log(f"# oracle: cycle {c} at its Rayleigh-Ritz, {stamps[-1] - c0:.1f} s")
+
+    r = O.solve(A, B, P.p, P.m, P.k, P.l, P.tol, X0, apply_M=O.jacobi(A), max_cycles=2, trace=hook)
     c1 = time.perf_counter()
     per_cycle = stamps[1] - stamps[0] if len(stamps) >= 2 else (c1 - c0)
     log(f"# oracle: start + {r.cycles} cycles in {c1 - c0:.1f} s, one cycle {per_cycle:.2f} s")

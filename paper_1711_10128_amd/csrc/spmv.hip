@@ -40,6 +40,7 @@ constexpr int SPMV_THREADS = 256;
 // x staged in LDS for diagonal storage with more than 16 diagonals
 bool g_dia_lds = true;
 constexpr int DIA_CHUNK = 256;   // rows per block iteration of the staged kernel (one per thread)
+constexpr int DIA_LDS_CH = 8;    // diagonal values in flight per thread in the staged kernel
 
 template <typename T>
 __device__ __forceinline__ double to_d(T v) {
@@ -476,6 +477,40 @@ __global__ void k_find_long(int n, const int* rowptr, int* flags, int* maxlen, i
 // skipping the zeros that pad the diagonals; x is read at the clamped
 // column, which only the padding ever needs.  MAXD bounds the unrolled
 // diagonal count (ndiag <= MAXD).
+// Chunks of 256 rows for the diagonal kernels.  XCD: workgroups are
+// dispatched to the eight XCDs in turn (workgroup b on XCD b mod 8), each
+// with its own L2; with a grid that is a multiple of 8 every XCD takes a
+// contiguous eighth of the chunks, its workgroups striding through it
+// together, so the rows a chunk shares with its neighbours stay in one L2.
+// Used with LDS staging (27-point stencils: 3% on the 97^3 FEM pencil
+// together with the non-temporal value loads); the unstaged kernel keeps the
+// plain grid stride (no gain measured on the 7-point operators).
+struct ChunkRange {
+  int first, end, step;
+};
+
+template <bool XCD>
+__device__ __forceinline__ ChunkRange dia_chunks(int nchunk) {
+  if (XCD && (gridDim.x & 7) == 0) {
+    const int per = static_cast<int>(gridDim.x) >> 3;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int cx = (nchunk + 7) / 8;
+    return {xcd * cx + local, min(nchunk, (xcd + 1) * cx), per};
+  }
+  return {static_cast<int>(blockIdx.x), nchunk, static_cast<int>(gridDim.x)};
+}
+
+// NT: non-temporal loads of the diagonal values, which are read once.
+// Measured on MI355X: the staged 27-diagonal product gains 4%, but on the
+// 7-point 256^3 operator the unstaged product's 5% gain came with a 3%
+// slower solve (the kernels around it lost more), so only the staged kernel
+// uses them.
+template <bool NT, typename VT>
+__device__ __forceinline__ VT ld_val(const VT* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 template <int MAXD, typename VT, typename XT, typename AT, typename OT>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, const int* __restrict__ off,
                                                         int ndiag, const VT* __restrict__ dval) {
@@ -492,7 +527,10 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) o[d] = d < ndiag ? off[d] : 0;
   double acc = 0.0;
-  for (int row = blockIdx.x * SPMV_THREADS + threadIdx.x; row < n; row += gridDim.x * SPMV_THREADS) {
+  const ChunkRange cr = dia_chunks<false>((n + SPMV_THREADS - 1) / SPMV_THREADS);
+  for (int ch = cr.first; ch < cr.end; ch += cr.step) {
+    const int row = ch * SPMV_THREADS + threadIdx.x;
+    if (row >= n) continue;
     AT sum = 0;
     if constexpr (MAXD <= 8) {
       VT v[MAXD];
@@ -500,7 +538,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
 #pragma unroll
       for (int d = 0; d < MAXD; ++d) {
         if (d < ndiag) {
-          v[d] = dval[static_cast<int64_t>(d) * n + row];
+          v[d] = ld_val<false>(dval + static_cast<int64_t>(d) * n + row);
           const int64_t c = static_cast<int64_t>(row) + o[d];
           xv[d] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
         }
@@ -521,7 +559,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
         for (int q = 0; q < 8; ++q) {
           const int d = d0 + q;
           if (d < ndiag) {
-            v[q] = dval[static_cast<int64_t>(d) * n + row];
+            v[q] = ld_val<false>(dval + static_cast<int64_t>(d) * n + row);
             const int64_t c = static_cast<int64_t>(row) + o[d];
             xv[q] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
           }
@@ -538,15 +576,17 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
 
 // The same product with x staged in LDS.  A block owns DIA_CHUNK = 256
 // consecutive rows per iteration (one per thread; 1024 rows, four per
-// thread, measured 11% slower); the column offsets fall into a few clusters
-// (a stencil's planes: the 27-point operator has three, each 195 rows wide),
-// and the block loads each cluster's window of x (256 + span entries,
-// coalesced) once, so the ndiag shifted reads of a row come from LDS instead
-// of the cache hierarchy.  Values, the summation order of each row and the
-// epilogue are those of k_spmv_dia, so the products are identical (the
-// fused dot of SPMV_DOT / SPMV_RESID sums the same rows per block).  Used
-// for more than 16 diagonals: with fewer (the FSAI factors' 14) the staging
-// costs more than the reads it saves (measured).
+// thread, measured 11% slower), the chunks taken XCD by XCD; the column
+// offsets fall into a few clusters (a stencil's planes: the 27-point
+// operator has three, each 195 rows wide), and the block loads each
+// cluster's window of x (256 + span entries, coalesced) once, so the ndiag
+// shifted reads of a row come from LDS instead of the cache hierarchy.
+// Values, the summation order of each row and the epilogue are those of
+// k_spmv_dia, so the products are identical (the fused dot of SPMV_DOT /
+// SPMV_RESID groups the rows per block differently).  Used for more than
+// 16 diagonals: with fewer (the FSAI factors' 14) the staging costs more
+// than the reads it saves (measured); 8 values in flight per thread (16:
+// the same, 32: 5% slower).
 struct DiaStage {
   int ncl;
   int lo[8];
@@ -571,7 +611,9 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia_lds(const SpmvArgs a,
   const XT* __restrict__ x = static_cast<const XT*>(a.x);
   const int n = a.n;
   double acc = 0.0;
-  for (int r0 = blockIdx.x * DIA_CHUNK; r0 < n; r0 += gridDim.x * DIA_CHUNK) {
+  const ChunkRange cr = dia_chunks<true>((n + DIA_CHUNK - 1) / DIA_CHUNK);
+  for (int ch = cr.first; ch < cr.end; ch += cr.step) {
+    const int r0 = ch * DIA_CHUNK;
     for (int c = 0; c < ds.ncl; ++c) {
       const int64_t g0 = static_cast<int64_t>(r0) + ds.lo[c];
       for (int t = threadIdx.x; t < ds.len[c]; t += SPMV_THREADS) {
@@ -586,14 +628,14 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia_lds(const SpmvArgs a,
       if (row < n) {
         AT sum = 0;
 #pragma unroll 1
-        for (int d0 = 0; d0 < MAXD; d0 += 8) {
+        for (int d0 = 0; d0 < MAXD; d0 += DIA_LDS_CH) {
           if (d0 >= ndiag) break;
-          VT v[8];
+          VT v[DIA_LDS_CH];
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (d0 + q < ndiag) v[q] = dval[static_cast<int64_t>(d0 + q) * n + row];
+          for (int q = 0; q < DIA_LDS_CH; ++q)
+            if (d0 + q < ndiag) v[q] = ld_val<true>(dval + static_cast<int64_t>(d0 + q) * n + row);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < DIA_LDS_CH; ++q) {
             const int d = d0 + q;
             if (d < ndiag && v[q] != VT(0))
               sum += static_cast<AT>(v[q]) * static_cast<AT>(xs[ds.doff[d] + loc]);
