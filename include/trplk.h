@@ -358,6 +358,17 @@ void trplk_destroy(trplk_ctx* ctx);
 int trplk_spmv(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                const double* x, double* y, int32_t lanes, void* stream);
 
+/* Y(:, j) = A X(:, j) for j < ncols <= 16 (column-major X and Y, leading
+ * dimensions ldx, ldy >= n), float64: the products with A of the columns a
+ * block of block TRPL+K has appended (the block form the paper leaves to
+ * future work, Sec. 5.5).  When A's pattern fits diagonal storage its values
+ * are read once for all columns; each column equals trplk_spmv's product
+ * (lanes = 0) bit for bit.  Other patterns take one CSR product per column.
+ * Device pointers; EINVAL for ncols outside 1..16 or short leading
+ * dimensions. */
+int trplk_spmm(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X,
+               int64_t ldx, int32_t ncols, double* Y, int64_t ldy, void* stream);
+
 /* Same in float32 (values, vector and accumulation): the SpMV of the
  * mixed-precision form. */
 int trplk_spmv_f32(int32_t n, const int32_t* rowptr, const int32_t* col, const float* val,

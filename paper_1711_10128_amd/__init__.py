@@ -91,7 +91,8 @@ EXPORTS = ["trplk_default_opts", "trplk_create", "trplk_workspace_size", "trplk_
            "trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_cgs_update_dot", "trplk_syev",
            "trplk_rotate", "trplk_learned_factor", "trplk_factor_nnz", "trplk_factor_values",
            "trplk_factor_loss_grad", "trplk_train_step", "trplk_get_factor",
-           "trplk_gemv_t_noalloc", "trplk_get_history", "trplk_block_dot", "trplk_block_update"]
+           "trplk_gemv_t_noalloc", "trplk_get_history", "trplk_block_dot", "trplk_block_update",
+           "trplk_spmm"]
 MLP_NPARAM = 1217
 MLP_NF, MLP_NIN, MLP_NH = 8, 17, 64
 
@@ -130,6 +131,7 @@ def lib():
     L.trplk_destroy.restype = None
     L.trplk_spmv.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
     L.trplk_spmv_f32.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp]
+    L.trplk_spmm.argtypes = [i32, vp, vp, vp, vp, i64, i32, vp, i64, vp]
     L.trplk_gemv_t.argtypes = [i32, i32, vp, i64, vp, vp, vp]
     L.trplk_gemv_t_noalloc.argtypes = [i32, i32, vp, i64, vp, vp, vp]
     L.trplk_cgs_update_dot.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp]
@@ -137,7 +139,7 @@ def lib():
     L.trplk_block_dot.argtypes = [i32, i32, vp, i64, vp, i64, i32, vp, i32, vp]
     L.trplk_block_update.argtypes = [i32, i32, vp, i64, vp, i32, i32, ctypes.c_double, vp, i64, vp]
     L.trplk_rotate.argtypes = [i32, i32, i32, vp, i64, vp, i32, vp]
-    for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_gemv_t", "trplk_gemv_t_noalloc",
+    for f in ("trplk_spmv", "trplk_spmv_f32", "trplk_spmm", "trplk_gemv_t", "trplk_gemv_t_noalloc",
               "trplk_cgs_update_dot", "trplk_block_dot", "trplk_block_update",
               "trplk_syev", "trplk_rotate"):
         getattr(L, f).restype = ctypes.c_int
@@ -387,6 +389,15 @@ def spmv(rowptr, col, val, x, y, lanes=0):
     _check(f(int(rowptr.shape[0] - 1), _ptr(rowptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
              lanes, _stream()))
     return y
+
+
+def spmm(rowptr, col, val, X, Y):
+    """Y = A X for X, Y given as (ncols, ld) contiguous float64 tensors
+    (column-major n x ncols blocks, ld >= n); ncols <= 16."""
+    ncols, ldx = X.shape
+    _check(lib().trplk_spmm(int(rowptr.shape[0] - 1), _ptr(rowptr), _ptr(col), _ptr(val), _ptr(X), ldx,
+                            ncols, _ptr(Y), Y.shape[1], _stream()))
+    return Y
 
 
 def gemv_t(U, v, h, n=None):

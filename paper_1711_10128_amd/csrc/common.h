@@ -164,6 +164,12 @@ void spmv_plan_free(SpmvPlan& plan);
 int spmv_partial_blocks(const SpmvPlan& plan);
 hipError_t spmv_f64(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s);
 hipError_t spmv_f32(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s);
+// Y(:, j) = A X(:, j), j < ncols <= 16, for a plan with float64 diagonal
+// storage (spmm_dia_ready): the values are read once for all columns; each
+// column is bitwise the product spmv_f64 forms with SPMV_STORE.
+bool spmm_dia_ready(const SpmvPlan& plan);
+hipError_t spmm_dia(const SpmvPlan& plan, int n, const double* X, int64_t ldx, int ncols, double* Y,
+                    int64_t ldy, hipStream_t s);
 
 // ---------------------------------------------------------- orth passes --
 enum OrthMode : int {

@@ -839,7 +839,8 @@ struct Solver {
   // Gram-Schmidt applied twice with block passes (one read of the basis for
   // every column), then its columns in order against the block's columns
   // already appended (the same, over those few columns), tested for
-  // breakdown (R7), appended with A g, and turned into the next block,
+  // breakdown (R7) and appended; the appended columns are multiplied by A
+  // together (one pass over A's diagonals) and turned into the next block,
   // M (A g - rho_j B g) with the shift of the target the column descends
   // from.  Host decisions per column (O(1) scalars read back); returns the
   // products with A it made.
@@ -884,7 +885,7 @@ struct Solver {
       S.check(hipStreamSynchronize(s), "sync h1");
       if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
       const int nb0 = nbh;
-      std::vector<int> nxt;
+      std::vector<int> nxt, kept;
       for (int j = 0; j < take; ++j) {
         double h1n2 = 0.0;
         for (int i = 0; i < nq; ++i) h1n2 += H1h[i + j * ORTH_MAXCOL] * H1h[i + j * ORTH_MAXCOL];
@@ -925,29 +926,41 @@ struct Solver {
           S.check(scale_copy(n, ib, c->tmpB, BUcol(nbh), s), "append BU");
           ++bprod;
         }
-        SpmvArgs a;
-        a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = Ucol(nbh);
-        a.mode = SPMV_STORE; a.y = AUcol(nbh);
-        S.check(spmv(c->A, a, false, PC_SPMV, 0), "block A g");
+        kept.push_back(j);
         ++*mv;
         ++nbh;
-        if (nbh < room) {
-          // next block column (index = number of columns kept so far; it only
-          // overwrites columns of this block already consumed)
-          const int q = static_cast<int>(nxt.size());
-          double* wq = c->Wblk + static_cast<int64_t>(q) * ld;
-          S.check(restart_residual(n, AUcol(nbh - 1), BUcol(nbh - 1), c->bshift, tgt[j], next, c->dinv,
-                                   wq, fac ? c->vtmp : nullptr, nullptr, s), "block next");
-          if (fac) {
-            S.check(apply_factor(), "block next factor");
-            S.check(copy_cols(n, c->w, ld, wq, ld, 1, s), "block next copy");
+      }
+      const int ra = nbh - nb0;
+      // A g for the appended columns: one pass over A's diagonals for all of
+      // them (SpMM), else one product per column
+      if (ra > 0) {
+        if (spmm_dia_ready(c->A.plan)) {
+          ProfScope ps(c, PC_SPMV, spmv_matrix_bytes(c->A.plan, c->A.nnz, false) + 16LL * n * ra);
+          S.check(spmm_dia(c->A.plan, n, Ucol(nb0), ld, ra, AUcol(nb0), ld, s), "block A G");
+        } else {
+          for (int q = 0; q < ra; ++q) {
+            SpmvArgs a;
+            a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.val = c->A.val; a.x = Ucol(nb0 + q);
+            a.mode = SPMV_STORE; a.y = AUcol(nb0 + q);
+            S.check(spmv(c->A, a, false, PC_SPMV, 0), "block A g");
           }
-          nxt.push_back(tgt[j]);
-          ++*precs;
         }
       }
+      // the next block: column q from the q-th appended column with room
+      // after it (index = number of columns kept so far; it only overwrites
+      // columns of this block already consumed)
+      for (int q = 0; q < ra && nb0 + q + 1 < room; ++q) {
+        double* wq = c->Wblk + static_cast<int64_t>(q) * ld;
+        S.check(restart_residual(n, AUcol(nb0 + q), BUcol(nb0 + q), c->bshift, tgt[kept[q]], next, c->dinv,
+                                 wq, fac ? c->vtmp : nullptr, nullptr, s), "block next");
+        if (fac) {
+          S.check(apply_factor(), "block next factor");
+          S.check(copy_cols(n, c->w, ld, wq, ld, 1, s), "block next copy");
+        }
+        nxt.push_back(tgt[kept[q]]);
+        ++*precs;
+      }
       // T columns of the appended block columns: T(0:nb0+j, nb0+j) = U^T A g_j
-      const int ra = nbh - nb0;
       if (ra > 0) {
         S.check(block_dot(n, nbh, Ucol(0), ld, AUcol(nb0), ld, ra, c->bpart, c->bh, ORTH_MAXCOL, s),
                 "block T");
@@ -2190,6 +2203,33 @@ int trplk_spmv(int32_t n, const int32_t* rowptr, const int32_t* col, const doubl
   SpmvArgs a;
   a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = x; a.y = y; a.mode = SPMV_STORE;
   e = spmv_f64(plan, a, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  spmv_plan_free(plan);
+  return kernel_err(e);
+}
+
+int trplk_spmm(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X,
+               int64_t ldx, int32_t ncols, double* Y, int64_t ldy, void* stream) {
+  if (n < 0 || ncols < 1 || ncols > 16 || (n > 0 && (!rowptr || !col || !val || !X || !Y)) || ldx < n ||
+      ldy < n)
+    return TRPLK_EINVAL;
+  if (n == 0) return TRPLK_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SpmvPlan plan;
+  hipError_t e = spmv_plan(plan, n, rowptr, 0, s);
+  if (e == hipSuccess) e = spmv_plan_dia(plan, n, rowptr, col, val, nullptr, s);
+  if (e == hipSuccess) {
+    if (spmm_dia_ready(plan)) {
+      e = spmm_dia(plan, n, X, ldx, ncols, Y, ldy, s);
+    } else {
+      for (int j = 0; j < ncols && e == hipSuccess; ++j) {
+        SpmvArgs a;
+        a.n = n; a.rowptr = rowptr; a.col = col; a.val = val; a.x = X + static_cast<int64_t>(j) * ldx;
+        a.y = Y + static_cast<int64_t>(j) * ldy; a.mode = SPMV_STORE;
+        e = spmv_f64(plan, a, s);
+      }
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   spmv_plan_free(plan);
   return kernel_err(e);

@@ -1006,6 +1006,60 @@ int spmv_partial_blocks(const SpmvPlan& plan) {
   return plan.kmax ? plan.nblk_short : plan.nblk_short + plan.nlong;
 }
 
+namespace {
+
+// Y(:, j) = A X(:, j) for the s <= S columns a block of block TRPL+K has
+// appended, A in diagonal storage (float64): each diagonal value is read
+// once for all columns.  A row's sum over the diagonals runs in ascending
+// order with the zero entries skipped, as in k_spmv_dia, so every column
+// equals that kernel's product bit for bit.
+template <int S>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmm_dia(int n, int ndiag, const int* __restrict__ off,
+                                                        const double* __restrict__ dval,
+                                                        const double* __restrict__ X, int64_t ldx, int s,
+                                                        double* __restrict__ Y, int64_t ldy) {
+  __shared__ int so[DIA_MAXD];
+  for (int d = threadIdx.x; d < ndiag; d += SPMV_THREADS) so[d] = off[d];
+  __syncthreads();
+  for (int row = blockIdx.x * SPMV_THREADS + threadIdx.x; row < n; row += gridDim.x * SPMV_THREADS) {
+    double acc[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[j] = 0.0;
+    for (int d = 0; d < ndiag; ++d) {
+      const double v = dval[static_cast<int64_t>(d) * n + row];
+      if (v != 0.0) {
+        const int64_t c = static_cast<int64_t>(row) + so[d];   // in range where v != 0
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+          if (j < s) acc[j] += v * X[static_cast<int64_t>(j) * ldx + c];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      if (j < s) Y[static_cast<int64_t>(j) * ldy + row] = acc[j];
+  }
+}
+
+}  // namespace
+
+bool spmm_dia_ready(const SpmvPlan& plan) { return plan.ndiag > 0 && plan.dia_val != nullptr; }
+
+hipError_t spmm_dia(const SpmvPlan& plan, int n, const double* X, int64_t ldx, int ncols, double* Y,
+                    int64_t ldy, hipStream_t s) {
+  if (!spmm_dia_ready(plan) || ncols < 1 || ncols > 16 || n < 1) return hipErrorInvalidValue;
+  const dim3 g(plan.nblk_dia), b(SPMV_THREADS);
+  if (ncols <= 2)
+    hipLaunchKernelGGL(k_spmm_dia<2>, g, b, 0, s, n, plan.ndiag, plan.dia_off, plan.dia_val, X, ldx, ncols, Y, ldy);
+  else if (ncols <= 4)
+    hipLaunchKernelGGL(k_spmm_dia<4>, g, b, 0, s, n, plan.ndiag, plan.dia_off, plan.dia_val, X, ldx, ncols, Y, ldy);
+  else if (ncols <= 8)
+    hipLaunchKernelGGL(k_spmm_dia<8>, g, b, 0, s, n, plan.ndiag, plan.dia_off, plan.dia_val, X, ldx, ncols, Y, ldy);
+  else
+    hipLaunchKernelGGL(k_spmm_dia<16>, g, b, 0, s, n, plan.ndiag, plan.dia_off, plan.dia_val, X, ldx, ncols, Y,
+                       ldy);
+  return hipGetLastError();
+}
+
 hipError_t spmv_f64(const SpmvPlan& plan, const SpmvArgs& a, hipStream_t s) {
   return launch<double, double, double, double>(plan, a, s);
 }

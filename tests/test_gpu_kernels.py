@@ -144,6 +144,32 @@ def test_spmv_diagonal_storage_parity(T, name):
     assert np.all(np.abs(y32.cpu().numpy() - ref32) <= 1e-6 * scale * np.diff(A.rowptr).max())
 
 
+@pytest.mark.parametrize("name,ncols", [("lap3d", 3), ("aniso", 16), ("band27", 5), ("band_gaps", 2),
+                                        ("band_dup", 9), ("diagonal", 1), ("powerlaw_hubs", 4),
+                                        ("fem3d_A", 7)])
+def test_spmm_columns_equal_spmv(T, name, ncols):
+    """Y = A X for the block form's appended columns: with diagonal storage
+    one read of A serves every column, and each column is the single-vector
+    product bit for bit; CSR patterns take one product per column."""
+    A = {**MATS, **BANDS}[name]()
+    print(f"spmm {name} n={A.n} nnz={A.nnz} ncols={ncols}", flush=True)
+    rng = np.random.default_rng(ncols)
+    ld = A.n + 5
+    X = rng.standard_normal((ncols, ld))
+    Y = torch.full((ncols, ld + 2), float("nan"), dtype=torch.float64, device="cuda")
+    rp, cl, vl = _dev(A.rowptr), _dev(A.col), _dev(A.val)
+    T.spmm(rp, cl, vl, _dev(X), Y)
+    got = Y.cpu().numpy()
+    for j in range(ncols):
+        y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        T.spmv(rp, cl, vl, _dev(X[j, :A.n]), y, 0)
+        assert np.array_equal(got[j, :A.n], y.cpu().numpy()), j
+    assert np.all(np.isnan(got[:, A.n:]))            # nothing written past n rows
+    ref = A.to_scipy() @ X[:, :A.n].T
+    bound = 4 * 2.2e-16 * (abs(A.to_scipy()) @ np.abs(X[:, :A.n].T)) * np.diff(A.rowptr).max()
+    assert np.all(np.abs(got[:, :A.n].T - ref) <= bound + 1e-300)
+
+
 @pytest.mark.parametrize("name", ["lap3d", "powerlaw_hubs", "fem3d_A", "aniso"])
 def test_spmv_f32_against_f64(T, name):
     A = MATS[name]()
