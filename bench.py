@@ -77,7 +77,7 @@ def prof_class(name):
             return "orth_dc_dot" if nvec == "3" else "orth_dot"
         return "orth_upd_dot"
     for key, cls in (("k_upd2", "orth_dc_upd"), ("k_upd<", "orth_upd"),
-                     ("k_spmv_dia_lds", "spmv_staged"),
+                     ("k_spmv_dia_lds", "spmv_staged"), ("k_spmm_dia", "spmm"),
                      ("k_spmv_dia<8, double", "spmv_f64"), ("k_spmv", "spmv_f32_or_factor"),
                      ("k_rotate", "rot"), ("k_block_dot_finish", "block_finish"),
                      ("k_block_dot", "block_dot"), ("k_dot_small", "block_dot_small"),
