@@ -39,7 +39,7 @@ namespace {
 constexpr int SPMV_THREADS = 256;
 // x staged in LDS for diagonal storage with more than 16 diagonals
 bool g_dia_lds = true;
-constexpr int DIA_CHUNK = 256;   // rows per block iteration of the staged kernel (one per thread)
+constexpr int DIA_CHUNK = 512;   // rows per block iteration of the staged kernel (two per thread)
 constexpr int DIA_LDS_CH = 8;    // diagonal values in flight per thread in the staged kernel
 
 template <typename T>
@@ -574,19 +574,21 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
   if (a.mode == SPMV_DOT || a.mode == SPMV_RESID) block_partial(acc, a.partial, blockIdx.x);
 }
 
-// The same product with x staged in LDS.  A block owns DIA_CHUNK = 256
-// consecutive rows per iteration (one per thread; 1024 rows, four per
-// thread, measured 11% slower), the chunks taken XCD by XCD; the column
-// offsets fall into a few clusters (a stencil's planes: the 27-point
-// operator has three, each 195 rows wide), and the block loads each
-// cluster's window of x (256 + span entries, coalesced) once, so the ndiag
-// shifted reads of a row come from LDS instead of the cache hierarchy.
-// Values, the summation order of each row and the epilogue are those of
-// k_spmv_dia, so the products are identical (the fused dot of SPMV_DOT /
-// SPMV_RESID groups the rows per block differently).  Used for more than
-// 16 diagonals: with fewer (the FSAI factors' 14) the staging costs more
-// than the reads it saves (measured); 8 values in flight per thread (16:
-// the same, 32: 5% slower).
+// The same product with x staged in LDS.  A block owns DIA_CHUNK = 512
+// consecutive rows per iteration, two adjacent rows per thread (one 16-byte
+// load of each diagonal's pair of values when n is even; 256 rows, one per
+// thread: 1.6% slower; 1024 rows, four per thread 256 apart: 11% slower),
+// the chunks taken XCD by XCD; the column offsets fall into a few clusters
+// (a stencil's planes: the 27-point operator has three, each 195 rows
+// wide), and the block loads each cluster's window of x (512 + span
+// entries, coalesced) once, so the ndiag shifted reads of a row come from
+// LDS instead of the cache hierarchy.  Values, the summation order of each
+// row and the epilogue are those of k_spmv_dia, so the products are
+// identical (the fused dot of SPMV_DOT / SPMV_RESID groups the rows per
+// thread and block differently).  Used for more than 16 diagonals: with
+// fewer (the FSAI factors' 14) the staging costs more than the reads it
+// saves (measured); 8 values in flight per row (16: the same, 32: 5%
+// slower).
 struct DiaStage {
   int ncl;
   int lo[8];
@@ -622,26 +624,42 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia_lds(const SpmvArgs a,
       }
     }
     __syncthreads();
-    for (int rr = 0; rr < DIA_CHUNK; rr += SPMV_THREADS) {
-      const int loc = rr + threadIdx.x;
+    {
+      typedef VT VT2 __attribute__((ext_vector_type(2)));
+      const int loc = 2 * threadIdx.x;
       const int row = r0 + loc;
       if (row < n) {
-        AT sum = 0;
+        const bool two = row + 1 < n;
+        const bool vec = two && (n & 1) == 0;
+        AT s0 = 0, s1 = 0;
 #pragma unroll 1
         for (int d0 = 0; d0 < MAXD; d0 += DIA_LDS_CH) {
           if (d0 >= ndiag) break;
-          VT v[DIA_LDS_CH];
+          VT v0[DIA_LDS_CH], v1[DIA_LDS_CH];
 #pragma unroll
           for (int q = 0; q < DIA_LDS_CH; ++q)
-            if (d0 + q < ndiag) v[q] = ld_val<true>(dval + static_cast<int64_t>(d0 + q) * n + row);
+            if (d0 + q < ndiag) {
+              const VT* p = dval + static_cast<int64_t>(d0 + q) * n + row;
+              if (vec) {
+                const VT2 pr = __builtin_nontemporal_load(reinterpret_cast<const VT2*>(p));
+                v0[q] = pr.x;
+                v1[q] = pr.y;
+              } else {
+                v0[q] = ld_val<true>(p);
+                v1[q] = two ? ld_val<true>(p + 1) : VT(0);
+              }
+            }
 #pragma unroll
           for (int q = 0; q < DIA_LDS_CH; ++q) {
             const int d = d0 + q;
-            if (d < ndiag && v[q] != VT(0))
-              sum += static_cast<AT>(v[q]) * static_cast<AT>(xs[ds.doff[d] + loc]);
+            if (d < ndiag) {
+              if (v0[q] != VT(0)) s0 += static_cast<AT>(v0[q]) * static_cast<AT>(xs[ds.doff[d] + loc]);
+              if (v1[q] != VT(0)) s1 += static_cast<AT>(v1[q]) * static_cast<AT>(xs[ds.doff[d] + loc + 1]);
+            }
           }
         }
-        epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
+        epilogue<OT>(a, e, row, static_cast<double>(s0), acc);
+        if (two) epilogue<OT>(a, e, row + 1, static_cast<double>(s1), acc);
       }
     }
     __syncthreads();
