@@ -374,6 +374,12 @@ hipError_t syev(const double* T, int ldT, int b_fixed, const int* nb_dev, int nb
 // the Ritz value, st->nb = the columns used; failures in st->pl1_err.
 // work: pl1_work_doubles() doubles, qdev: 2 ints (device).
 int64_t pl1_work_doubles();
+// Start block by Cholesky QR (pencil.hip): Rinv = R^-1 for G = R^T R (G
+// k x k, symmetrised; flag = 1 when G is too close to singular), T <- (T +
+// T^T)/2, and the state after k start vectors (nb, product counts).
+hipError_t chol_inv(const double* G, int ldg, int k, double* Rinv, int ldr, int* flag, hipStream_t s);
+hipError_t symmetrise(double* T, int ldT, int k, hipStream_t s);
+hipError_t start_state(DevState* st, int k, bool with_b, hipStream_t s);
 hipError_t pl1_pencil(const double* T, int ldT, const double* S, int sp, int nq, bool use_p, bool conj,
                       double rho_prev, double* work, int* qdev, double* Y, int ldY, double* theta,
                       DevState* st, hipStream_t s);

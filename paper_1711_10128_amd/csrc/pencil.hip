@@ -20,9 +20,10 @@
 // as the two columns of the rotation that forms x_{k+1} and p_k.
 //
 // Three single-workgroup kernels, no host round trip: k_pl1_reduce,
-// k_syev, k_pl1_direction.  Failures are recorded in DevState::pl1_err
-// (1: TB not positive definite, 2: non-finite Ritz value, 3: a zero
-// direction) for the host to read with the step's report.
+// k_syev, k_pl1_direction.  Failures are recorded in DevState::pl1_err (1:
+// TB not positive definite, 2: non-finite Ritz value, 3: a zero direction)
+// for the host to read with the step's report.  The file also holds the
+// small factorisation of the start block's Cholesky QR (k_chol_inv).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -236,6 +237,87 @@ __global__ __launch_bounds__(WAVE) void k_pl1_direction(const double* __restrict
   }
 }
 
+// ---- start block: Cholesky QR ----
+//
+// G = X^T B X of the k start vectors (k <= 64), symmetrised, is factored as
+// R^T R (R upper triangular) and Rinv = R^-1 written for the rotation
+// X <- X Rinv.  flag = 1 when a column keeps less than 1e-5 of its norm
+// once the previous ones are removed (pivot^2 <= 1e-10 of its diagonal
+// entry: the Gram route, applied twice, is accurate for condition numbers
+// well below 1/sqrt(eps), and the caller then orthonormalises column by
+// column instead) or a value is not finite.
+__global__ __launch_bounds__(PT) void k_chol_inv(const double* __restrict__ G, int ldg, int k,
+                                                 double* __restrict__ Rinv, int ldr, int* __restrict__ flag) {
+  __shared__ double sR[PQ * PLD];   // R^T in the lower triangle (row i, column j <= i)
+  __shared__ double sI[PQ * PLD];   // Rinv, column j in row j of sI (transposed)
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int t = threadIdx.x; t < k * k; t += PT) {
+    const int i = t % k, j = t / k;
+    sR[i * PLD + j] = 0.5 * (G[i + static_cast<int64_t>(j) * ldg] + G[j + static_cast<int64_t>(i) * ldg]);
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      const double g = sR[j * PLD + j];
+      double d = g;
+      for (int q = 0; q < j; ++q) d -= sR[j * PLD + q] * sR[j * PLD + q];
+      if (!(d > 1e-10 * g) || !(g < 1.0e300)) bad = 1;
+      sR[j * PLD + j] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double rjj = sR[j * PLD + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += PT) {
+      double v = sR[i * PLD + j];
+      for (int q = 0; q < j; ++q) v -= sR[i * PLD + q] * sR[j * PLD + q];
+      sR[i * PLD + j] = v / rjj;
+    }
+    __syncthreads();
+  }
+  // Rinv column c solves R y = e_c (back substitution, one thread per column)
+  for (int c = threadIdx.x; c < k; c += PT) {
+    for (int i = k - 1; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      if (i <= c) {
+        for (int q = i + 1; q <= c; ++q) v -= sR[q * PLD + i] * sI[c * PLD + q];
+        v /= sR[i * PLD + i];
+      } else {
+        v = 0.0;
+      }
+      sI[c * PLD + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k * k; t += PT) {
+    const int i = t % k, c = t / k;
+    const double v = sI[c * PLD + i];
+    if (!isfinite(v)) bad = 1;
+    Rinv[i + static_cast<int64_t>(c) * ldr] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = bad;
+}
+
+// T(0:k, 0:k) <- (T + T^T) / 2
+__global__ void k_symmetrise(double* T, int ldT, int k) {
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+    const int i = t % k, j = t / k;
+    if (i < j) {
+      const double v = 0.5 * (T[i + static_cast<int64_t>(j) * ldT] + T[j + static_cast<int64_t>(i) * ldT]);
+      T[i + static_cast<int64_t>(j) * ldT] = v;
+      T[j + static_cast<int64_t>(i) * ldT] = v;
+    }
+  }
+}
+
+// the solver state after a start block of k vectors: k columns, k products
+// with A and, with B != I, k with B
+__global__ void k_start_state(DevState* st, int k, int with_b) {
+  st->nb = k;
+  st->cnt_append = k;
+  st->cnt_norm = with_b ? k : 0;
+}
+
 }  // namespace
 
 int64_t pl1_work_doubles() { return 4LL * PQ * PQ + 2 * PQ + PQ * PQ; }
@@ -254,6 +336,22 @@ hipError_t pl1_pencil(const double* T, int ldT, const double* S, int sp, int nq,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pl1_direction, dim3(1), dim3(WAVE), 0, s, work, qdev, theta_c, Yc, PQ, conj ? 1 : 0,
                      rho_prev, Y, ldY, theta, st);
+  return hipGetLastError();
+}
+
+hipError_t chol_inv(const double* G, int ldg, int k, double* Rinv, int ldr, int* flag, hipStream_t s) {
+  if (k < 1 || k > PQ) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(PT), 0, s, G, ldg, k, Rinv, ldr, flag);
+  return hipGetLastError();
+}
+
+hipError_t symmetrise(double* T, int ldT, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetrise, dim3(1), dim3(256), 0, s, T, ldT, k);
+  return hipGetLastError();
+}
+
+hipError_t start_state(DevState* st, int k, bool with_b, hipStream_t s) {
+  hipLaunchKernelGGL(k_start_state, dim3(1), dim3(1), 0, s, st, k, with_b ? 1 : 0);
   return hipGetLastError();
 }
 

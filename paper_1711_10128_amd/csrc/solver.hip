@@ -53,6 +53,11 @@ struct DevCsr {
   SpmvPlan plan;
 };
 
+// start blocks of at least this many vectors are orthonormalised by Cholesky
+// QR on the matrix cores (fewer: column by column)
+constexpr int CHOLQR_MIN_K = 8;
+constexpr int START_BY_COLUMNS = 100;  // start_cholqr: fall back to the column-by-column start
+
 struct Report {
   int nb;
   int bad;
@@ -104,6 +109,7 @@ struct trplk_ctx {
   double* pl1_s = nullptr;   // PL+1: border of Q^T B Q (2 * ORTH_MAXCOL)
   double* pl1_work = nullptr;  // PL+1: the projected pencil's matrices (pl1_work_doubles())
   int* pl1_q = nullptr;        // PL+1: columns of the pencil used, p_{k-1} kept
+  int* cq_flag = nullptr;      // start block by Cholesky QR: 1 = the Gram matrix was too close to singular
   double* T = nullptr;
   double* theta = nullptr;
   double* Y = nullptr;
@@ -411,8 +417,10 @@ int ensure_workspace(trplk_ctx* c) {
     HIPCHK(c, dalloc(c, &c->pl1_work, static_cast<size_t>(pl1_work_doubles())));
     HIPCHK(c, dalloc(c, &c->pl1_q, 2));
   }
-  if (o.block > 1) {
+  if (o.block > 1 || (o.method == TRPLK_METHOD_TRPLK && o.k >= CHOLQR_MIN_K))
     HIPCHK(c, dalloc(c, &c->bpart, static_cast<size_t>(block_partial_doubles())));
+  HIPCHK(c, dalloc(c, &c->cq_flag, 1));
+  if (o.block > 1) {
     HIPCHK(c, dalloc(c, &c->bh, ORTH_MAXCOL * BLOCK_MAX));
     HIPCHK(c, dalloc(c, &c->bsmall, 4 * BLOCK_MAX));
     HIPCHK(c, dalloc(c, &c->bshift, BLOCK_MAX));
@@ -759,15 +767,87 @@ struct Solver {
 
   // Column j of the start block into w: copied from src, or, when src is
   // NULL, drawn on the device from the seeded counter-based stream.
-  int load_w(const double* src, int32_t mem, int j) {
+  int load_w(const double* src, int32_t mem, int j, double* dst = nullptr) {
+    if (!dst) dst = c->w;
     if (!src) {
       hipLaunchKernelGGL(k_start_column, dim3(std::max(1, std::min((n + 255) / 256, 4096))), dim3(256), 0, s, n, c->o.seed,
-                         static_cast<uint64_t>(j) * static_cast<uint64_t>(n), c->w);
+                         static_cast<uint64_t>(j) * static_cast<uint64_t>(n), dst);
       HIPCHK(c, hipGetLastError());
       return TRPLK_OK;
     }
-    HIPCHK(c, hipMemcpyAsync(c->w, src, sizeof(double) * n,
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(double) * n,
                              mem == TRPLK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    return TRPLK_OK;
+  }
+
+  // Start block by Cholesky QR applied twice: the k columns are loaded into
+  // U (and B U formed), G = U^T B U by the block dot passes, U <- U R^-1
+  // (R^T R = G) by the rotation kernel, twice; then A U and T = U^T A U.
+  // The span is the start block's, as with column-by-column Gram-Schmidt,
+  // and the Rayleigh-Ritz that follows depends only on the span.  Returns
+  // START_BY_COLUMNS (state untouched but U) when G is too close to
+  // singular: the caller then orthonormalises column by column.
+  int start_cholqr(const double* x0, int32_t mem) {
+    Status S;
+    const int k = c->o.k;
+    int r;
+    for (int j = 0; j < k; ++j)
+      if ((r = load_w(x0 ? x0 + static_cast<int64_t>(j) * n : nullptr, mem, j, Ucol(j)))) return r;
+    if (c->hasB) {
+      for (int j = 0; j < k; ++j) {
+        SpmvArgs b;
+        b.n = n; b.rowptr = c->B.rowptr; b.col = c->B.col; b.val = c->B.val; b.x = Ucol(j);
+        b.mode = SPMV_STORE; b.y = BUcol(j);
+        S.check(spmv(c->B, b, false, PC_SPMV, 0), "start B x");
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      {
+        ProfScope ps(c, PC_ORTH, 8LL * n * k * ((k + 15) / 16 + 1));
+        for (int q = 0; q < k; q += 16)
+          S.check(block_dot(n, k, Ucol(0), ld, BUcol(q), ld, std::min(16, k - q), c->bpart,
+                            c->Lm + static_cast<int64_t>(q) * SYEV_MAXB, SYEV_MAXB, s), "start gram");
+      }
+      S.check(chol_inv(c->Lm, SYEV_MAXB, k, c->Y, SYEV_MAXB, c->cq_flag, s), "start chol");
+      int flag = 1;
+      // (the report's pinned pl1_err slot as the landing place; the next
+      // report overwrites it)
+      S.check(hipMemcpyAsync(&c->rep_h->pl1_err, c->cq_flag, sizeof(int), hipMemcpyDeviceToHost, s), "flag d2h");
+      S.check(hipStreamSynchronize(s), "sync start");
+      if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+      flag = c->rep_h->pl1_err;
+      if (flag) return START_BY_COLUMNS;
+      RotArgs ra;
+      ra.n = n; ra.kout = k; ra.b_fixed = k; ra.Y = c->Y; ra.ldY = SYEV_MAXB;
+      ra.U = Ucol(0); ra.AU = nullptr; ra.BU = c->hasB ? BUcol(0) : nullptr; ra.ld = ld;
+      {
+        ProfScope ps(c, PC_ROT, 16LL * n * k * (c->hasB ? 2 : 1));
+        S.check(rotate(ra, c->rot_nblk, s), "start rotate");
+      }
+    }
+    // A U (float32 values in the float32 phase, as every other product then)
+    const bool f32 = c->fp32_phase;
+    for (int j = 0; j < k; ++j) {
+      SpmvArgs a;
+      a.n = n; a.rowptr = c->A.rowptr; a.col = c->A.col; a.mode = SPMV_STORE; a.y = AUcol(j);
+      if (f32) {
+        S.check(cast_f32(n, Ucol(j), c->wtmp32, s), "start cast");
+        a.val = c->A.val32; a.x = c->wtmp32; a.out_f64 = true;
+      } else {
+        a.val = c->A.val; a.x = Ucol(j);
+      }
+      S.check(spmv(c->A, a, f32, PC_SPMV, f32 ? 4LL * n : 0), "start A x");
+    }
+    {
+      ProfScope ps(c, PC_ORTH, 8LL * n * k * ((k + 15) / 16 + 1));
+      for (int q = 0; q < k; q += 16)
+        S.check(block_dot(n, k, Ucol(0), ld, AUcol(q), ld, std::min(16, k - q), c->bpart,
+                          c->T + static_cast<int64_t>(q) * SYEV_MAXB, SYEV_MAXB, s), "start T");
+    }
+    S.check(symmetrise(c->T, SYEV_MAXB, k, s), "start T sym");
+    S.check(start_state(c->st, k, c->hasB, s), "start state");
+    if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
+    nbh = k;
     return TRPLK_OK;
   }
 
@@ -1011,11 +1091,19 @@ int Solver::run(const double* x0, int32_t mem, trplk_stats* out) {
   HIPCHK(c, hipEventRecord(c->ev0, s));
   HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
   HIPCHK(c, hipMemsetAsync(c->T, 0, sizeof(double) * SYEV_MAXB * SYEV_MAXB, s));
-  // ---- start block: B-orthonormalise X0 column by column, A X0, T0 ----
+  // ---- start block: B-orthonormalise X0 (Cholesky QR twice, or column by
+  // column), A X0, T0 ----
   nbh = 0;
-  for (int j = 0; j < k; ++j) {
-    if ((r = load_w(x0 ? x0 + static_cast<int64_t>(j) * n : nullptr, mem, j))) return r;
-    if ((r = add_vector(BREAKDOWN_TOL))) return r;
+  r = (k >= CHOLQR_MIN_K && c->bpart) ? start_cholqr(x0, mem) : START_BY_COLUMNS;
+  if (r != TRPLK_OK && r != START_BY_COLUMNS) return r;
+  if (r == START_BY_COLUMNS) {
+    HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), s));
+    HIPCHK(c, hipMemsetAsync(c->T, 0, sizeof(double) * SYEV_MAXB * SYEV_MAXB, s));
+    nbh = 0;
+    for (int j = 0; j < k; ++j) {
+      if ((r = load_w(x0 ? x0 + static_cast<int64_t>(j) * n : nullptr, mem, j))) return r;
+      if ((r = add_vector(BREAKDOWN_TOL))) return r;
+    }
   }
   if ((r = rayleigh_ritz(k, std::min(k, SYEV_MAXB)))) return r;
   if (c->rep_h->nb != k) return set_err(c, TRPLK_EINVAL, "start block is rank deficient");
@@ -2102,7 +2190,7 @@ void trplk_destroy(trplk_ctx* c) {
     ws_pieces(c, pcs);
     for (const WsPiece& q : pcs) dfree(*q.ptr);
   }
-  void* ptrs[] = {c->dinv, c->pl1_s, c->pl1_work, c->pl1_q, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
+  void* ptrs[] = {c->dinv, c->pl1_s, c->pl1_work, c->pl1_q, c->cq_flag, c->T, c->theta, c->Y, c->hbuf, c->cbuf, c->Lm, c->YA,
                   c->partial, c->resout, c->thout, c->st, c->rep_d, c->bpart, c->bh, c->bsmall,
                   c->bshift};
   for (void* p : ptrs) dfree(p);

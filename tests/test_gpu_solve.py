@@ -186,13 +186,39 @@ def test_max_cycles_partial_results(T):
 def test_hard_locking_at_the_column_limit(T):
     """p = m = 64: the locked set plus the basis fill the 128 columns the
     projection passes take; 64 locked pairs and a final 64 x 64
-    Rayleigh-Ritz on them."""
+    Rayleigh-Ritz on them.  The cycle count of this case moves with
+    rounding: the oracle itself needs 110 cycles from X0 and 112 from X0
+    perturbed by 1e-15 relative or from X0 orthonormalised beforehand by
+    Cholesky QR (as the GPU's start does), hence the wider cycle slack;
+    eigenvalues and residuals keep the usual bounds."""
     P = make("lap3d", "small", N=12, vmax=0.05, p=64, m=64, k=24)
     print(f"solve lap3d N=12 p=64 m=64 k=24 n={P.A.n}", flush=True)
     X0 = start_block(P.A.n, P.k, 12)
     ref = _oracle(P, "jacobi", X0)
     st, ev, X, res, conv = _gpu(T, P, "jacobi", X0)
-    _compare(P, st, ev, X, res, conv, ref, cycle_slack=3)
+    _compare(P, st, ev, X, res, conv, ref, cycle_slack=6)
+
+
+@pytest.mark.parametrize("keep", [1e-3, 1e-7])
+def test_start_block_cholesky_qr_and_column_fallback(T, keep):
+    """k = 8 start vectors, the last one keeping only `keep` of its norm
+    outside the span of the others: at 1e-3 the start block is
+    orthonormalised by Cholesky QR twice, at 1e-7 (below the Gram route's
+    1e-5 limit) column by column; both match the oracle, whose start is
+    column-by-column Gram-Schmidt (R2)."""
+    P = make("lap2d", "small", N=30, p=4, m=20, k=8)
+    X0 = start_block(P.A.n, P.k, 5)
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(X0[:, :-1])
+    f = rng.standard_normal(P.A.n)
+    f -= Q @ (Q.T @ f)
+    f -= Q @ (Q.T @ f)
+    X0[:, -1] = X0[:, :-1] @ rng.standard_normal(P.k - 1) + keep * np.linalg.norm(X0[:, 0]) * f / np.linalg.norm(f)
+    print(f"start block keep={keep} n={P.A.n}", flush=True)
+    ref = _oracle(P, "jacobi", X0)
+    st, ev, X, res, conv = _gpu(T, P, "jacobi", X0)
+    assert st["matvecs"] == P.k + (P.m - P.k) * st["cycles"]
+    _compare(P, st, ev, X, res, conv, ref)
 
 
 @pytest.mark.parametrize("s,k,m,prec", [(6, 4, 12, "jacobi"), (9, 3, 16, "none")])
