@@ -30,7 +30,6 @@ template <int NTILE, int KS, bool TWOY>
 __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
   const int b = a.state ? a.state->nb : a.b_fixed;
   const int kk = min(a.kout, b);
-  const int nks = (b + 3) / 4;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   const int li = lane & 15;   // row within the tile / output column of A fragment
@@ -99,25 +98,28 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
     for (int mi = 0; mi < 3; ++mi) {
       double* M = mats[mi];
       if (M == nullptr) continue;
+      // every load unconditional (no branches around them): rows past n and
+      // columns past b read a valid entry of the basis instead, whose
+      // coefficient in Y is zero, so the products are those of the exact
+      // tile; the K steps past b then add exact zeros
+      const double* Mrow = M + (ok ? row : n - 1);
       double bv[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const int kin = 4 * ks + lg;
-        bv[ks] = (ks < nks && ok && kin < b) ? M[kin * ld + row] : 0.0;
+        const int kin = min(4 * ks + lg, b - 1);
+        bv[ks] = Mrow[kin * ld];
       }
       d4 D[NTILE];
 #pragma unroll
       for (int t = 0; t < NTILE; ++t) D[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        if (ks < nks) {
 #pragma unroll
-          for (int t = 0; t < NTILE; ++t)
-            D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                (TWOY && mi == 0) ? Ya[TWOY ? 4 * ks + lg : 0][TWOY ? 16 * t + li : 0]
-                : YLDS ? Ys[4 * ks + lg][16 * t + li] : yf[t][YLDS ? 0 : ks],
-                bv[ks], D[t], 0, 0, 0);
-        }
+        for (int t = 0; t < NTILE; ++t)
+          D[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              (TWOY && mi == 0) ? Ya[TWOY ? 4 * ks + lg : 0][TWOY ? 16 * t + li : 0]
+              : YLDS ? Ys[4 * ks + lg][16 * t + li] : yf[t][YLDS ? 0 : ks],
+              bv[ks], D[t], 0, 0, 0);
       }
       // lane holds X(row = rb*16 + li, col = 16 t + lg + 4 r): the F64 16x16x4
       // result places output row lg + 4 r of the tile in register r
@@ -129,7 +131,8 @@ __global__ __launch_bounds__(RT) void k_rotate(const RotArgs a) {
           if (ok && kc < kk) M[kc * ld + row] = D[t][r];
         }
       }
-      if (resid) {
+      // (rows past n hold products of the stand-in row: kept out of the sums)
+      if (resid && ok) {
         if (mi == 0) {
 #pragma unroll
           for (int t = 0; t < NTILE; ++t) DA[t] = D[t];
