@@ -543,9 +543,11 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
           xv[d] = x[c < 0 ? 0 : (c >= n ? n - 1 : c)];
         }
       }
+      // zero entries (the padding of diagonals that leave the matrix) add
+      // 0 * x[clamped] = 0: no per-lane branch, the same sums
 #pragma unroll
       for (int d = 0; d < MAXD; ++d)
-        if (d < ndiag && v[d] != VT(0)) sum += static_cast<AT>(v[d]) * static_cast<AT>(xv[d]);
+        if (d < ndiag) sum += static_cast<AT>(v[d]) * static_cast<AT>(xv[d]);
     } else {
       // diagonals in chunks of 8, the loads of a chunk in flight together:
       // fewer registers than holding every diagonal's loads keep more
