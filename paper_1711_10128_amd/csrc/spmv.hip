@@ -568,7 +568,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia(const SpmvArgs a, con
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (d0 + q < ndiag && v[q] != VT(0)) sum += static_cast<AT>(v[q]) * static_cast<AT>(xv[q]);
+          if (d0 + q < ndiag) sum += static_cast<AT>(v[q]) * static_cast<AT>(xv[q]);  // zeros add 0
       }
     }
     epilogue<OT>(a, e, row, static_cast<double>(sum), acc);
@@ -655,8 +655,9 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_dia_lds(const SpmvArgs a,
           for (int q = 0; q < DIA_LDS_CH; ++q) {
             const int d = d0 + q;
             if (d < ndiag) {
-              if (v0[q] != VT(0)) s0 += static_cast<AT>(v0[q]) * static_cast<AT>(xs[ds.doff[d] + loc]);
-              if (v1[q] != VT(0)) s1 += static_cast<AT>(v1[q]) * static_cast<AT>(xs[ds.doff[d] + loc + 1]);
+              // zero entries add 0 (the staged x is finite, 0 outside the vector)
+              s0 += static_cast<AT>(v0[q]) * static_cast<AT>(xs[ds.doff[d] + loc]);
+              s1 += static_cast<AT>(v1[q]) * static_cast<AT>(xs[ds.doff[d] + loc + 1]);
             }
           }
         }
@@ -1031,8 +1032,8 @@ namespace {
 // Y(:, j) = A X(:, j) for the s <= S columns a block of block TRPL+K has
 // appended, A in diagonal storage (float64): each diagonal value is read
 // once for all columns.  A row's sum over the diagonals runs in ascending
-// order with the zero entries skipped, as in k_spmv_dia, so every column
-// equals that kernel's product bit for bit.
+// order; zero entries are skipped here and add exact zeros in k_spmv_dia
+// (x finite), so every column equals that kernel's product bit for bit.
 template <int S>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmm_dia(int n, int ndiag, const int* __restrict__ off,
                                                         const double* __restrict__ dval,
