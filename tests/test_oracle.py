@@ -494,3 +494,34 @@ def test_soft_locked_pair_unflagged_when_a_lower_mode_appears():
     assert r.converged.all()
     assert np.all(np.abs(r.theta - ev) <= 1e-12)
     assert (r.cycles, r.matvecs) == (20, 4 + 8 * 20)
+
+
+@pytest.mark.parametrize("gen", ["standard", "generalized"])
+def test_start_depends_only_on_the_span_of_x0(gen):
+    """Reading R2: Alg. 1 starts from a B-orthonormal basis of span(X0)
+    followed by a Rayleigh-Ritz on it, so any such basis gives the same
+    first cycle.  X0 and X0 R (R upper triangular, well conditioned: the
+    Cholesky-QR route the GPU takes for k >= 8 is of this form) give the
+    same Ritz values after one and after three cycles, and the same product
+    counts; a start block with one column replaced does not."""
+    if gen == "standard":
+        P = make("lap2d", "small", N=20, p=4, m=16, k=8)
+        A, B = P.A.to_scipy(), None
+    else:
+        P = make("fem3d", "small", Ne=6, p=4, m=16, k=8)
+        A, B = P.A.to_scipy(), P.B.to_scipy()
+    X0 = start_block(A.shape[0], P.k, 12)
+    rng = np.random.default_rng(7)
+    R = np.triu(rng.uniform(-0.3, 0.3, (P.k, P.k))) + np.eye(P.k) * 2.0
+    Xr = X0 @ R
+    Xo = X0.copy()
+    Xo[:, -1] = rng.uniform(-1.0, 1.0, A.shape[0])
+    M = O.jacobi(A)
+    for cycles in (1, 3):
+        a = O.solve(A, B, P.p, P.m, P.k, P.l, 1e-300, X0, apply_M=M, max_cycles=cycles)
+        b = O.solve(A, B, P.p, P.m, P.k, P.l, 1e-300, Xr, apply_M=M, max_cycles=cycles)
+        c = O.solve(A, B, P.p, P.m, P.k, P.l, 1e-300, Xo, apply_M=M, max_cycles=cycles)
+        scale = np.max(np.abs(a.theta))
+        assert a.matvecs == b.matvecs
+        assert np.max(np.abs(a.theta - b.theta)) <= 1e-12 * scale
+        assert np.max(np.abs(a.theta - c.theta)) > 1e-9 * scale
