@@ -809,14 +809,12 @@ struct Solver {
                             c->Lm + static_cast<int64_t>(q) * SYEV_MAXB, SYEV_MAXB, s), "start gram");
       }
       S.check(chol_inv(c->Lm, SYEV_MAXB, k, c->Y, SYEV_MAXB, c->cq_flag, s), "start chol");
-      int flag = 1;
       // (the report's pinned pl1_err slot as the landing place; the next
       // report overwrites it)
       S.check(hipMemcpyAsync(&c->rep_h->pl1_err, c->cq_flag, sizeof(int), hipMemcpyDeviceToHost, s), "flag d2h");
       S.check(hipStreamSynchronize(s), "sync start");
       if (!S.ok()) return set_err(c, TRPLK_EDEVICE, S.where + ": " + hipGetErrorString(S.err));
-      flag = c->rep_h->pl1_err;
-      if (flag) return START_BY_COLUMNS;
+      if (c->rep_h->pl1_err) return START_BY_COLUMNS;
       RotArgs ra;
       ra.n = n; ra.kout = k; ra.b_fixed = k; ra.Y = c->Y; ra.ldY = SYEV_MAXB;
       ra.U = Ucol(0); ra.AU = nullptr; ra.BU = c->hasB ? BUcol(0) : nullptr; ra.ld = ld;
