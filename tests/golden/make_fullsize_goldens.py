@@ -16,7 +16,10 @@ Cases (name = workload_preconditioner_tol):
   powerlaw_jacobi_1e-08 shifted power-law graph Laplacian, n = 10^6, p20 m48 k24
   fem3d_fsai_1e-08      Q1 FEM pencil on 97^3 elements (B != I), FSAI on A,
                         p16 m48 k24
-Each takes minutes (seconds per cycle on a few host cores).
+  aniso3d96_jacobi_1e-08  the anisotropic generator of the largest workload
+                        at 96^3 (n = 884,736) with its solver shape, p50 m64
+                        k32, hard locking (the 256^3 instance takes days)
+Each takes minutes to hours (seconds per cycle on a few host cores).
 """
 from __future__ import annotations
 
@@ -40,7 +43,13 @@ CASES = {
     "lap3d_jacobi_1e-11": ("lap3d", "jacobi", 1e-11),
     "powerlaw_jacobi_1e-08": ("powerlaw", "jacobi", 1e-8),
     "fem3d_fsai_1e-08": ("fem3d", "fsai", 1e-8),
+    "aniso3d96_jacobi_1e-08": ("aniso3d", "jacobi", 1e-8, {"N": 96}),
 }
+
+
+def case_kwargs(case: str) -> dict:
+    """Generator overrides of a case (the size of a reduced instance)."""
+    return dict(CASES[case][3]) if len(CASES[case]) > 3 else {}
 
 
 def path(case: str) -> str:
@@ -48,8 +57,8 @@ def path(case: str) -> str:
 
 
 def run(case: str) -> str:
-    name, prec, tol = CASES[case]
-    P = make(name, "full")
+    name, prec, tol = CASES[case][:3]
+    P = make(name, "full", **case_kwargs(case))
     A = P.A.to_scipy()
     B = P.B.to_scipy() if P.B is not None else None
     X0 = start_block(P.A.n, P.k, P.seed)
@@ -59,7 +68,11 @@ def run(case: str) -> str:
     else:
         M = O.factorized(OP.fsai(A))
     t1 = time.perf_counter()
-    r = O.solve(A, B, P.p, P.m, P.k, P.l, tol, X0, apply_M=M)
+    def progress(cycle, *args):
+        if cycle % 100 == 0:
+            print(f"  {case}: cycle {cycle}, {time.perf_counter() - t1:.0f} s", flush=True)
+
+    r = O.solve(A, B, P.p, P.m, P.k, P.l, tol, X0, apply_M=M, trace=progress)
     t2 = time.perf_counter()
     lines = [
         f"# full-size oracle reference: {case}",

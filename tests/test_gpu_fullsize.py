@@ -156,6 +156,11 @@ FULL_PARITY = [
     ("powerlaw_jacobi_1e-08", "powerlaw", "jacobi", "fp64", True),
     ("fem3d_fsai_1e-08", "fem3d", "fsai", "fp64", True),
     ("fem3d_fsai_1e-08", "fem3d", "fsai", "mixed", False),
+    # the largest workload's generator and solver shape at 96^3, hard locking:
+    # the float64 form follows the oracle's iteration, but with 50 clustered
+    # pairs locked one by one the cycle count drifts with rounding, so it is
+    # held to the certified bound and to 5% of the oracle's cycles
+    ("aniso3d96_jacobi_1e-08", "aniso3d", "jacobi", "fp64", False),
 ]
 
 
@@ -168,12 +173,14 @@ def test_full_size_eigenvalues_match_oracle(T, case, name, prec, precision, same
     bound directly; the mixed form takes other Krylov directions and stops
     at another cycle, so it is held to the bound or, where larger, to the
     sum of both sides' certified errors ||r||^2 / gap (gap from the
-    oracle's own eigenvalues)."""
+    oracle's own eigenvalues).  A float64 case whose locking order can
+    drift with rounding is held to the second bound and to its cycle count
+    within 5% of the oracle's."""
     if not os.path.exists(G.path(case)):
         pytest.skip(f"no reference run {case}")
     g = G.load(case)
     tol = float(case.rsplit("_", 1)[1])
-    P = make(name, "full", tol=tol)
+    P = make(name, "full", tol=tol, **G.case_kwargs(case))
     print(f"full {case} on the GPU: {prec} {precision} n={P.A.n}", flush=True)
     st, ev, X, res, conv = _solve(T, P, prec, precision)
     rel = np.abs(ev - g["theta"]) / np.abs(g["theta"])
@@ -197,6 +204,8 @@ def test_full_size_eigenvalues_match_oracle(T, case, name, prec, precision, same
             cert = np.full_like(th, np.inf)
         allow = np.maximum(floor, np.minimum(cert, 1e-8 * np.abs(th)))
         assert np.all(np.abs(ev - th) <= allow)
+        if precision == "fp64":
+            assert abs(st["cycles"] - g["cycles"]) <= 0.05 * g["cycles"]
 
 
 def test_anisotropic_constant_field_closed_form(T):
