@@ -432,6 +432,7 @@ template <bool NT, bool GEN>
 __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
   if (a.state->skip) return;
   constexpr int RPU = GEN ? 2 : UPD_RP;  // row pairs per lane (two matrices: fewer)
+  constexpr int CB = 4;                  // columns per batch of loads
   const double ig = a.state->inv_gamma;
   const bool corr = ig != 0.0;
   const int j = a.ncol_fixed + a.state->nb - (corr ? 1 : 0);
@@ -467,17 +468,17 @@ __global__ __launch_bounds__(UPD_THREADS) void k_upd2(const OrthArgs a) {
       pb[r] = d2{0.0, 0.0};
     }
     int c = 0;
-    for (; c + 4 <= j; c += 4) {
-      d2 u[4][RPU], bq[GEN ? 4 : 1][RPU];
+    for (; c + CB <= j; c += CB) {
+      d2 u[CB][RPU], bq[GEN ? CB : 1][RPU];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < CB; ++q)
 #pragma unroll
         for (int r = 0; r < RPU; ++r) {
           u[q][r] = ld_pair<F, NT>(a.Mu + (c + q) * ld, base + WAVE * r, n);
           if constexpr (GEN) bq[q][r] = ld_pair<F, NT>(a.Md1 + (c + q) * ld, base + WAVE * r, n);
         }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < CB; ++q)
 #pragma unroll
         for (int r = 0; r < RPU; ++r) {
           pu[r].x += u[q][r].x * cs[c + q];
