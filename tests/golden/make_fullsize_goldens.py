@@ -16,8 +16,8 @@ Cases (name = workload_preconditioner_tol):
   powerlaw_jacobi_1e-08 shifted power-law graph Laplacian, n = 10^6, p20 m48 k24
   fem3d_fsai_1e-08      Q1 FEM pencil on 97^3 elements (B != I), FSAI on A,
                         p16 m48 k24
-  aniso3d96_jacobi_1e-08  the anisotropic generator of the largest workload
-                        at 96^3 (n = 884,736) with its solver shape, p50 m64
+  aniso3d64_jacobi_1e-08  the anisotropic generator of the largest workload
+                        at 64^3 (n = 262,144) with its solver shape, p50 m64
                         k32, hard locking (the 256^3 instance takes days)
 Each takes minutes to hours (seconds per cycle on a few host cores).
 """
@@ -43,7 +43,7 @@ CASES = {
     "lap3d_jacobi_1e-11": ("lap3d", "jacobi", 1e-11),
     "powerlaw_jacobi_1e-08": ("powerlaw", "jacobi", 1e-8),
     "fem3d_fsai_1e-08": ("fem3d", "fsai", 1e-8),
-    "aniso3d96_jacobi_1e-08": ("aniso3d", "jacobi", 1e-8, {"N": 96}),
+    "aniso3d64_jacobi_1e-08": ("aniso3d", "jacobi", 1e-8, {"N": 64}),
 }
 
 

@@ -156,11 +156,11 @@ FULL_PARITY = [
     ("powerlaw_jacobi_1e-08", "powerlaw", "jacobi", "fp64", True),
     ("fem3d_fsai_1e-08", "fem3d", "fsai", "fp64", True),
     ("fem3d_fsai_1e-08", "fem3d", "fsai", "mixed", False),
-    # the largest workload's generator and solver shape at 96^3, hard locking:
+    # the largest workload's generator and solver shape at 64^3, hard locking:
     # the float64 form follows the oracle's iteration, but with 50 clustered
     # pairs locked one by one the cycle count drifts with rounding, so it is
     # held to the certified bound and to 5% of the oracle's cycles
-    ("aniso3d96_jacobi_1e-08", "aniso3d", "jacobi", "fp64", False),
+    ("aniso3d64_jacobi_1e-08", "aniso3d", "jacobi", "fp64", False),
 ]
 
 
