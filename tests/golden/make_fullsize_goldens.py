@@ -1,10 +1,11 @@
 """Write the full-size reference eigenvalues the GPU tests compare against.
 
-Runs the FP64 CPU oracle (oracle/trplk.py, Alg. 1) on the full-size
-workloads that bench.py and tests/test_gpu_fullsize.py run, from the same
-seeded start block, and stores per case the Ritz values, the residual norms
-(stored and recomputed), the cycle and product counts and the norm used in
-the stopping test of eq. (5.1).  Only oracle/ and the seeded input
+Runs the FP64 CPU oracle (oracle/trplk.py, Alg. 1; oracle/block.py for a
+block case) on the full-size workloads that bench.py and
+tests/test_gpu_fullsize.py run, from the same seeded start block, and
+stores per case the Ritz values, the residual norms (stored and
+recomputed), the cycle and product counts and the norm used in the stopping
+test of eq. (5.1).  Only oracle/ and the seeded input
 generators are called: no value here comes from the GPU path.
 
     python tests/golden/make_fullsize_goldens.py [case ...]
@@ -19,6 +20,9 @@ Cases (name = workload_preconditioner_tol):
   aniso3d64_jacobi_1e-08  the anisotropic generator of the largest workload
                         at 64^3 (n = 262,144) with its solver shape, p50 m64
                         k32, hard locking (the 256^3 instance takes days)
+  lap3d47_jacobi_s4_1e-08  block TRPL+K (oracle/block.py, block size 4) on the
+                        Laplacian's generator at 47^3 (n = 103,823: not a
+                        multiple of any tile), p10 m40 k20
 Each takes minutes to hours (seconds per cycle on a few host cores).
 """
 from __future__ import annotations
@@ -34,6 +38,7 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
+from oracle import block as OB  # noqa: E402
 from oracle import precond as OP  # noqa: E402
 from oracle import trplk as O  # noqa: E402
 from workloads import make, start_block  # noqa: E402
@@ -44,12 +49,18 @@ CASES = {
     "powerlaw_jacobi_1e-08": ("powerlaw", "jacobi", 1e-8),
     "fem3d_fsai_1e-08": ("fem3d", "fsai", 1e-8),
     "aniso3d64_jacobi_1e-08": ("aniso3d", "jacobi", 1e-8, {"N": 64}),
+    "lap3d47_jacobi_s4_1e-08": ("lap3d", "jacobi", 1e-8, {"N": 47}, 4),
 }
 
 
 def case_kwargs(case: str) -> dict:
     """Generator overrides of a case (the size of a reduced instance)."""
     return dict(CASES[case][3]) if len(CASES[case]) > 3 else {}
+
+
+def case_block(case: str) -> int:
+    """Block size of a case (1: TRPL+K itself, else the block form)."""
+    return CASES[case][4] if len(CASES[case]) > 4 else 1
 
 
 def path(case: str) -> str:
@@ -72,12 +83,16 @@ def run(case: str) -> str:
         if cycle % 100 == 0:
             print(f"  {case}: cycle {cycle}, {time.perf_counter() - t1:.0f} s", flush=True)
 
-    r = O.solve(A, B, P.p, P.m, P.k, P.l, tol, X0, apply_M=M, trace=progress)
+    s = case_block(case)
+    if s == 1:
+        r = O.solve(A, B, P.p, P.m, P.k, P.l, tol, X0, apply_M=M, trace=progress)
+    else:
+        r = OB.solve(A, B, P.p, P.m, P.k, P.l, s, tol, X0, apply_M=M, trace=progress)
     t2 = time.perf_counter()
     lines = [
         f"# full-size oracle reference: {case}",
         f"# workload {name} n={P.A.n} nnz={P.A.nnz} p={P.p} m={P.m} k={P.k} l={P.l} "
-        f"seed={P.seed} precond={prec} tol={tol:g} norm=inf",
+        f"seed={P.seed} precond={prec} tol={tol:g} norm=inf block={s}",
         "# written by tests/golden/make_fullsize_goldens.py (FP64 CPU oracle only)",
         f"# oracle setup {t1 - t0:.1f} s, solve {t2 - t1:.1f} s",
         f"cycles {r.cycles}",

@@ -23,13 +23,14 @@ def T():
     return T
 
 
-def _solve(T, P, prec, precision):
+def _solve(T, P, prec, precision, block=1):
     """The solve as bench.py runs it: device-resident CSR and start block."""
     Ad = T.DeviceCSR(P.A)
     Bd = T.DeviceCSR(P.B) if P.B is not None else None
     X0 = start_block(P.A.n, P.k, P.seed)
     Xd = torch.from_numpy(np.ascontiguousarray(X0.T)).cuda()
-    s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=prec, precision=precision)
+    s = T.Solver(Ad, Bd, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond=prec, precision=precision,
+                 block=block)
     st = s.solve(Xd)
     ev, X, res, conv = s.eigpairs()
     s.close()
@@ -160,6 +161,8 @@ FULL_PARITY = [
     # pairs hard-locked over ~1,200 cycles
     ("aniso3d64_jacobi_1e-08", "aniso3d", "jacobi", "fp64", True),
     ("aniso3d64_jacobi_1e-08", "aniso3d", "jacobi", "mixed", False),
+    # block TRPL+K (block size 4) against the block oracle at n = 103,823
+    ("lap3d47_jacobi_s4_1e-08", "lap3d", "jacobi", "fp64", True),
 ]
 
 
@@ -179,7 +182,7 @@ def test_full_size_eigenvalues_match_oracle(T, case, name, prec, precision, same
     tol = float(case.rsplit("_", 1)[1])
     P = make(name, "full", tol=tol, **G.case_kwargs(case))
     print(f"full {case} on the GPU: {prec} {precision} n={P.A.n}", flush=True)
-    st, ev, X, res, conv = _solve(T, P, prec, precision)
+    st, ev, X, res, conv = _solve(T, P, prec, precision, block=G.case_block(case))
     rel = np.abs(ev - g["theta"]) / np.abs(g["theta"])
     print(f"  gpu cycles={st['cycles']} mv={st['matvecs']}  oracle cycles={g['cycles']} "
           f"mv={g['matvecs']}  max rel eig err={rel.max():.2e}", flush=True)
