@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import pl1 as PL  # noqa: E402
 from oracle import trplk as O  # noqa: E402
-from workloads import fem3d, lap2d, powerlaw  # noqa: E402
+from workloads import fem3d, lap2d, lap3d, powerlaw  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -33,6 +33,11 @@ CASES = {
     "fem_generalized_conj": (lambda: tuple(M.to_scipy() for M in fem3d(7, 0.5, 12)), 5, "pl1"),
     "fem_generalized_practical": (lambda: tuple(M.to_scipy() for M in fem3d(7, 0.5, 12)), 5,
                                   "pl1_practical"),
+    # n = 103,823 (47^3 nodes): the grid and pencil kernels at many tiles and a
+    # ragged tail, the oracle still seconds per solve
+    "lap3d47_conj": (lambda: (lap3d(47, 0.05, 12).to_scipy(), None), 6, "pl1"),
+    "lap3d47_practical": (lambda: (lap3d(47, 0.05, 12).to_scipy(), None), 6, "pl1_practical"),
+    "fem48_generalized_conj": (lambda: tuple(M.to_scipy() for M in fem3d(48, 0.5, 12)), 5, "pl1"),
 }
 
 
