@@ -30,7 +30,9 @@ def _params(T, seed, scale_w2=0.3):
 
 
 @pytest.mark.parametrize("name,kw", [("powerlaw", dict(n=2000)), ("lap3d", dict(N=10)),
-                                     ("fem3d", dict(Ne=7))])
+                                     ("fem3d", dict(Ne=7)),
+                                     # the feature reductions over many workgroups
+                                     ("aniso3d", dict(N=64)), ("powerlaw", dict(n=200_000))])
 def test_forward_matches_oracle(T, name, kw):
     P = make(name, "small", **kw)
     A = P.A.to_scipy()
