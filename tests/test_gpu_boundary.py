@@ -237,6 +237,24 @@ def test_fsai_capped_factor_entry_by_entry(T, cap):
     assert _eig_ok(ev, ref.theta, ref.normA)
 
 
+def test_fsai_factor_entry_by_entry_on_the_fem_pencil(T):
+    """FSAI of the 27-point FEM stiffness matrix (14 lower entries per
+    interior row, one dense local solve each; n = 24,389 rows over many
+    workgroups) against the oracle's fsai(A), entry by entry (M = G^T G of
+    Sec. 2.2 with the FSAI pattern reading R19)."""
+    P = make("fem3d", "small", Ne=30, sigma=0.5, p=4, m=16, k=8)
+    A = P.A.to_scipy()
+    print(f"fsai fem3d n={P.A.n}", flush=True)
+    s = T.Solver(P.A, P.B, p=P.p, m=P.m, k=P.k, l=P.l, tol=P.tol, precond="fsai")
+    rp, cl, vl = s.factor()
+    s.close()
+    G = PC.fsai(A)
+    assert np.array_equal(rp, G.indptr) and np.array_equal(cl, G.indices)
+    assert np.diff(rp).max() == 14
+    scale = np.repeat(np.maximum.reduceat(np.abs(G.data), G.indptr[:-1]), np.diff(G.indptr))
+    assert np.max(np.abs(vl - G.data) / scale) < 1e-10
+
+
 def test_fsai_without_cap_rejects_hub_rows(T):
     P, _ = _hubs_last()
     with pytest.raises(T.TrplkError) as e:
