@@ -228,3 +228,56 @@ def test_anisotropic_constant_field_closed_form(T):
     assert conv.all() and np.all(res <= 1e-8 * st["normA"] * 1.001)
     assert abs(st["normA"] - 4 * (1 + 1e-2 + 1e-4)) < 1e-12
     assert np.all(np.abs(ev - lam) <= 1e-10 * lam)
+
+
+def test_headline_shape_kernels_on_sampled_outputs(T):
+    """The 256^3 step's basis shapes at its n = 16,777,216 (a basis far above
+    128 MiB: the non-temporal load paths): h = U^T v over 96 columns, the
+    projection w -= U h with h2 = U^T w, and the restart rotation b = 64 ->
+    k = 32 (Alg. 1), each checked on sampled outputs that NumPy computes one
+    by one from the same rows and columns."""
+    n, c = 256 ** 3, 96
+    eps = 2.2e-16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    U = torch.randn((c, n), dtype=torch.float64, device="cuda", generator=g)
+    v = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.r_[rng.choice(n, 4096, replace=False), np.arange(n - 64, n)])
+    ridx = torch.from_numpy(rows).cuda()
+    cols = [0, 1, 47, 95]
+    print(f"full-size passes n={n} c={c}", flush=True)
+
+    h = torch.zeros(c, dtype=torch.float64, device="cuda")
+    T.gemv_t(U, v, h)
+    vh = v.cpu().numpy()
+    for i in cols:
+        ui = U[i].cpu().numpy()
+        tol = 8 * eps * (np.abs(ui) @ np.abs(vh)) * np.log2(n + 2)
+        assert abs(h[i].item() - ui @ vh) <= tol
+
+    hh = rng.standard_normal(c)
+    w = v.clone()
+    h2 = torch.zeros(c, dtype=torch.float64, device="cuda")
+    T.cgs_update_dot(U, torch.from_numpy(hh).cuda(), w, h2)
+    Ur = U.index_select(1, ridx).cpu().numpy()             # (c, rows)
+    wref = vh[rows] - Ur.T @ hh
+    got = w.index_select(0, ridx).cpu().numpy()
+    assert np.allclose(got, wref, rtol=1e-13, atol=1e-13 * np.abs(vh).max() * c)
+    wh = w.cpu().numpy()
+    for i in cols:
+        # the pass sums h2 from the very values of w it stores: a dot's rounding
+        ui = U[i].cpu().numpy()
+        tol = 16 * eps * (np.abs(ui) @ np.abs(wh)) * np.log2(n + 2)
+        assert abs(h2[i].item() - ui @ wh) <= tol
+
+    b, k = 64, 32
+    Y = rng.standard_normal((b, b))
+    Ub = U[:b]
+    Ur = Ub.index_select(1, ridx).cpu().numpy()
+    T.rotate(Ub, torch.from_numpy(Y.T.copy()).cuda(), k)
+    got = Ub.index_select(1, ridx).cpu().numpy()
+    ref = (Ur.T @ Y[:, :k]).T
+    tol = 4 * b * eps * (np.abs(Ur.T) @ np.abs(Y[:, :k])).T
+    assert np.all(np.abs(got[:k] - ref) <= tol)
+    assert np.array_equal(got[k:], Ur[k:])
